@@ -1,0 +1,188 @@
+/*
+ * dmimo.h - C ABI of the MI355X (gfx950) distributed-MIMO channel,
+ * beamforming and power-map library (libdmimo.so).
+ *
+ * Notation follows the paper (Sec. II-A): M transmit antennas, K
+ * single-antenna users, precoder W in C^{K x M}.  The transmitted vector is
+ * x = W^T s and the channel is H in C^{K x M}, so user k receives
+ * r_k = sum_m h_km x_m + noise.  Coherent sums multiply h by w with no
+ * conjugate, and maximum-ratio precoding is W = H^*.
+ *
+ * Conventions shared by every call:
+ *  - Array arguments are DEVICE pointers owned by the caller, unless the
+ *    comment says "host".  The library never frees or keeps them.
+ *  - Complex arrays are interleaved (re, im).  They are complex128 (two
+ *    doubles) when the call's precision is DMIMO_F64, and complex64 (two
+ *    floats) otherwise.  Multi-dimensional arrays are dense and row-major in
+ *    the order written, e.g. H[b][k][m].
+ *  - Every call is asynchronous and ordered on `stream` (a hipStream_t;
+ *    NULL = the legacy default stream).  Nothing synchronises the host.
+ *  - The return value reports only what the host can check before launching:
+ *    arguments, shapes, precision and workspace size, plus HIP launch errors
+ *    (DMIMO_E_HIP, detail in dmimo_last_error()).  Argument errors are
+ *    detected before any HIP runtime call is made.
+ *  - Numeric failures found on the device go to a per-deployment `info[b]`
+ *    (0 = ok, j > 0 = Cholesky pivot j not positive).  A failed deployment
+ *    does not affect the others.
+ *  - B = 0 or N = 0 (an empty batch) is valid and launches nothing.
+ *  - K and M must be >= 1.  K is at most DMIMO_K_MAX.
+ *  - The calls are thread-safe on distinct streams.  No C++ exception
+ *    crosses the ABI.
+ */
+#ifndef DMIMO_H
+#define DMIMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMIMO_K_MAX 32
+
+typedef enum {
+    DMIMO_OK = 0,
+    DMIMO_E_ARG = 1,          /* NULL required pointer, bad scalar (freq <= 0, sigma2 < 0, ...) */
+    DMIMO_E_SHAPE = 2,        /* K < 1, M < 1, K > M for ZF, K > DMIMO_K_MAX, negative B/N, ... */
+    DMIMO_E_DTYPE = 3,        /* unknown precision / channel model / precoder / point kind       */
+    DMIMO_E_WORKSPACE = 4,    /* workspace smaller than dmimo_workspace_size()                   */
+    DMIMO_E_HIP = 5,          /* a HIP runtime call or kernel launch failed                      */
+    DMIMO_E_UNSUPPORTED = 6,  /* valid but not provided (e.g. Rician power maps)                 */
+    DMIMO_E_BUSY = 7,         /* server: no free slot now                                        */
+    DMIMO_E_NOMEM = 8,        /* server: query can never fit the HBM budget                      */
+    DMIMO_E_NOTFOUND = 9      /* server: unknown ticket or deployment                            */
+} dmimo_status;
+
+/* Arithmetic of a call.  Distances and phases are computed in FP64 in every mode. */
+typedef enum {
+    DMIMO_F64 = 0,        /* FP64 end to end; complex arrays are complex128           */
+    DMIMO_F32 = 1,        /* FP32 amplitude / sin / cos and FP32 contractions          */
+    DMIMO_MIX_F16X3 = 2,  /* contractions on FP16 MFMA, hi/lo split x3, FP32 accumulate */
+    DMIMO_MIX_BF16X3 = 3  /* contractions on BF16 MFMA, hi/lo split x3, FP32 accumulate */
+} dmimo_precision;
+
+typedef enum { DMIMO_CH_LOS = 0, DMIMO_CH_RICIAN = 1 } dmimo_chmodel;
+
+typedef enum {
+    DMIMO_MR = 0,        /* W = c H^*                                  */
+    DMIMO_ZF = 1,        /* W = scale * conj(G^-1 H), G = H H^H        */
+    DMIMO_MR_PHASE = 2   /* equal-gain MR, w_km = a exp(-j angle h_km) */
+} dmimo_precoder;
+
+typedef enum { DMIMO_PTS_GRID = 0, DMIMO_PTS_LIST = 1 } dmimo_points_kind;
+
+/* Channel model.  The paper is silent on geometry; the line-of-sight term is
+ * the free-space spherical wave h = lambda/(4 pi max(d, d_min)) exp(-j 2 pi d/lambda),
+ * with lambda = 299792458 / freq_hz.  Rician:
+ * h = lambda/(4 pi max(d,d_min)) [sqrt(k/(1+k)) exp(-j 2 pi d/lambda) + sqrt(1/(1+k)) g],
+ * with g ~ CN(0,1) supplied by the caller. */
+typedef struct {
+    double freq_hz;      /* carrier frequency (> 0)                              */
+    int32_t model;       /* dmimo_chmodel                                        */
+    double kappa_lin;    /* Rician K-factor, linear (>= 0); ignored for LoS      */
+    double d_min_m;      /* near-field clamp; <= 0 selects lambda / (4 pi)       */
+} dmimo_channel_params;
+
+/* Evaluation or user points.
+ * GRID: cell centres p(i,j) = (x0 + (i+1/2) dx, y0 + (j+1/2) dy, z), flat index
+ *       n = j * nx + i, N = nx * ny.  Shared by every deployment of a call.
+ * LIST: `xyz` is a device FP64 array of n points [n][3] per deployment
+ *       (dmimo_channel: [B][n][3]; dmimo_powermap: [n][3]). */
+typedef struct {
+    int32_t kind;            /* dmimo_points_kind              */
+    int32_t nx, ny;          /* GRID                           */
+    double x0, y0, dx, dy, z;/* GRID                           */
+    const double* xyz;       /* LIST, device                   */
+    int32_t n;               /* LIST: points per deployment    */
+} dmimo_points;
+
+/* Channel synthesis.  H[b][n][m] = h(point n of deployment b, antenna m of
+ * deployment b).
+ *   params  host; model LoS or Rician.
+ *   B, M    deployments and antennas per deployment (B >= 0, M >= 1).
+ *   ap_xyz  device FP64 [B][M][3] antenna positions (metres).
+ *   pts     host descriptor; N points per deployment.
+ *   nlos    Rician only: device complex64 [B][N][M] CN(0,1) draws; NULL for LoS.
+ *   out     DMIMO_F64 -> H is complex128, DMIMO_F32 -> complex64 (MIX modes
+ *           are not defined for a materialised channel: DMIMO_E_UNSUPPORTED).
+ *   H       device [B][N][M] output. */
+dmimo_status dmimo_channel(const dmimo_channel_params* params, int32_t B, int32_t M,
+                           const double* ap_xyz, const dmimo_points* pts,
+                           const void* nlos, int32_t out, void* H, void* stream);
+
+/* K x K Gram G[b] = H[b] H[b]^H (the K x K form of the paper's H^T H^*,
+ * Sec. IV).
+ *   H    device [B][K][M], complex128 for DMIMO_F64, else complex64.
+ *   prec DMIMO_F64: FP64 FMA.  DMIMO_F32: FP32 FMA.  MIX modes: hi/lo split
+ *        FP16 or BF16 MFMA products with FP32 accumulation.
+ *   G    device [B][K][K], complex128 for DMIMO_F64, else complex64; full
+ *        Hermitian matrix written. */
+dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t prec,
+                        void* G, void* stream);
+
+/* Precoder and its power / SINR epilogues (Sec. II-B, III, VI-B).
+ *   precoder  dmimo_precoder.
+ *   H         device [B][K][M] (complex128 for DMIMO_F64, else complex64).
+ *   gamma_lin host [K] per-user SINR targets (linear); NULL = all ones.  Used by
+ *             ZF with p_total <= 0 only.
+ *   sigma2    noise power (>= 0).
+ *   p_total   > 0: scale W so that ||W||_F^2 = p_total (eq. txpower).  For ZF
+ *             every user then has the same SINR.
+ *             <= 0: MR uses W = H^*; ZF uses the constraint of eq. (optim1),
+ *             H W^T = sqrt(sigma2) D_gamma^{1/2}; equal-gain MR uses |w| = 1.
+ *   prec      precision of the Gram (ZF); the Cholesky factorisation, G^-1 and
+ *             G^-1 H are FP64 in every mode.
+ * Outputs (device; any may be NULL except W):
+ *   W      [B][K][M] precoder, same complex type as H.
+ *   p_ant  FP64 [B][M]  per-antenna power p_m = sum_k |w_km|^2.
+ *   l21    FP64 [B]     ||W||_{2,1} = sum_m sqrt(p_m); consumed PA power is alpha * l21.
+ *   sinr   FP64 [B][K]  SINR_k = |A_kk|^2 / (sum_{j!=k} |A_kj|^2 + sigma2), A = H W^T.
+ *   rsum   FP64 [B]     sum rate, sum_k log2(1 + SINR_k).
+ *   info   int32 [B]    0 ok; j > 0 Cholesky pivot j not positive (ZF); W,
+ *                       p_ant, l21, sinr and rsum are zero for that deployment.
+ *   ws, ws_bytes  device workspace of at least
+ *                 dmimo_workspace_size(DMIMO_CALL_BEAMFORM_ZF, B, K, M, 0, prec) bytes
+ *                 (ZF; MR needs none and accepts NULL). */
+dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
+                            const void* H, const double* gamma_lin, double sigma2,
+                            double p_total, int32_t prec, void* W, double* p_ant,
+                            double* l21, double* sinr, double* rsum, int32_t* info,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Fused channel synthesis and coherent sums at N points.  h[n][m] is never
+ * stored.
+ *   z_k[n]    = sum_m h[n][m] w_km         (x = W^T s, Sec. II-A)
+ *   power[n]  = sum_k |z_k[n]|^2           (for K = 1: |sum_m h w|^2)
+ *   sinr[n]   = max_k |z_k|^2 / (sum_{j!=k} |z_j|^2 + sigma2), ties to the lowest k
+ *   best_k[n] = the maximising k
+ *   per_stream[n][k] = |z_k[n]|^2
+ *   params  LoS only (Rician maps: DMIMO_E_UNSUPPORTED).
+ *   ap_xyz  device FP64 [M][3].  W device [K][M] (complex128 for DMIMO_F64, else
+ *           complex64).
+ *   pts     host descriptor (GRID, or LIST of device FP64 [n][3]).
+ *   prec    DMIMO_F64: outputs FP64.  DMIMO_F32 and MIX: outputs FP32.
+ *   power   required.  sinr, best_k, per_stream may be NULL. */
+dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M,
+                            const double* ap_xyz, int32_t K, const void* W,
+                            const dmimo_points* pts, double sigma2, int32_t prec,
+                            void* power, void* sinr, int32_t* best_k, void* per_stream,
+                            void* stream);
+
+enum { DMIMO_CALL_CHANNEL = 0, DMIMO_CALL_GRAM = 1, DMIMO_CALL_BEAMFORM_MR = 2,
+       DMIMO_CALL_BEAMFORM_ZF = 3, DMIMO_CALL_POWERMAP = 4 };
+
+/* Workspace bytes a call needs (0 if none).  Pure host function. */
+size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32_t N,
+                            int32_t prec);
+
+const char* dmimo_status_string(int32_t status);
+/* Detail of the last non-OK status on the calling thread (empty if none). */
+const char* dmimo_last_error(void);
+/* Library version string. */
+const char* dmimo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMIMO_H */

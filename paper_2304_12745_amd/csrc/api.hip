@@ -1,0 +1,255 @@
+// Host side of the C ABI: argument validation, error state and dispatch.
+// Every check here runs before the first HIP runtime call of an entry point,
+// so argument errors are reported without touching the GPU.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "dmimo_internal.h"
+#include "kernels.h"
+
+namespace dmimo {
+
+static thread_local char g_last_error[512] = {0};
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_last_error[0] = 0; }
+
+dmimo_status check_launch(const char* kernel) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: %s", kernel, hipGetErrorString(e));
+        return DMIMO_E_HIP;
+    }
+    return DMIMO_OK;
+}
+
+dmimo_status make_wave_const(const dmimo_channel_params* p, WaveConst* out) {
+    if (!p) return fail(DMIMO_E_ARG, "channel params: NULL");
+    if (!(p->freq_hz > 0.0) || !std::isfinite(p->freq_hz))
+        return fail(DMIMO_E_ARG, "channel params: freq_hz must be > 0");
+    if (p->model != DMIMO_CH_LOS && p->model != DMIMO_CH_RICIAN)
+        return fail(DMIMO_E_DTYPE, "channel params: unknown channel model");
+    if (p->model == DMIMO_CH_RICIAN && !(p->kappa_lin >= 0.0))
+        return fail(DMIMO_E_ARG, "channel params: kappa_lin must be >= 0");
+    const double lam = kSpeedOfLight / p->freq_hz;
+    const double dmin = p->d_min_m > 0.0 ? p->d_min_m : lam / (4.0 * kPi);
+    out->inv_lam = 1.0 / lam;
+    out->amp_c = lam / (4.0 * kPi);
+    out->inv_dmin = 1.0 / dmin;
+    if (p->model == DMIMO_CH_RICIAN) {
+        const double k = p->kappa_lin;
+        out->a_los = std::sqrt(k / (1.0 + k));
+        out->a_nlos = std::sqrt(1.0 / (1.0 + k));
+    } else {
+        out->a_los = 1.0;
+        out->a_nlos = 0.0;
+    }
+    return DMIMO_OK;
+}
+
+dmimo_status make_points(const dmimo_points* p, PointsDev* out) {
+    if (!p) return fail(DMIMO_E_ARG, "points: NULL descriptor");
+    out->kind = p->kind;
+    out->nx = p->nx;
+    out->ny = p->ny;
+    out->x0 = p->x0;
+    out->y0 = p->y0;
+    out->dx = p->dx;
+    out->dy = p->dy;
+    out->z = p->z;
+    out->xyz = p->xyz;
+    if (p->kind == DMIMO_PTS_GRID) {
+        if (p->nx < 0 || p->ny < 0) return fail(DMIMO_E_SHAPE, "points: grid nx, ny must be >= 0");
+        if (!std::isfinite(p->x0) || !std::isfinite(p->y0) || !std::isfinite(p->dx) ||
+            !std::isfinite(p->dy) || !std::isfinite(p->z))
+            return fail(DMIMO_E_ARG, "points: grid origin / pitch / height must be finite");
+        out->n = (int64_t)p->nx * (int64_t)p->ny;
+        out->xyz = nullptr;
+    } else if (p->kind == DMIMO_PTS_LIST) {
+        if (p->n < 0) return fail(DMIMO_E_SHAPE, "points: list n must be >= 0");
+        if (p->n > 0 && !p->xyz) return fail(DMIMO_E_ARG, "points: list xyz is NULL");
+        out->n = p->n;
+    } else {
+        return fail(DMIMO_E_DTYPE, "points: unknown kind");
+    }
+    return DMIMO_OK;
+}
+
+static bool valid_prec(int32_t p) { return p >= DMIMO_F64 && p <= DMIMO_MIX_BF16X3; }
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace dmimo
+
+using namespace dmimo;
+
+extern "C" {
+
+const char* dmimo_version(void) { return "dmimo 0.1 (gfx950)"; }
+
+const char* dmimo_status_string(int32_t s) {
+    switch (s) {
+        case DMIMO_OK: return "ok";
+        case DMIMO_E_ARG: return "invalid argument";
+        case DMIMO_E_SHAPE: return "invalid shape";
+        case DMIMO_E_DTYPE: return "invalid precision / model / kind";
+        case DMIMO_E_WORKSPACE: return "workspace too small";
+        case DMIMO_E_HIP: return "HIP runtime error";
+        case DMIMO_E_UNSUPPORTED: return "unsupported combination";
+        case DMIMO_E_BUSY: return "busy";
+        case DMIMO_E_NOMEM: return "does not fit the memory budget";
+        case DMIMO_E_NOTFOUND: return "not found";
+        default: return "unknown status";
+    }
+}
+
+const char* dmimo_last_error(void) { return g_last_error; }
+
+size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32_t N,
+                            int32_t prec) {
+    (void)M;
+    (void)N;
+    if (B <= 0 || K <= 0) return 0;
+    switch (call) {
+        case DMIMO_CALL_BEAMFORM_ZF: {
+            const size_t elem = prec == DMIMO_F64 ? 16 : 8;
+            return align256((size_t)B * K * K * elem);
+        }
+        default:
+            return 0;
+    }
+}
+
+dmimo_status dmimo_channel(const dmimo_channel_params* params, int32_t B, int32_t M,
+                           const double* ap_xyz, const dmimo_points* pts, const void* nlos,
+                           int32_t out, void* H, void* stream) {
+    clear_error();
+    WaveConst w;
+    dmimo_status st = make_wave_const(params, &w);
+    if (st) return st;
+    PointsDev P;
+    if ((st = make_points(pts, &P))) return st;
+    if (B < 0) return fail(DMIMO_E_SHAPE, "channel: B must be >= 0");
+    if (M < 1) return fail(DMIMO_E_SHAPE, "channel: M must be >= 1");
+    if (!valid_prec(out)) return fail(DMIMO_E_DTYPE, "channel: unknown precision");
+    if (out != DMIMO_F64 && out != DMIMO_F32)
+        return fail(DMIMO_E_UNSUPPORTED, "channel: output must be DMIMO_F64 or DMIMO_F32");
+    if (params->model == DMIMO_CH_RICIAN && !nlos && B > 0 && P.n > 0)
+        return fail(DMIMO_E_ARG, "channel: Rician model needs the nlos draws");
+    if (B == 0 || P.n == 0) return DMIMO_OK;
+    if (!ap_xyz || !H) return fail(DMIMO_E_ARG, "channel: NULL ap_xyz or H");
+    return launch_channel(w, P, params->model == DMIMO_CH_RICIAN, B, M, ap_xyz,
+                          nlos, out == DMIMO_F64, H, as_stream(stream));
+}
+
+dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t prec,
+                        void* G, void* stream) {
+    clear_error();
+    if (B < 0) return fail(DMIMO_E_SHAPE, "gram: B must be >= 0");
+    if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "gram: K and M must be >= 1");
+    if (K > DMIMO_K_MAX) return fail(DMIMO_E_SHAPE, "gram: K exceeds DMIMO_K_MAX");
+    if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "gram: unknown precision");
+    if (B == 0) return DMIMO_OK;
+    if (!H || !G) return fail(DMIMO_E_ARG, "gram: NULL H or G");
+    return launch_gram(B, K, M, H, prec, G, as_stream(stream));
+}
+
+dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, const void* H,
+                            const double* gamma_lin, double sigma2, double p_total,
+                            int32_t prec, void* W, double* p_ant, double* l21, double* sinr,
+                            double* rsum, int32_t* info, void* ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    if (precoder != DMIMO_MR && precoder != DMIMO_ZF && precoder != DMIMO_MR_PHASE)
+        return fail(DMIMO_E_DTYPE, "beamform: unknown precoder");
+    if (B < 0) return fail(DMIMO_E_SHAPE, "beamform: B must be >= 0");
+    if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "beamform: K and M must be >= 1");
+    if (K > DMIMO_K_MAX) return fail(DMIMO_E_SHAPE, "beamform: K exceeds DMIMO_K_MAX");
+    if (precoder == DMIMO_ZF && K > M)
+        return fail(DMIMO_E_SHAPE, "beamform: ZF needs K <= M");
+    if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "beamform: unknown precision");
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2))
+        return fail(DMIMO_E_ARG, "beamform: sigma2 must be >= 0");
+    if (!std::isfinite(p_total)) return fail(DMIMO_E_ARG, "beamform: p_total must be finite");
+    if ((sinr || rsum) && !(sigma2 > 0.0))
+        return fail(DMIMO_E_ARG, "beamform: SINR outputs need sigma2 > 0");
+    double gam[DMIMO_K_MAX];
+    for (int k = 0; k < K; ++k) {
+        gam[k] = gamma_lin ? gamma_lin[k] : 1.0;
+        if (!(gam[k] >= 0.0) || !std::isfinite(gam[k]))
+            return fail(DMIMO_E_ARG, "beamform: gamma_lin must be finite and >= 0");
+    }
+    const size_t need = precoder == DMIMO_ZF
+                            ? dmimo_workspace_size(DMIMO_CALL_BEAMFORM_ZF, B, K, M, 0, prec)
+                            : 0;
+    if (B == 0) return DMIMO_OK;
+    if (!H || !W) return fail(DMIMO_E_ARG, "beamform: NULL H or W");
+    if (need > 0 && (!ws || ws_bytes < need)) {
+        set_error("beamform: workspace needs %zu bytes, got %zu", need, ws ? ws_bytes : 0);
+        return DMIMO_E_WORKSPACE;
+    }
+    BeamformArgs a;
+    a.precoder = precoder;
+    a.B = B;
+    a.K = K;
+    a.M = M;
+    a.H = H;
+    for (int k = 0; k < DMIMO_K_MAX; ++k) a.gamma[k] = k < K ? gam[k] : 0.0;
+    a.sigma2 = sigma2;
+    a.p_total = p_total;
+    a.prec = prec;
+    a.W = W;
+    a.p_ant = p_ant;
+    a.l21 = l21;
+    a.sinr = sinr;
+    a.rsum = rsum;
+    a.info = info;
+    a.ws = ws;
+    return launch_beamform(a, as_stream(stream));
+}
+
+dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const double* ap_xyz,
+                            int32_t K, const void* W, const dmimo_points* pts, double sigma2,
+                            int32_t prec, void* power, void* sinr, int32_t* best_k,
+                            void* per_stream, void* stream) {
+    clear_error();
+    WaveConst w;
+    dmimo_status st = make_wave_const(params, &w);
+    if (st) return st;
+    if (params->model != DMIMO_CH_LOS)
+        return fail(DMIMO_E_UNSUPPORTED, "powermap: only the LoS model is mapped");
+    PointsDev P;
+    if ((st = make_points(pts, &P))) return st;
+    if (M < 1 || K < 1) return fail(DMIMO_E_SHAPE, "powermap: K and M must be >= 1");
+    if (K > DMIMO_K_MAX) return fail(DMIMO_E_SHAPE, "powermap: K exceeds DMIMO_K_MAX");
+    if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "powermap: unknown precision");
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2))
+        return fail(DMIMO_E_ARG, "powermap: sigma2 must be >= 0");
+    if (sinr && !(sigma2 > 0.0)) return fail(DMIMO_E_ARG, "powermap: SINR map needs sigma2 > 0");
+    if (P.n > (int64_t)INT32_MAX * 8) return fail(DMIMO_E_SHAPE, "powermap: too many points");
+    if (P.n == 0) return DMIMO_OK;
+    if (!ap_xyz || !W || !power) return fail(DMIMO_E_ARG, "powermap: NULL ap_xyz, W or power");
+    PowermapArgs a;
+    a.w = w;
+    a.P = P;
+    a.M = M;
+    a.K = K;
+    a.ap = ap_xyz;
+    a.W = W;
+    a.sigma2 = sigma2;
+    a.prec = prec;
+    a.power = power;
+    a.sinr = sinr;
+    a.best_k = best_k;
+    a.per_stream = per_stream;
+    return launch_powermap(a, as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Launchers of the device kernels (host functions, one per entry point).
+#pragma once
+
+#include "dmimo_internal.h"
+
+namespace dmimo {
+
+dmimo_status launch_channel(const WaveConst& w, const PointsDev& P, bool rician, int64_t B,
+                            int64_t M, const double* ap, const void* nlos, bool f64, void* H,
+                            hipStream_t s);
+
+dmimo_status launch_gram(int64_t B, int K, int64_t M, const void* H, int prec, void* G,
+                         hipStream_t s);
+
+struct BeamformArgs {
+    int precoder;
+    int64_t B;
+    int K;
+    int64_t M;
+    const void* H;
+    double gamma[DMIMO_K_MAX];
+    double sigma2;
+    double p_total;
+    int prec;
+    void* W;
+    double* p_ant;
+    double* l21;
+    double* sinr;
+    double* rsum;
+    int32_t* info;
+    void* ws;
+};
+
+dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s);
+
+struct PowermapArgs {
+    WaveConst w;
+    PointsDev P;
+    int M;
+    int K;
+    const double* ap;
+    const void* W;
+    double sigma2;
+    int prec;
+    void* power;
+    void* sinr;
+    int32_t* best_k;
+    void* per_stream;
+};
+
+dmimo_status launch_powermap(const PowermapArgs& a, hipStream_t s);
+
+}  // namespace dmimo

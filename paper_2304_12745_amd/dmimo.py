@@ -1,0 +1,254 @@
+"""Python binding of libdmimo (ctypes).
+
+Argument marshalling only: every step runs in the HIP kernels of
+libdmimo.so.  Arrays are torch tensors on the GPU (device memory), and calls
+are ordered on the current torch stream unless ``stream`` is given.  There is
+no CPU fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmimo.so")
+
+# precision / model / precoder / points enums (include/dmimo.h)
+F64, F32, MIX_F16X3, MIX_BF16X3 = 0, 1, 2, 3
+CH_LOS, CH_RICIAN = 0, 1
+MR, ZF, MR_PHASE = 0, 1, 2
+PTS_GRID, PTS_LIST = 0, 1
+CALL_CHANNEL, CALL_GRAM, CALL_BEAMFORM_MR, CALL_BEAMFORM_ZF, CALL_POWERMAP = 0, 1, 2, 3, 4
+K_MAX = 32
+
+PRECISIONS = {"f64": F64, "f32": F32, "f16x3": MIX_F16X3, "bf16x3": MIX_BF16X3}
+PRECODERS = {"mr": MR, "zf": ZF, "mr_phase": MR_PHASE}
+
+STATUS = {0: "DMIMO_OK", 1: "DMIMO_E_ARG", 2: "DMIMO_E_SHAPE", 3: "DMIMO_E_DTYPE",
+          4: "DMIMO_E_WORKSPACE", 5: "DMIMO_E_HIP", 6: "DMIMO_E_UNSUPPORTED",
+          7: "DMIMO_E_BUSY", 8: "DMIMO_E_NOMEM", 9: "DMIMO_E_NOTFOUND"}
+
+
+class DmimoError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class ChannelParams(ctypes.Structure):
+    _fields_ = [("freq_hz", ctypes.c_double), ("model", ctypes.c_int32),
+                ("kappa_lin", ctypes.c_double), ("d_min_m", ctypes.c_double)]
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dx", ctypes.c_double),
+                ("dy", ctypes.c_double), ("z", ctypes.c_double),
+                ("xyz", ctypes.c_void_p), ("n", ctypes.c_int32)]
+
+
+_vp, _i32, _f64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+_SIGS = {
+    "dmimo_channel": [ctypes.POINTER(ChannelParams), _i32, _i32, _vp, ctypes.POINTER(Points),
+                      _vp, _i32, _vp, _vp],
+    "dmimo_gram": [_i32, _i32, _i32, _vp, _i32, _vp, _vp],
+    "dmimo_beamform": [_i32, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _vp, _vp,
+                       _vp, _vp, _vp, _sz, _vp],
+    "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
+                       ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
+    "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
+    "dmimo_status_string": [_i32],
+    "dmimo_last_error": [],
+    "dmimo_version": [],
+}
+_RESTYPES = {"dmimo_workspace_size": _sz, "dmimo_status_string": ctypes.c_char_p,
+             "dmimo_last_error": ctypes.c_char_p, "dmimo_version": ctypes.c_char_p}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libdmimo.so not built ({path}); run python -m paper_2304_12745_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPES.get(name, _i32)
+    return lib
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        detail = lib().dmimo_last_error().decode()
+        raise DmimoError(status, where, detail)
+
+
+# ---------------------------------------------------------------------------
+# helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def channel_params(freq_hz: float, model: int = CH_LOS, kappa_lin: float = 0.0,
+                   d_min_m: float = 0.0) -> ChannelParams:
+    return ChannelParams(float(freq_hz), int(model), float(kappa_lin), float(d_min_m))
+
+
+def grid_points(grid) -> Points:
+    """Descriptor of a regular grid (an object with x0, y0, dx, dy, z, nx, ny)."""
+    return Points(PTS_GRID, int(grid.nx), int(grid.ny), float(grid.x0), float(grid.y0),
+                  float(grid.dx), float(grid.dy), float(grid.z), None, 0)
+
+
+def list_points(xyz, n: int) -> Points:
+    """Descriptor of an explicit device point list (FP64 tensor [.., n, 3]).
+
+    The descriptor holds a reference to ``xyz``, so the device memory stays
+    alive as long as the descriptor does.
+    """
+    p = Points(PTS_LIST, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, _ptr(xyz), int(n))
+    p._keep = xyz
+    return p
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _cdtype(prec: int):
+    import torch
+    return torch.complex128 if prec == F64 else torch.complex64
+
+
+def _rdtype(prec: int):
+    import torch
+    return torch.float64 if prec == F64 else torch.float32
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def channel(params: ChannelParams, ap_xyz, points: Points, nlos=None, prec="f32", out=None,
+            B: Optional[int] = None, N: Optional[int] = None, stream=None):
+    """H[b][n][m] (dmimo_channel).  ap_xyz: float64 [B][M][3] on the GPU."""
+    import torch
+    prec = _prec(prec)
+    B = ap_xyz.shape[0] if B is None else B
+    M = ap_xyz.shape[1]
+    if N is None:
+        N = points.nx * points.ny if points.kind == PTS_GRID else points.n
+    if out is None:
+        out = torch.empty((B, N, M), dtype=_cdtype(prec), device=ap_xyz.device)
+    _check(lib().dmimo_channel(ctypes.byref(params), B, M, _ptr(ap_xyz), ctypes.byref(points),
+                               _ptr(nlos), prec, _ptr(out), _stream(stream)), "dmimo_channel")
+    return out
+
+
+def gram(H, prec="f32", out=None, stream=None):
+    """G[b] = H[b] H[b]^H (dmimo_gram).  H: complex [B][K][M] on the GPU."""
+    import torch
+    prec = _prec(prec)
+    B, K, M = H.shape
+    if out is None:
+        out = torch.empty((B, K, K), dtype=_cdtype(prec), device=H.device)
+    _check(lib().dmimo_gram(B, K, M, _ptr(H), prec, _ptr(out), _stream(stream)), "dmimo_gram")
+    return out
+
+
+def workspace_size(call: int, B: int, K: int, M: int, N: int, prec) -> int:
+    return int(lib().dmimo_workspace_size(call, B, K, M, N, _prec(prec)))
+
+
+@dataclass
+class BeamformResult:
+    W: object
+    p_ant: object
+    l21: object
+    sinr: object
+    rsum: object
+    info: object
+
+
+def beamform(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f32",
+             outputs=True, ws=None, stream=None) -> BeamformResult:
+    """Precoder + epilogues (dmimo_beamform).  H: complex [B][K][M] on the GPU."""
+    import torch
+    prec = _prec(prec)
+    pc = PRECODERS[precoder] if isinstance(precoder, str) else int(precoder)
+    B, K, M = H.shape
+    dev = H.device
+    W = torch.empty((B, K, M), dtype=_cdtype(prec), device=dev)
+    p_ant = torch.empty((B, M), dtype=torch.float64, device=dev) if outputs else None
+    l21 = torch.empty((B,), dtype=torch.float64, device=dev) if outputs else None
+    sinr = torch.empty((B, K), dtype=torch.float64, device=dev) if outputs else None
+    rsum = torch.empty((B,), dtype=torch.float64, device=dev) if outputs else None
+    info = torch.empty((B,), dtype=torch.int32, device=dev) if outputs else None
+    need = workspace_size(CALL_BEAMFORM_ZF if pc == ZF else CALL_BEAMFORM_MR, B, K, M, 0, prec)
+    if need and ws is None:
+        ws = torch.empty((need,), dtype=torch.uint8, device=dev)
+    g = None
+    if gamma_lin is not None:
+        g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+    _check(lib().dmimo_beamform(pc, B, K, M, _ptr(H), g, float(sigma2), float(p_total), prec,
+                                _ptr(W), _ptr(p_ant), _ptr(l21), _ptr(sinr), _ptr(rsum),
+                                _ptr(info), _ptr(ws), ws.numel() if ws is not None else 0,
+                                _stream(stream)), "dmimo_beamform")
+    return BeamformResult(W, p_ant, l21, sinr, rsum, info)
+
+
+@dataclass
+class MapResult:
+    power: object
+    sinr: object
+    best_k: object
+    per_stream: object
+
+
+def powermap(params: ChannelParams, ap_xyz, W, points: Points, sigma2=1e-12, prec="f32",
+             want_sinr=True, want_best=True, want_per_stream=False, out=None,
+             stream=None) -> MapResult:
+    """Fused synthesis + coherent sums (dmimo_powermap).  ap_xyz float64 [M][3], W [K][M]."""
+    import torch
+    prec = _prec(prec)
+    K, M = W.shape
+    N = points.nx * points.ny if points.kind == PTS_GRID else points.n
+    dev = W.device
+    rd = _rdtype(prec)
+    if out is None:
+        out = MapResult(
+            torch.empty((N,), dtype=rd, device=dev),
+            torch.empty((N,), dtype=rd, device=dev) if want_sinr else None,
+            torch.empty((N,), dtype=torch.int32, device=dev) if want_best else None,
+            torch.empty((N, K), dtype=rd, device=dev) if want_per_stream else None)
+    _check(lib().dmimo_powermap(ctypes.byref(params), M, _ptr(ap_xyz), K, _ptr(W),
+                                ctypes.byref(points), float(sigma2), prec, _ptr(out.power),
+                                _ptr(out.sinr), _ptr(out.best_k), _ptr(out.per_stream),
+                                _stream(stream)), "dmimo_powermap")
+    return out
+
+
+def version() -> str:
+    return lib().dmimo_version().decode()

