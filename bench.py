@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Benchmark of the distributed-MIMO hot path on one MI355X.
+
+Workload ("room"): M = 64 APs on a jittered 8x8 ceiling grid (pitch 2.5 m,
+z = 4 m) of a 20x20x4 m room, 3.5 GHz, K = 8 users at z = 1.2 m, noise -90 dBm.
+One step is one pass of the whole path, with inputs already resident in HBM:
+
+  1. dmimo_channel   user channels H (K x M, complex64)
+  2. dmimo_beamform  MR at 1 W                      (+ p_m, L2,1, SINR_k, R_sum)
+  3. dmimo_beamform  ZF at 1 W: Gram, FP64 Cholesky (+ the same epilogues)
+  4. dmimo_powermap  MR power + SINR + best-stream maps, 512 x 512 grid at z = 1.2 m
+  5. dmimo_powermap  ZF power + SINR + best-stream maps, same grid
+
+value = channel terms h[n,m] synthesised and consumed per second, over the
+whole step (K M for each of 1-3, N M for each map), in G h/s.
+
+The JSON line also carries:
+* ``roofline`` for the dominant kernel (the FP32 power map).  It is bound by
+  plain VALU arithmetic; the algorithmic cost and the peak are stated below.
+* ``cpu_baseline``: the FP64 oracle timed on a bounded sample of the same step.
+* ``err_db``: the error of the GPU maps against the oracle on that sample.
+
+Only the cpu_baseline leg imports the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# ---------------------------------------------------------------------------
+# roofline model of the power-map kernel (VALU issue slots)
+# ---------------------------------------------------------------------------
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-slots/s.
+# FP64 add/mul/FMA and unpacked FP32 ops issue at that full rate.  The
+# transcendental ops (rsq, sin, cos) take 4 slots each.
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# Algorithmic slots per term for FP64 distance/phase + FP32 synthesis:
+#   3 sub + 3 (mul, 2 FMA) for d^2                             6
+#   sqrt: cvt, rsq(4), cvt, 4 FP64 Newton ops                  10
+#   revolutions: mul, floor, FMA (fract), cvt                   4
+#   sin(4) + cos(4)                                             8
+#   amplitude min + mul, h = amp * (c, -s): 2 mul                4
+# = 32 slots, plus 4 FP32 FMA per stream (one complex MAC).
+SYNTH_SLOTS = 32
+
+
+def alg_slots_per_term(K: int) -> int:
+    return SYNTH_SLOTS + 4 * K
+
+
+def _src_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
+                    "paper_2304_12745_amd/csrc/dmimo_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
+
+
+def load_traffic(kernel_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary.
+
+    None if there is none, or if it was taken on other kernel sources.
+    """
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_hash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def parse_args():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=500)
+    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--nx", type=int, default=512)
+    p.add_argument("--cpu-seconds", type=float, default=10.0,
+                   help="budget of the oracle CPU baseline (0 disables it)")
+    p.add_argument("--no-cpu", action="store_true")
+    return p.parse_args()
+
+
+def main():
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(grid points shard with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2304_12745_amd import dmimo as D
+    from paper_2304_12745_amd import workloads as WL
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    D.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    w = WL.room_workload(nx=args.nx, ny=args.nx)
+    K, M, N = w.K, w.M, w.grid.n
+    params = D.channel_params(w.freq_hz)
+    ap = torch.from_numpy(w.ap_xyz).to(dev)            # [1][M][3]
+    ap0 = ap[0].contiguous()
+    users = torch.from_numpy(w.user_xyz).to(dev)       # [1][K][3]
+    upts = D.list_points(users, K)
+    gpts = D.grid_points(w.grid)
+    H = torch.empty((1, K, M), dtype=torch.complex64, device=dev)
+    ws = torch.empty((max(D.workspace_size(D.CALL_BEAMFORM_ZF, 1, K, M, 0, "f32"), 256),),
+                     dtype=torch.uint8, device=dev)
+    maps = {p: D.MapResult(torch.empty(N, device=dev), torch.empty(N, device=dev),
+                           torch.empty(N, dtype=torch.int32, device=dev), None)
+            for p in ("mr", "zf")}
+    bf = {}
+
+    # a plain copy of known size, for scaling the HBM counters of a profiled run
+    cp_src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    cp_dst = torch.empty_like(cp_src)
+    cp_dst.copy_(cp_src)
+
+    def step(evs=None):
+        D.channel(params, ap, upts, prec="f32", out=H)
+        bf["mr"] = D.beamform(H, "mr", None, w.sigma2, w.p_total, "f32")
+        bf["zf"] = D.beamform(H, "zf", None, w.sigma2, w.p_total, "f32", ws=ws)
+        for i, p in enumerate(("mr", "zf")):
+            if evs is not None:
+                evs[2 * i].record()
+            D.powermap(params, ap0, bf[p].W[0], gpts, w.sigma2, "f32", out=maps[p])
+            if evs is not None:
+                evs[2 * i + 1].record()
+
+    for _ in range(args.warmup):
+        step()
+    # HIP events around both map launches of every timed step, on the stream the
+    # kernels run on (torch's current stream); read after the final sync
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        step(events[s_])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kernel_ms_total = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in events)
+
+    terms_per_step = 3 * K * M + 2 * N * M
+    value = terms_per_step / (ms_per_step * 1e-3) / 1e9
+    map_launch_ms = kernel_ms_total / (2 * args.steps)
+    alg = alg_slots_per_term(K) * N * M
+    achieved = alg / (map_launch_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_SLOTS / 1e12
+    khash = _src_hash(POWERMAP_SOURCES)
+    traffic = load_traffic(khash)
+
+    out = {
+        "metric": "channel-term evals/sec (G h[n,m]/s)",
+        "value": round(value, 3),
+        "unit": "G h/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"room: M={M} APs jittered 8x8 ceiling grid 20x20x4 m, K={K} users, "
+                        f"3.5 GHz, MR+ZF at 1 W, noise -90 dBm, {w.grid.nx}x{w.grid.ny} power+SINR "
+                        "maps at z=1.2 m; FP64 distance/phase, FP32 synthesis and contraction",
+            "M": M, "K": K, "N": N, "terms_per_step": terms_per_step,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "powermap_valu_kernel<8,false>",
+            "achieved": round(achieved, 3),
+            "peak": round(peak, 3),
+            "unit": "T VALU lane-slots/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": traffic,
+            "launch_ms": round(map_launch_ms, 5),
+            "alg_slots_per_term": alg_slots_per_term(K),
+            "terms_per_launch": N * M,
+            "source_hash": khash,
+        },
+    }
+
+    if not args.no_cpu and args.cpu_seconds > 0:
+        out["cpu_baseline"], out["err_db"] = cpu_baseline(w, bf, maps, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, bf, maps, budget_s):
+    """Oracle timed on a bounded sample of the step, single-threaded.
+
+    The sample is the user-side calls (channel, MR and ZF precoders with
+    their SINR and L2,1 epilogues) plus power and SINR maps of both precoders
+    on 16 random grid rows, repeated until the budget is spent.
+
+    Also reports the dB error of the GPU chain (GPU H -> GPU W -> GPU map)
+    against the oracle chain (oracle H -> oracle W -> oracle map) on the first
+    sampled rows.  No GPU output enters the oracle.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dberror
+    from oracle import dmimo_oracle as O
+
+    g = w.grid
+    nx = g.nx
+    rows_per_rep = 16
+    pts_all = O.grid_points(g.x0, g.y0, g.dx, g.dy, g.z, g.nx, g.ny)
+    aps = w.ap_xyz[0]
+    K, M = w.K, w.M
+    gpu = {p: (maps[p].power.cpu().numpy(), maps[p].sinr.cpu().numpy()) for p in maps}
+    pairs = {"power": [], "sinr": []}
+    terms = 0
+    reps = 0
+    rng = np.random.default_rng(0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            Hu = O.los_channel(w.user_xyz[0], aps, w.freq_hz)
+            Wmr = O.mr_precoder(Hu, w.p_total)
+            Wzf, _ = O.zf_precoder(Hu, None, w.sigma2, w.p_total)
+            for Wp in (Wmr, Wzf):
+                O.user_sinr(Hu, Wp, w.sigma2)
+                O.antenna_power(Wp)
+                O.l21_norm(Wp)
+            terms += 3 * K * M
+            j0 = int(rng.integers(0, g.ny - rows_per_rep + 1))
+            sl = slice(j0 * nx, (j0 + rows_per_rep) * nx)
+            Hg = O.los_channel(pts_all[sl], aps, w.freq_hz)
+            for name, Wp in (("mr", Wmr), ("zf", Wzf)):
+                y = O.power_map(Hg, Wp)
+                s, _ = O.sinr_map(Hg, Wp, w.sigma2)
+                terms += (sl.stop - sl.start) * M
+                if reps < 8:
+                    pairs["power"].append((gpu[name][0][sl], y))
+                    pairs["sinr"].append((gpu[name][1][sl], s))
+            reps += 1
+        elapsed = time.perf_counter() - t0
+    err = {}
+    for k, pr in pairs.items():
+        y = np.concatenate([p[0] for p in pr])
+        r = np.concatenate([p[1] for p in pr])
+        sm = dberror.summary(y, r, 0.01)
+        err[k] = {"max_db": sm["max_db"], "p99_db": sm["p99_db"], "n": sm["n"],
+                  "n_below_floor": sm["n_below_floor"], "n_over_0.01dB": sm["n_fail"]}
+    err["compared"] = "GPU chain vs oracle chain (users -> precoder -> map), both precoders"
+    cpu = {
+        "value": round(terms / elapsed / 1e9, 6),
+        "unit": "G h/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{reps} reps of the step's user-side calls plus power+SINR maps of MR and ZF "
+                  f"on {rows_per_rep} random grid rows ({rows_per_rep * nx} points each): "
+                  f"{terms} terms in {elapsed:.1f} s",
+    }
+    return cpu, err
+
+
+if __name__ == "__main__":
+    main()
