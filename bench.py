@@ -47,12 +47,15 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 #   revolutions: mul, floor, FMA (fract), cvt                   4
 #   sin(4) + cos(4)                                             8
 #   amplitude min + mul, h = amp * (c, -s): 2 mul                4
-# = 32 slots, plus 4 FP32 FMA per stream (one complex MAC).
+# = 32 slots.  With K >= 3 the K complex MACs (8K real flops per term) run on
+# FP32 MFMA (157.3 TFLOP/s dense) and overlap the VALU; the kernel is bound by
+# whichever of the two pipes has the larger fraction.
 SYNTH_SLOTS = 32
+MFMA_F32_PEAK = 157.3e12
 
 
 def alg_slots_per_term(K: int) -> int:
-    return SYNTH_SLOTS + 4 * K
+    return SYNTH_SLOTS if K >= 3 else SYNTH_SLOTS + 4 * K
 
 
 def _src_hash(files):
@@ -64,6 +67,7 @@ def _src_hash(files):
 
 
 POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
+                    "paper_2304_12745_amd/csrc/powermap_mfma.hip",
                     "paper_2304_12745_amd/csrc/dmimo_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
 
@@ -168,6 +172,7 @@ def main():
     alg = alg_slots_per_term(K) * N * M
     achieved = alg / (map_launch_ms * 1e-3) / 1e12
     peak = VALU_PEAK_SLOTS / 1e12
+    mfma_tflops = 8 * K * N * M / (map_launch_ms * 1e-3) / 1e12
     khash = _src_hash(POWERMAP_SOURCES)
     traffic = load_traffic(khash)
 
@@ -192,7 +197,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "powermap_valu_kernel<8,false>",
+            "kernel": "powermap_mfma_kernel<1,4>",
             "achieved": round(achieved, 3),
             "peak": round(peak, 3),
             "unit": "T VALU lane-slots/s",
@@ -200,6 +205,9 @@ def main():
             "traffic": traffic,
             "launch_ms": round(map_launch_ms, 5),
             "alg_slots_per_term": alg_slots_per_term(K),
+            "mfma_f32": {"achieved": round(mfma_tflops, 3), "peak": MFMA_F32_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": round(mfma_tflops * 1e12 / MFMA_F32_PEAK, 4),
+                         "flops_per_term": 8 * K},
             "terms_per_launch": N * M,
             "source_hash": khash,
         },

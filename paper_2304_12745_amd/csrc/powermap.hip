@@ -149,7 +149,11 @@ dmimo_status launch_powermap(const PowermapArgs& a, hipStream_t s) {
     d.best_k = a.best_k;
     d.per_stream = a.per_stream;
     if (a.prec == DMIMO_F64) return launch_valu<true>(d, s);
-    if (a.prec == DMIMO_F32) return launch_valu<false>(d, s);
+    if (a.prec == DMIMO_F32) {
+        // one or two streams: four or eight FMA per term stay on the VALU
+        if (a.K <= 2) return launch_valu<false>(d, s);
+        return launch_powermap_f32_mfma(a, s);
+    }
     return launch_powermap_mfma(a, s);
 }
 

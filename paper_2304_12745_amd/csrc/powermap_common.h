@@ -1,0 +1,173 @@
+// Pieces shared by the matrix-core power-map kernels.
+#pragma once
+
+#include "kernels.h"
+
+namespace dmimo {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Device arguments of the FP32-output map kernels.
+struct PmMapDev {
+    PointsDev P;
+    int M;
+    int K;
+    double inv_lam;      // 1 / lambda: positions are converted to wavelengths
+    float amp_rev;       // 1 / (4 pi): amplitude = amp_rev / d_rev
+    float inv_dmin_rev;  // lambda / d_min
+    const double* ap;    // [M][3] metres
+    const float2* W;     // [K][M]
+    float sigma2;
+    float* power;
+    float* sinr;
+    int32_t* best_k;
+    float* per_stream;
+};
+
+inline PmMapDev make_map_dev(const PowermapArgs& a) {
+    PmMapDev d;
+    d.P = a.P;
+    d.M = a.M;
+    d.K = a.K;
+    d.inv_lam = a.w.inv_lam;
+    d.amp_rev = (float)(1.0 / (4.0 * kPi));
+    d.inv_dmin_rev = (float)(a.w.inv_dmin / a.w.inv_lam);
+    d.ap = a.ap;
+    d.W = reinterpret_cast<const float2*>(a.W);
+    d.sigma2 = (float)a.sigma2;
+    d.power = reinterpret_cast<float*>(a.power);
+    d.sinr = reinterpret_cast<float*>(a.sinr);
+    d.best_k = a.best_k;
+    d.per_stream = reinterpret_cast<float*>(a.per_stream);
+    return d;
+}
+
+// Point n in wavelengths (FP64).
+__device__ __forceinline__ void point_rev(const PmMapDev& a, int64_t n, double& x, double& y,
+                                          double& z) {
+    point_xyz(a.P, 0, n, x, y, z);
+    x *= a.inv_lam;
+    y *= a.inv_lam;
+    z *= a.inv_lam;
+}
+
+// One spherical-wave term with every length in wavelengths.
+//   d2 = dx^2 + dy^2 + dz^2 (FP64).
+//   d  = sqrt(d2): an FP32 rsq seed refined by one FP64 Newton step
+//        (relative error ~1.5 eps_seed^2 ~ 1e-13).
+//   fr = frac(d): exact in FP64, i.e. the phase 2 pi d / lambda reduced
+//        to [0, 1) revolutions.
+//   h  = amp * (cos 2 pi fr - j sin 2 pi fr), with amp = 1 / (4 pi max(d, d_min)).
+// The hardware sin / cos take revolutions directly.  `scale` multiplies the
+// amplitude (the FP16 split path uses it to place h in the FP16 range).
+__device__ __forceinline__ void wave_term_rev(double dx, double dy, double dz, float amp_scaled,
+                                              float inv_dmin_rev, float& hr, float& hi) {
+    const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const float rs = __builtin_amdgcn_rsqf(fmaxf((float)d2, 1e-30f));
+    const double y = (double)rs;
+    const double s0 = d2 * y;
+    const double e = fma(-s0, s0, d2);
+    const double d = fma(e, 0.5 * y, s0);
+    const float fr = (float)__builtin_amdgcn_fract(d);
+    const float amp = amp_scaled * fminf(rs, inv_dmin_rev);
+    hr = amp * __builtin_amdgcn_cosf(fr);
+    hi = -amp * __builtin_amdgcn_sinf(fr);
+}
+
+// Column layouts of the output tiles (see the kernels):
+//   NT = 1 (K <= 8):  column j < 8 is Re z_j, column j >= 8 is Im z_{j-8}.
+//   NT = 2, 4:        tile 2q holds Re z_{16q+j}, tile 2q+1 holds Im z_{16q+j}.
+template <int NT>
+__device__ __forceinline__ void column_stream(int nt, int j, int& k, int& part) {
+    if (NT == 1) {
+        k = j & 7;
+        part = j >> 3;
+    } else {
+        k = 16 * (nt >> 1) + j;
+        part = nt & 1;
+    }
+}
+
+// B1 = [wr | wi] multiplies hr; B2 = [-wi | wr] multiplies hi.
+__device__ __forceinline__ float b_value(float2 w, int part, bool second) {
+    if (!second) return part == 0 ? w.x : w.y;
+    return part == 0 ? -w.y : w.x;
+}
+
+// Floats per point in the epilogue buffer: every column of a tile (re^2 and
+// im^2 separately for NT = 1, stream powers for NT >= 2), padded by one.
+template <int NT>
+constexpr int ep_stride() {
+    return NT == 1 ? 17 : (NT == 2 ? 17 : 33);
+}
+
+// LDS bytes of the epilogue buffer of a 4-wave workgroup.
+template <int NT, int PT>
+constexpr int ep_bytes() {
+    return 4 * 16 * PT * ep_stride<NT>() * 4;
+}
+
+// Epilogue of all PT x NT accumulator tiles of a wave.
+//
+// The per-stream powers go through LDS.  Lane (grp, col) holds D[4 grp + r][col]
+// of every tile, and writes column col of its four rows.  Then lane p < 16 PT
+// reads back point p's K powers.  It forms the total power, the best stream
+// (largest power, lowest index on ties) and the interference of the others,
+// accumulating in ascending stream order.  `ep` is this wave's slice of the
+// buffer.  The caller has made sure the LDS is no longer used for anything
+// else, and every thread of the workgroup calls this function.
+template <int NT, int PT>
+__device__ __forceinline__ void map_epilogue(const PmMapDev& a, const f32x4 (&acc)[PT][NT],
+                                             int64_t base, int lane, float* ep) {
+    constexpr int KS = ep_stride<NT>();
+    const int grp = lane >> 4;
+    const int col = lane & 15;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float* row = ep + (16 * t + 4 * grp + r) * KS;
+            if constexpr (NT == 1) {
+                const float v = acc[t][0][r];
+                row[col] = v * v;                       // re^2 (col < 8) or im^2 (col >= 8)
+            } else {
+                const float re0 = acc[t][0][r], im0 = acc[t][1][r];
+                row[col] = re0 * re0 + im0 * im0;
+                if constexpr (NT == 4) {
+                    const float re1 = acc[t][2][r], im1 = acc[t][3][r];
+                    row[16 + col] = re1 * re1 + im1 * im1;
+                }
+            }
+        }
+    }
+    __syncthreads();   // every thread of the workgroup reaches the epilogue
+    if (lane >= 16 * PT) return;
+    const int64_t n = base + lane;
+    if (n >= a.P.n) return;
+    const float* row = ep + lane * KS;
+    const int K = a.K;
+    float y = 0.0f, pb = -1.0f;
+    int kb = 0;
+    for (int k = 0; k < K; ++k) {
+        const float p = NT == 1 ? row[k] + row[8 + k] : row[k];
+        y += p;
+        if (p > pb) {
+            pb = p;
+            kb = k;
+        }
+    }
+    a.power[n] = y;
+    if (a.sinr) {
+        float intf = 0.0f;
+        for (int k = 0; k < K; ++k)
+            if (k != kb) intf += NT == 1 ? row[k] + row[8 + k] : row[k];
+        a.sinr[n] = pb / (intf + a.sigma2);
+    }
+    if (a.best_k) a.best_k[n] = kb;
+    if (a.per_stream) {
+        float* ps = a.per_stream + n * K;
+        for (int k = 0; k < K; ++k) ps[k] = NT == 1 ? row[k] + row[8 + k] : row[k];
+    }
+}
+
+}  // namespace dmimo

@@ -322,15 +322,19 @@ def test_powermap_focus_f32(D):
                "f32", 0.01)
 
 
+MAP_TOL = {"f32": 0.01, "f16x3": 0.1, "bf16x3": 0.1}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 @pytest.mark.parametrize("precoder", ["mr", "zf"])
-def test_powermap_room_small_grid(D, precoder):
-    say(f"powermap room {precoder} (M=64, K=8, 128x128 grid, FP32)")
+def test_powermap_room_small_grid(D, precoder, prec):
+    say(f"powermap room {precoder} (M=64, K=8, 128x128 grid, {prec})")
     w = WL.room_workload(nx=128, ny=128)
     aps = w.ap_xyz[0]
     Hu = c64(_room_users(w))[0].astype(np.complex128)
     W = O.mr_precoder(Hu, 1.0) if precoder == "mr" else O.zf_precoder(Hu, None, w.sigma2, 1.0)[0]
     _check_map(D, aps, c64(W), D.grid_points(w.grid), grid_pts(w.grid), w.freq_hz, w.sigma2,
-               "f32", 0.01)
+               prec, MAP_TOL[prec])
 
 
 @pytest.mark.parametrize("precoder", ["mr", "zf"])
@@ -356,15 +360,29 @@ def test_powermap_room_full_grid_sampled_rows(D, precoder):
     assert np.all(np.isfinite(power)) and np.all(power > 0)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 @pytest.mark.parametrize("K", [1, 2, 3, 5, 8, 12, 16, 32])
-def test_powermap_stream_counts(D, K):
-    say(f"powermap K={K} list points (N=1000 ragged), FP32")
+def test_powermap_stream_counts(D, K, prec):
+    say(f"powermap K={K} list points (N=1000 ragged, M=48), {prec}")
     rng = np.random.default_rng(40 + K)
     M = 48
     aps = WL.uniform_positions(rng, M, 20, 20, 4.0)
     pts = WL.uniform_positions(rng, 1000, 20, 20, 1.2)
     W = c64(WL.complex_normal(rng, (K, M)) * 0.1)
-    _check_map(D, aps, W, D.list_points(dev(pts), 1000), pts, 3.5e9, 1e-12, "f32", 0.01)
+    _check_map(D, aps, W, D.list_points(dev(pts), 1000), pts, 3.5e9, 1e-12, prec, MAP_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+def test_powermap_mixed_weight_dynamic_range(D, prec):
+    # weights spanning 1e-6 .. 1e4 across 64-antenna chunks, M = 200 (4 chunks, ragged)
+    say(f"powermap weights over 10 decades, M=200, K=4, {prec}")
+    rng = np.random.default_rng(77)
+    M, K = 200, 4
+    aps = WL.uniform_positions(rng, M, 20, 20, 4.0)
+    pts = WL.uniform_positions(rng, 700, 20, 20, 1.2)
+    mag = 10.0 ** rng.uniform(-6, 4, size=(K, M))
+    W = c64(WL.complex_normal(rng, (K, M)) * mag)
+    _check_map(D, aps, W, D.list_points(dev(pts), 700), pts, 5.8e9, 1e-12, prec, MAP_TOL[prec])
 
 
 def test_powermap_single_point_single_antenna(D):
@@ -378,19 +396,23 @@ def test_powermap_single_point_single_antenna(D):
     assert host(r.power)[0] == pytest.approx(5.1624e-6, rel=1e-4)
 
 
-def test_powermap_hall_sampled(D):
-    # the full-size hall map (N = 2048^2, M = 1024, K = 32) in the launch the
-    # benchmark times, checked on sampled rows
-    say("powermap hall full 2048x2048, K=32, M=1024, FP32, sampled rows")
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
+def test_powermap_hall_sampled(D, prec):
+    # the full-size hall map (N = 2048^2, M = 1024, K = 32) in one launch,
+    # checked on sampled rows
+    say(f"powermap hall full 2048x2048, K=32, M=1024, {prec}, sampled rows")
     w = WL.hall_workload()
     aps = w.ap_xyz[0]
     Hu = c64(O.los_channel(w.user_xyz[0], aps, w.freq_hz)).astype(np.complex128)
     W = c64(O.zf_precoder(Hu, None, w.sigma2, 1.0)[0])
     r = D.powermap(D.channel_params(w.freq_hz), dev(aps), dev(W), D.grid_points(w.grid),
-                   w.sigma2, "f32", want_best=False)
+                   w.sigma2, prec)
     power = host(r.power).reshape(2048, 2048)
+    sinr = host(r.sinr).reshape(2048, 2048)
     rows = [0, 1023, 2047]
     pts = grid_pts(w.grid).reshape(2048, 2048, 3)[rows].reshape(-1, 3)
     Hg = O.los_channel(pts, aps, w.freq_hz)
-    check_db(power[rows].ravel(), O.power_map(Hg, W.astype(np.complex128)), 0.01,
-             what="power rows")
+    Wc = W.astype(np.complex128)
+    check_db(power[rows].ravel(), O.power_map(Hg, Wc), MAP_TOL[prec], what="power rows")
+    s_ref, _ = O.sinr_map(Hg, Wc, w.sigma2)
+    check_db(sinr[rows].ravel(), s_ref, MAP_TOL[prec], what="sinr rows")
