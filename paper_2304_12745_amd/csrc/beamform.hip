@@ -1,16 +1,23 @@
-// Precoders and their epilogues, one workgroup per deployment.
+// Precoders and their epilogues, one 256-thread workgroup per deployment.
 //
 // ZF (eq. optim1 constraint H W^T = sigma D_gamma^{1/2}, or total-power
-// scaling), after the Gram kernel has written G = H H^H to the workspace:
+// scaling) runs after the Gram kernel has written G = H H^H to the workspace:
 //   1. G -> FP64 in LDS, Cholesky G = L L^H (left-looking, one column per
 //      step).  A pivot below tol * G_jj sets info = j+1.
-//   2. L^-1 by forward substitution, one column per thread; tr(G^-1) = ||L^-1||_F^2.
+//   2. L^-1 by forward substitution, one column per thread.
+//      tr(G^-1) = ||L^-1||_F^2.
 //   3. G^-1 = L^-H L^-1 (FP64, K x K in LDS).
-//   4. Column pass, one antenna per thread: x = G^-1 h_m, w_m = c * conj(x),
-//      p_m = sum_k |w_km|^2 (of the stored W), and a partial sum of sqrt(p_m).
-// MR / equal-gain MR: ||H||_F^2 by block reduction, then the column pass.
-// Epilogue (all precoders): A = H W^T (FP64, one entry per thread, read back
-// from the stored H and W), then SINR_k and the sum rate.
+// MR / equal-gain MR: ||H||_F^2 by block reduction.
+// Then, for every tile of 64 antennas:
+//   4. H tile -> LDS.  Four threads per antenna form x = G^-1 h_m (ZF) or the
+//      MR weights, write w_m = c conj(x) to HBM and to LDS, and reduce
+//      p_m = sum_k |w_km|^2 of the stored W.
+//   5. The K x K gains A = H W^T accumulate in FP64 from the two LDS tiles.
+//      Four adjacent threads share an entry, each taking every fourth antenna,
+//      and combine their partial sums after the last tile.
+// Epilogue: SINR_k from A, sum rate, sum_m sqrt(p_m).
+// Every read of H and W after the first comes from LDS, so a deployment reads
+// H once and writes W once.
 #include <cmath>
 
 #include "kernels.h"
@@ -18,6 +25,9 @@
 namespace dmimo {
 
 namespace {
+
+constexpr int kCols = 64;   // antennas per tile
+constexpr int kThreads = 256;
 
 struct BfDev {
     int precoder;
@@ -38,20 +48,18 @@ struct BfDev {
 };
 
 template <typename T2>
-__device__ __forceinline__ double2 ld2(const T2* p, int64_t i) {
-    const T2 v = p[i];
+__device__ __forceinline__ double2 to_d2(T2 v) {
     return make_double2((double)v.x, (double)v.y);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
-    // 256 threads = 4 waves
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wv] = v;
     __syncthreads();
     double t = 0.0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    for (int i = 0; i < kThreads / 64; ++i) t += red[i];
     return t;
 }
 
@@ -64,15 +72,33 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
 __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
 
 template <typename T2, int KT>
-__global__ __launch_bounds__(256) void beamform_kernel(BfDev a) {
-    __shared__ double2 sL[KT][KT + 1];     // Cholesky factor, later A = H W^T
-    __shared__ double2 sI[KT][KT + 1];     // L^-1
-    __shared__ double2 sG[KT][KT + 1];     // G^-1
-    __shared__ double red[8];
-    __shared__ int s_fail;
-    __shared__ double s_scale[KT];
+struct BfShared {
+    double2 ginv[KT][KT + 1];                 // G^-1 (ZF)
+    union {
+        struct {
+            double2 L[KT][KT + 1];            // Cholesky factor
+            double2 Li[KT][KT + 1];           // L^-1
+        } f;
+        struct {
+            T2 h[KT][kCols + 1];              // H tile
+            T2 w[KT][kCols + 1];              // W tile (stored precision)
+        } t;
+        double2 A[KT][KT + 1];                // gains, after the tiles
+    } u;
+    double red[kThreads / 64];
+    double scale[KT];
+    int fail;
+};
+
+template <typename T2, int KT>
+__global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
+    __shared__ BfShared<T2, KT> S;
 
     const int64_t b = blockIdx.x;
     const int K = a.K;
@@ -81,174 +107,198 @@ __global__ __launch_bounds__(256) void beamform_kernel(BfDev a) {
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
     T2* Wb = reinterpret_cast<T2*>(a.W) + b * K * M;
 
-    if (tid == 0) s_fail = 0;
+    if (tid == 0) S.fail = 0;
 
     if (a.precoder == DMIMO_ZF) {
         const T2* Gb = reinterpret_cast<const T2*>(a.G) + b * K * K;
-        for (int e = tid; e < K * K; e += blockDim.x) {
+        for (int e = tid; e < K * K; e += kThreads) {
             const int i = e / K, j = e - (e / K) * K;
-            sG[i][j] = ld2(Gb, e);   // G kept intact in sG for the pivot test
-            sL[i][j] = make_double2(0.0, 0.0);
-            sI[i][j] = make_double2(0.0, 0.0);
+            S.ginv[i][j] = to_d2(Gb[e]);   // G, kept intact for the pivot test
+            S.u.f.L[i][j] = make_double2(0.0, 0.0);
+            S.u.f.Li[i][j] = make_double2(0.0, 0.0);
         }
         __syncthreads();
-        // 1. Cholesky, left-looking: column j uses columns < j.
+        // 1. Cholesky, left-looking
         for (int j = 0; j < K; ++j) {
             if (tid == 0) {
-                double d = sG[j][j].x;
-                for (int p = 0; p < j; ++p) d -= sL[j][p].x * sL[j][p].x + sL[j][p].y * sL[j][p].y;
-                if (!(d > a.pivot_tol * sG[j][j].x)) {
-                    s_fail = j + 1;
+                double d = S.ginv[j][j].x;
+                for (int p = 0; p < j; ++p) d -= S.u.f.L[j][p].x * S.u.f.L[j][p].x + S.u.f.L[j][p].y * S.u.f.L[j][p].y;
+                if (!(d > a.pivot_tol * S.ginv[j][j].x)) {
+                    S.fail = j + 1;
                     d = 1.0;
                 }
-                sL[j][j] = make_double2(sqrt(d), 0.0);
+                S.u.f.L[j][j] = make_double2(sqrt(d), 0.0);
             }
             __syncthreads();
-            if (s_fail) break;
+            if (S.fail) break;
             const int i = j + 1 + tid;
             if (i < K) {
-                double2 s = sG[i][j];
+                double2 s = S.ginv[i][j];
                 for (int p = 0; p < j; ++p) {
-                    const double2 t = cmulc(sL[i][p], sL[j][p]);
+                    const double2 t = cmulc(S.u.f.L[i][p], S.u.f.L[j][p]);
                     s.x -= t.x;
                     s.y -= t.y;
                 }
-                const double inv = 1.0 / sL[j][j].x;
-                sL[i][j] = make_double2(s.x * inv, s.y * inv);
+                const double inv = 1.0 / S.u.f.L[j][j].x;
+                S.u.f.L[i][j] = make_double2(s.x * inv, s.y * inv);
             }
             __syncthreads();
         }
-        if (s_fail) {
-            // zero outputs of this deployment
-            for (int64_t e = tid; e < (int64_t)K * M; e += blockDim.x) {
+        if (S.fail) {
+            for (int64_t e = tid; e < (int64_t)K * M; e += kThreads) {
                 T2 z;
                 z.x = 0;
                 z.y = 0;
                 Wb[e] = z;
             }
             if (a.p_ant)
-                for (int64_t m = tid; m < M; m += blockDim.x) a.p_ant[b * M + m] = 0.0;
+                for (int64_t m = tid; m < M; m += kThreads) a.p_ant[b * M + m] = 0.0;
             if (a.sinr)
-                for (int k = tid; k < K; k += blockDim.x) a.sinr[b * K + k] = 0.0;
+                for (int k = tid; k < K; k += kThreads) a.sinr[b * K + k] = 0.0;
             if (tid == 0) {
                 if (a.l21) a.l21[b] = 0.0;
                 if (a.rsum) a.rsum[b] = 0.0;
-                if (a.info) a.info[b] = s_fail;
+                if (a.info) a.info[b] = S.fail;
             }
             return;
         }
-        // 2. L^-1: thread c solves L x = e_c (x_i = 0 for i < c).
+        // 2. L^-1: thread c solves L x = e_c
         if (tid < K) {
             const int c = tid;
             for (int i = c; i < K; ++i) {
                 double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
                 for (int p = c; p < i; ++p) {
-                    const double2 t = cmul(sL[i][p], sI[p][c]);
+                    const double2 t = cmul(S.u.f.L[i][p], S.u.f.Li[p][c]);
                     s.x -= t.x;
                     s.y -= t.y;
                 }
-                const double inv = 1.0 / sL[i][i].x;
-                sI[i][c] = make_double2(s.x * inv, s.y * inv);
+                const double inv = 1.0 / S.u.f.L[i][i].x;
+                S.u.f.Li[i][c] = make_double2(s.x * inv, s.y * inv);
             }
         }
         __syncthreads();
         double tr = 0.0;
-        for (int e = tid; e < K * K; e += blockDim.x) {
-            const double2 v = sI[e / K][e % K];
+        for (int e = tid; e < K * K; e += kThreads) {
+            const double2 v = S.u.f.Li[e / K][e % K];
             tr += v.x * v.x + v.y * v.y;
         }
-        tr = block_sum(tr, red);   // tr(G^-1) = ||L^-1||_F^2
-        // 3. G^-1 = L^-H L^-1: (G^-1)_ij = sum_{p >= max(i,j)} conj(Li_pi) Li_pj
-        for (int e = tid; e < K * K; e += blockDim.x) {
+        tr = block_sum(tr, S.red);   // tr(G^-1) = ||L^-1||_F^2
+        // 3. G^-1 = L^-H L^-1
+        for (int e = tid; e < K * K; e += kThreads) {
             const int i = e / K, j = e - (e / K) * K;
             double2 s = make_double2(0.0, 0.0);
             for (int p = (i > j ? i : j); p < K; ++p) {
-                const double2 t = cconjmul(sI[p][i], sI[p][j]);
+                const double2 t = cconjmul(S.u.f.Li[p][i], S.u.f.Li[p][j]);
                 s.x += t.x;
                 s.y += t.y;
             }
-            sG[i][j] = s;
+            S.ginv[i][j] = s;
         }
-        if (tid < K) {
-            s_scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total / tr)
-                                           : sqrt(a.sigma2) * sqrt(a.gamma[tid]);
-        }
+        if (tid < K)
+            S.scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total / tr) : sqrt(a.sigma2) * sqrt(a.gamma[tid]);
         __syncthreads();
     } else {
         double f = 0.0;
-        for (int64_t e = tid; e < (int64_t)K * M; e += blockDim.x) {
-            const double2 h = ld2(Hb, e);
+        for (int64_t e = tid; e < (int64_t)K * M; e += kThreads) {
+            const double2 h = to_d2(Hb[e]);
             f += h.x * h.x + h.y * h.y;
         }
-        f = block_sum(f, red);
+        f = block_sum(f, S.red);
         if (tid < K) {
             if (a.precoder == DMIMO_MR)
-                s_scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total) / sqrt(f) : 1.0;
+                S.scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total) / sqrt(f) : 1.0;
             else
-                s_scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total / ((double)K * (double)M)) : 1.0;
+                S.scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total / ((double)K * (double)M)) : 1.0;
         }
         __syncthreads();
     }
 
-    // 4. column pass
+    // 4-5. tiles of kCols antennas
+    // column pass: thread -> (column c = tid / 4, row group g = tid % 4, rows g, g+4, ...)
+    const int cc = tid >> 2;
+    const int rg = tid & 3;
+    // gains: entries e = tid / 4 + 64 q, antennas c = tid % 4 (mod 4)
+    constexpr int QE = (KT * KT + 63) / 64;
+    double2 acc[QE];
+#pragma unroll
+    for (int q = 0; q < QE; ++q) acc[q] = make_double2(0.0, 0.0);
     double l21 = 0.0;
-    for (int64_t m = tid; m < M; m += blockDim.x) {
-        double2 hv[KT];
-#pragma unroll
-        for (int k = 0; k < KT; ++k)
-            hv[k] = k < K ? ld2(Hb, (int64_t)k * M + m) : make_double2(0.0, 0.0);
-        double pm = 0.0;
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            if (k >= K) break;
-            double2 w;
-            if (a.precoder == DMIMO_ZF) {
-                double2 x = make_double2(0.0, 0.0);
-#pragma unroll
-                for (int j = 0; j < KT; ++j) {
-                    if (j >= K) break;
-                    const double2 t = cmul(sG[k][j], hv[j]);
-                    x.x += t.x;
-                    x.y += t.y;
-                }
-                w = make_double2(s_scale[k] * x.x, -s_scale[k] * x.y);
-            } else if (a.precoder == DMIMO_MR) {
-                w = make_double2(s_scale[k] * hv[k].x, -s_scale[k] * hv[k].y);
-            } else {
-                const double mag = sqrt(hv[k].x * hv[k].x + hv[k].y * hv[k].y);
-                w = mag > 0.0 ? make_double2(s_scale[k] * hv[k].x / mag, -s_scale[k] * hv[k].y / mag)
-                              : make_double2(s_scale[k], 0.0);
-            }
-            T2 ws;
-            ws.x = w.x;
-            ws.y = w.y;
-            Wb[(int64_t)k * M + m] = ws;
-            const double wr = (double)ws.x, wi = (double)ws.y;
-            pm += wr * wr + wi * wi;
+    const bool want_gain = a.sinr || a.rsum;
+
+    for (int64_t m0 = 0; m0 < M; m0 += kCols) {
+        const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
+        __syncthreads();
+        for (int e = tid; e < K * kCols; e += kThreads) {
+            const int k = e / kCols, c = e - k * kCols;
+            if (c < mc) S.u.t.h[k][c] = Hb[(int64_t)k * M + m0 + c];
         }
-        if (a.p_ant) a.p_ant[b * M + m] = pm;
-        l21 += sqrt(pm);
+        __syncthreads();
+        if (cc < mc) {
+            const int64_t m = m0 + cc;
+            double pm = 0.0;
+            for (int k = rg; k < K; k += 4) {
+                double2 w;
+                if (a.precoder == DMIMO_ZF) {
+                    double2 x = make_double2(0.0, 0.0);
+#pragma unroll 8
+                    for (int j = 0; j < KT; ++j) {
+                        if (j >= K) break;
+                        cfma(x, S.ginv[k][j], to_d2(S.u.t.h[j][cc]));
+                    }
+                    w = make_double2(S.scale[k] * x.x, -S.scale[k] * x.y);
+                } else {
+                    const double2 h = to_d2(S.u.t.h[k][cc]);
+                    if (a.precoder == DMIMO_MR) {
+                        w = make_double2(S.scale[k] * h.x, -S.scale[k] * h.y);
+                    } else {
+                        const double mag = sqrt(h.x * h.x + h.y * h.y);
+                        w = mag > 0.0 ? make_double2(S.scale[k] * h.x / mag, -S.scale[k] * h.y / mag)
+                                      : make_double2(S.scale[k], 0.0);
+                    }
+                }
+                T2 ws;
+                ws.x = w.x;
+                ws.y = w.y;
+                Wb[(int64_t)k * M + m] = ws;
+                S.u.t.w[k][cc] = ws;
+                pm += (double)ws.x * (double)ws.x + (double)ws.y * (double)ws.y;
+            }
+            // the four threads of a column are adjacent lanes
+            pm += __shfl_xor(pm, 1, 64);
+            pm += __shfl_xor(pm, 2, 64);
+            if (rg == 0) {
+                if (a.p_ant) a.p_ant[b * M + m] = pm;
+                l21 += sqrt(pm);
+            }
+        }
+        if (!want_gain) continue;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QE; ++q) {
+            const int e = cc + 64 * q;
+            if (e >= K * K) break;
+            const int k = e / K, j = e - (e / K) * K;
+            double2 s = acc[q];
+            for (int c = rg; c < mc; c += 4) cfma(s, to_d2(S.u.t.h[k][c]), to_d2(S.u.t.w[j][c]));
+            acc[q] = s;
+        }
     }
-    l21 = block_sum(l21, red);
+    l21 = block_sum(l21, S.red);
     if (tid == 0) {
         if (a.l21) a.l21[b] = l21;
         if (a.info) a.info[b] = 0;
     }
-    if (!a.sinr && !a.rsum) return;
-
-    // make this block's W stores visible to its own later loads
-    __threadfence_block();
+    if (!want_gain) return;
     __syncthreads();
-    // 5. A = H W^T, one entry (k, j) per thread
-    for (int e = tid; e < K * K; e += blockDim.x) {
-        const int k = e / K, j = e - (e / K) * K;
-        double2 s = make_double2(0.0, 0.0);
-        for (int64_t m = 0; m < M; ++m) {
-            const double2 t = cmul(ld2(Hb, (int64_t)k * M + m), ld2((const T2*)Wb, (int64_t)j * M + m));
-            s.x += t.x;
-            s.y += t.y;
-        }
-        sL[k][j] = s;
+#pragma unroll
+    for (int q = 0; q < QE; ++q) {
+        const int e = cc + 64 * q;
+        double2 v = acc[q];
+        v.x += __shfl_xor(v.x, 1, 64);
+        v.y += __shfl_xor(v.y, 1, 64);
+        v.x += __shfl_xor(v.x, 2, 64);
+        v.y += __shfl_xor(v.y, 2, 64);
+        if (e < K * K && rg == 0) S.u.A[e / K][e % K] = v;
     }
     __syncthreads();
     double rate = 0.0;
@@ -256,7 +306,8 @@ __global__ __launch_bounds__(256) void beamform_kernel(BfDev a) {
         const int k = tid;
         double sig = 0.0, intf = 0.0;
         for (int j = 0; j < K; ++j) {
-            const double p = sL[k][j].x * sL[k][j].x + sL[k][j].y * sL[k][j].y;
+            const double2 v = S.u.A[k][j];
+            const double p = v.x * v.x + v.y * v.y;
             if (j == k) sig = p;
             else intf += p;
         }
@@ -264,13 +315,13 @@ __global__ __launch_bounds__(256) void beamform_kernel(BfDev a) {
         if (a.sinr) a.sinr[b * K + k] = snr;
         rate = log2(1.0 + snr);
     }
-    rate = block_sum(rate, red);
+    rate = block_sum(rate, S.red);
     if (tid == 0 && a.rsum) a.rsum[b] = rate;
 }
 
 template <typename T2>
 dmimo_status launch_typed(const BfDev& d, int64_t B, hipStream_t s) {
-    dim3 grid((unsigned)B), block(256);
+    dim3 grid((unsigned)B), block(kThreads);
     if (d.K <= 8) beamform_kernel<T2, 8><<<grid, block, 0, s>>>(d);
     else if (d.K <= 16) beamform_kernel<T2, 16><<<grid, block, 0, s>>>(d);
     else beamform_kernel<T2, 32><<<grid, block, 0, s>>>(d);

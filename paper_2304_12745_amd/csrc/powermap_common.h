@@ -101,10 +101,10 @@ constexpr int ep_stride() {
     return NT == 1 ? 17 : (NT == 2 ? 17 : 33);
 }
 
-// LDS bytes of the epilogue buffer of a 4-wave workgroup.
-template <int NT, int PT>
+// LDS bytes of the epilogue buffer of a workgroup of WAVES wavefronts.
+template <int NT, int PT, int WAVES>
 constexpr int ep_bytes() {
-    return 4 * 16 * PT * ep_stride<NT>() * 4;
+    return WAVES * 16 * PT * ep_stride<NT>() * 4;
 }
 
 // Epilogue of all PT x NT accumulator tiles of a wave.

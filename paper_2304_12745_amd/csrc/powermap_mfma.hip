@@ -43,11 +43,12 @@ constexpr int kChunk = 64;   // antennas per LDS stage
 // FP32 MFMA
 // ---------------------------------------------------------------------------
 
-template <int NT, int PT>
-__global__ __launch_bounds__(256) void powermap_mfma_kernel(PmMapDev a) {
+template <int NT, int PT, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void powermap_mfma_kernel(PmMapDev a) {
+    constexpr int NTH = 64 * WAVES;
     constexpr int BS = NT * 32 + 16;   // floats per antenna row (padded: disjoint banks per group)
     constexpr int TB = kChunk * 3 * 8 + kChunk * BS * 4;
-    constexpr int LB = TB > ep_bytes<NT, PT>() ? TB : ep_bytes<NT, PT>();
+    constexpr int LB = TB > ep_bytes<NT, PT, WAVES>() ? TB : ep_bytes<NT, PT, WAVES>();
     __shared__ __attribute__((aligned(16))) char smem[LB];
     double* s_ap = reinterpret_cast<double*>(smem);
     float* s_b = reinterpret_cast<float*>(smem + kChunk * 3 * 8);
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void powermap_mfma_kernel(PmMapDev a) {
     const int64_t N = a.P.n;
     const int M = a.M;
     const int K = a.K;
-    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * PT);
+    const int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * (16 * PT);
 
     double px[PT], py[PT], pz[PT];
 #pragma unroll
@@ -79,11 +80,11 @@ __global__ __launch_bounds__(256) void powermap_mfma_kernel(PmMapDev a) {
     for (int m0 = 0; m0 < M; m0 += kChunk) {
         const int mc = min(kChunk, M - m0);
         __syncthreads();
-        for (int e = tid; e < kChunk * 3; e += 256) {
+        for (int e = tid; e < kChunk * 3; e += NTH) {
             const int mm = e / 3;
             s_ap[e] = mm < mc ? a.ap[(int64_t)(m0 + mm) * 3 + (e - 3 * mm)] * a.inv_lam : 0.0;
         }
-        for (int e = tid; e < kChunk * NT * 16; e += 256) {
+        for (int e = tid; e < kChunk * NT * 16; e += NTH) {
             const int mm = e / (NT * 16);
             const int r = e - mm * (NT * 16);
             const int q = r >> 4;
@@ -187,8 +188,9 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
 
 constexpr float kHScale = 16384.0f;   // 2^14: FP16 range placement of h (|h| <= 1)
 
-template <int NT, int PT, bool BF16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void powermap_x3_kernel(PmMapDev a) {
+template <int NT, int PT, bool BF16, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4))) void powermap_x3_kernel(PmMapDev a) {
+    constexpr int NTH = 64 * WAVES;
     // LDS: the B tables of the two 32-antenna steps of a chunk,
     // [step][tile][B1hi, B1lo, B2hi, B2lo][lane] x 16 B, and the antenna
     // positions (wavelengths, SoA).  The epilogue reuses the same bytes.
@@ -196,9 +198,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         u32x4 b[2][NT][4][64];
         double x[kChunk], y[kChunk], z[kChunk];
     };
-    constexpr int LB = sizeof(Tables) > (size_t)ep_bytes<NT, PT>() ? sizeof(Tables) : ep_bytes<NT, PT>();
+    constexpr int LB = sizeof(Tables) > (size_t)ep_bytes<NT, PT, WAVES>() ? sizeof(Tables)
+                                                                          : ep_bytes<NT, PT, WAVES>();
     __shared__ __attribute__((aligned(16))) char smem[LB];
-    __shared__ float s_red[4];
+    __shared__ float s_red[WAVES];
     Tables& T = *reinterpret_cast<Tables*>(smem);
 
     const int tid = threadIdx.x;
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     const int64_t N = a.P.n;
     const int M = a.M;
     const int K = a.K;
-    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * PT);
+    const int64_t base = ((int64_t)blockIdx.x * WAVES + wave) * (16 * PT);
     const float hscale = BF16 ? 1.0f : kHScale;
     const float amp_s = a.amp_rev * hscale;
 
@@ -236,11 +239,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     for (int m0 = 0; m0 < M; m0 += kChunk) {
         const int mc = min(kChunk, M - m0);
         __syncthreads();
-        float2 wv[(kItems + 255) / 256][8];
+        constexpr int kPer = (kItems + NTH - 1) / NTH;
+        float2 wv[kPer][8];
         float mx = 0.0f;
 #pragma unroll
-        for (int it = 0; it < (kItems + 255) / 256; ++it) {
-            const int e = tid + 256 * it;
+        for (int it = 0; it < kPer; ++it) {
+            const int e = tid + NTH * it;
             const int s = e / (NT * 64);
             const int q = (e - s * NT * 64) >> 6;
             const int l = e & 63;
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
                 mx = fmaxf(mx, fmaxf(fabsf(w.x), fabsf(w.y)));
             }
         }
-        for (int e = tid; e < kChunk; e += 256) {
+        for (int e = tid; e < kChunk; e += NTH) {
             const bool live = e < mc;
             T.x[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 0] * a.inv_lam : 0.0;
             T.y[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 1] * a.inv_lam : 0.0;
@@ -267,7 +271,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_down(mx, off, 64));
             if (lane == 0) s_red[wave] = mx;
             __syncthreads();
-            mx = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+            mx = s_red[0];
+#pragma unroll
+            for (int i = 1; i < WAVES; ++i) mx = fmaxf(mx, s_red[i]);
             const int ne = mx > 0.0f ? 14 - (ilogbf(mx) + 1) : wexp;
             if (m0 > 0 && ne != wexp) {
                 const float f = ldexpf(1.0f, ne - wexp);
@@ -280,8 +286,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
             wscale = ldexpf(1.0f, wexp);
         }
 #pragma unroll
-        for (int it = 0; it < (kItems + 255) / 256; ++it) {
-            const int e = tid + 256 * it;
+        for (int it = 0; it < kPer; ++it) {
+            const int e = tid + NTH * it;
             if (e >= kItems) break;
             const int s = e / (NT * 64);
             const int q = (e - s * NT * 64) >> 6;
@@ -352,9 +358,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
                          reinterpret_cast<float*>(smem) + wave * 16 * PT * ep_stride<NT>());
 }
 
+#ifndef DMIMO_PM_WAVES
+#define DMIMO_PM_WAVES 8   // wavefronts per workgroup of the map kernels (measured best of 4, 8, 16)
+#endif
+constexpr int kWaves = DMIMO_PM_WAVES;
+
 template <int PT, typename F>
 dmimo_status launch_blocks(const PmMapDev& d, F&& launch) {
-    const int64_t blocks = ceil_div(d.P.n, 4 * 16 * PT);
+    const int64_t blocks = ceil_div(d.P.n, kWaves * 16 * PT);
     if (blocks > 0x7fffffff) return fail(DMIMO_E_SHAPE, "powermap: too many points");
     launch(dim3((unsigned)blocks));
     return check_launch("powermap_mfma");
@@ -363,7 +374,8 @@ dmimo_status launch_blocks(const PmMapDev& d, F&& launch) {
 template <int NT>
 dmimo_status launch_f32(const PmMapDev& d, hipStream_t s) {
     constexpr int PT = 2;
-    return launch_blocks<PT>(d, [&](dim3 g) { powermap_mfma_kernel<NT, PT><<<g, 256, 0, s>>>(d); });
+    return launch_blocks<PT>(
+        d, [&](dim3 g) { powermap_mfma_kernel<NT, PT, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
 }
 
 template <int NT, bool BF16>
@@ -371,7 +383,8 @@ dmimo_status launch_x3(const PmMapDev& d, hipStream_t s) {
     // one 16-point tile per wave for K > 8 keeps the kernel within 128 VGPRs
     // (4 waves per SIMD) without spills
     constexpr int PT = NT == 1 ? 2 : 1;
-    return launch_blocks<PT>(d, [&](dim3 g) { powermap_x3_kernel<NT, PT, BF16><<<g, 256, 0, s>>>(d); });
+    return launch_blocks<PT>(
+        d, [&](dim3 g) { powermap_x3_kernel<NT, PT, BF16, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
 }
 
 }  // namespace

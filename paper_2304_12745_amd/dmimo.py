@@ -192,31 +192,51 @@ class BeamformResult:
     info: object
 
 
-def beamform(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f32",
-             outputs=True, ws=None, stream=None) -> BeamformResult:
-    """Precoder + epilogues (dmimo_beamform).  H: complex [B][K][M] on the GPU."""
+def beamform_outputs(B: int, K: int, M: int, prec="f32", device=None, outputs=True,
+                     precoder="zf") -> BeamformResult:
+    """Allocate the outputs of beamform() once, for reuse through ``out=``.
+
+    The workspace of a ZF call (``ws``) is allocated here too.
+    """
     import torch
+    prec = _prec(prec)
+    W = torch.empty((B, K, M), dtype=_cdtype(prec), device=device)
+    r = BeamformResult(
+        W,
+        torch.empty((B, M), dtype=torch.float64, device=device) if outputs else None,
+        torch.empty((B,), dtype=torch.float64, device=device) if outputs else None,
+        torch.empty((B, K), dtype=torch.float64, device=device) if outputs else None,
+        torch.empty((B,), dtype=torch.float64, device=device) if outputs else None,
+        torch.empty((B,), dtype=torch.int32, device=device) if outputs else None)
+    pc = PRECODERS[precoder] if isinstance(precoder, str) else int(precoder)
+    need = workspace_size(CALL_BEAMFORM_ZF if pc == ZF else CALL_BEAMFORM_MR, B, K, M, 0, prec)
+    r.ws = torch.empty((need,), dtype=torch.uint8, device=device) if need else None
+    return r
+
+
+def beamform(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f32",
+             outputs=True, ws=None, stream=None, out: Optional[BeamformResult] = None
+             ) -> BeamformResult:
+    """Precoder + epilogues (dmimo_beamform).  H: complex [B][K][M] on the GPU.
+
+    ``out`` (from beamform_outputs) reuses preallocated outputs and workspace.
+    """
     prec = _prec(prec)
     pc = PRECODERS[precoder] if isinstance(precoder, str) else int(precoder)
     B, K, M = H.shape
-    dev = H.device
-    W = torch.empty((B, K, M), dtype=_cdtype(prec), device=dev)
-    p_ant = torch.empty((B, M), dtype=torch.float64, device=dev) if outputs else None
-    l21 = torch.empty((B,), dtype=torch.float64, device=dev) if outputs else None
-    sinr = torch.empty((B, K), dtype=torch.float64, device=dev) if outputs else None
-    rsum = torch.empty((B,), dtype=torch.float64, device=dev) if outputs else None
-    info = torch.empty((B,), dtype=torch.int32, device=dev) if outputs else None
-    need = workspace_size(CALL_BEAMFORM_ZF if pc == ZF else CALL_BEAMFORM_MR, B, K, M, 0, prec)
-    if need and ws is None:
-        ws = torch.empty((need,), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = beamform_outputs(B, K, M, prec, H.device, outputs, pc)
+    if ws is None:
+        ws = getattr(out, "ws", None)
     g = None
     if gamma_lin is not None:
         g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
     _check(lib().dmimo_beamform(pc, B, K, M, _ptr(H), g, float(sigma2), float(p_total), prec,
-                                _ptr(W), _ptr(p_ant), _ptr(l21), _ptr(sinr), _ptr(rsum),
-                                _ptr(info), _ptr(ws), ws.numel() if ws is not None else 0,
-                                _stream(stream)), "dmimo_beamform")
-    return BeamformResult(W, p_ant, l21, sinr, rsum, info)
+                                _ptr(out.W), _ptr(out.p_ant), _ptr(out.l21), _ptr(out.sinr),
+                                _ptr(out.rsum), _ptr(out.info), _ptr(ws),
+                                ws.numel() if ws is not None else 0, _stream(stream)),
+           "dmimo_beamform")
+    return out
 
 
 @dataclass

@@ -67,6 +67,9 @@ def grid_pts(g):
     return O.grid_points(g.x0, g.y0, g.dx, g.dy, g.z, g.nx, g.ny)
 
 
+MAP_TOL = {"f32": 0.01, "f16x3": 0.1, "bf16x3": 0.1}
+
+
 def check_db(y, ref, tol, floor_rel=1e-6, what=""):
     s = dberror.summary(y, ref, tol, floor_rel)
     say(f"    {what}: max {s['max_db']:.2e} dB  p99 {s['p99_db']:.2e} dB  "
@@ -143,14 +146,19 @@ def test_channel_near_field_clamp(D):
 # dmimo_gram
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("K,M", [(8, 64), (16, 256), (5, 37), (32, 1024), (1, 3)])
+# |dG_kj| / sqrt(G_kk G_jj): FP32 sums; FP16 x3 splits every value to
+# ~2^-22 and drops lo*lo (~2^-22); BF16 x3 splits to ~2^-17.
+GRAM_TOL = {"f64": 1e-12, "f32": 1e-5, "f16x3": 1e-5, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "f16x3", "bf16x3"])
+@pytest.mark.parametrize("K,M", [(8, 64), (16, 256), (5, 37), (32, 1024), (17, 100), (1, 3)])
 def test_gram(D, prec, K, M):
     say(f"gram prec={prec} K={K} M={M}")
     rng = np.random.default_rng(K * 1000 + M)
     B = 7
-    H = WL.complex_normal(rng, (B, K, M))
-    if prec == "f32":
+    H = WL.complex_normal(rng, (B, K, M)) * 10.0 ** rng.uniform(-4, 1)
+    if prec != "f64":
         H = c64(H)
     G = host(D.gram(dev(H), prec=prec))
     ref = O.gram(H.astype(np.complex128))
@@ -158,7 +166,7 @@ def test_gram(D, prec, K, M):
     scale = d[:, :, None] * d[:, None, :]
     e = np.max(np.abs(G - ref) / scale)
     say(f"    max |dG|/sqrt(GkkGjj) = {e:.3e}")
-    assert e <= (1e-5 if prec == "f32" else 1e-12)
+    assert e <= GRAM_TOL[prec]
     # exactly Hermitian, real diagonal
     np.testing.assert_array_equal(G, np.conj(np.swapaxes(G, 1, 2)))
 
@@ -232,12 +240,24 @@ def test_beamform_room_zf_total_power(D):
     assert host(r.p_ant).sum() == pytest.approx(1.0, rel=1e-5)
 
 
-def test_beamform_batched_rician_zf(D):
-    say("beamform ZF batched Rician (K=16, M=256)")
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
+def test_beamform_batched_rician_zf(D, prec):
+    # ZF via the mixed Gram: SINR within 0.01 dB (FP32) / 0.1 dB (mixed), FP64 Cholesky
+    say(f"beamform ZF batched Rician (K=16, M=256), Gram {prec}")
     w = WL.batched_workload(B=16)
     Hc = np.stack([O.rician_channel(w.user_xyz[b], w.ap_xyz[b], w.freq_hz, w.kappa_lin,
                                     w.nlos[b].astype(np.complex128)) for b in range(16)])
-    _check_beamform(D, c64(Hc), "zf", None, w.sigma2, 1.0, "f32", 0.01, 1e-4)
+    _check_beamform(D, c64(Hc), "zf", None, w.sigma2, 1.0, prec, MAP_TOL[prec],
+                    1e-4 if prec != "bf16x3" else 1e-2)
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+def test_beamform_paper_zf_mixed(D, prec):
+    say(f"beamform ZF, paper setting, Gram {prec}")
+    w = WL.paper_workload(seed=0, B=256)
+    r = _check_beamform(D, c64(w.H), "zf", w.gamma_lin, 1.0, 0.0, prec, MAP_TOL[prec],
+                        1e-4 if prec != "bf16x3" else 1e-2)
+    assert np.all(np.abs(host(r.rsum) - 27.68) < 0.005)
 
 
 @pytest.mark.parametrize("K,M", [(1, 1), (3, 3), (5, 37), (32, 64), (17, 300)])
@@ -320,9 +340,6 @@ def test_powermap_focus_f32(D):
     W = c64(O.mr_precoder(O.los_channel(w.focal_xyz, aps, w.freq_hz), 1.0))
     _check_map(D, aps, W, D.grid_points(w.grid), grid_pts(w.grid), w.freq_hz, w.sigma2,
                "f32", 0.01)
-
-
-MAP_TOL = {"f32": 0.01, "f16x3": 0.1, "bf16x3": 0.1}
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
