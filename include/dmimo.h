@@ -169,6 +169,67 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M,
                             void* power, void* sinr, int32_t* best_k, void* per_stream,
                             void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of power-map queries on one GPU.
+ *
+ * A server owns one HIP stream, one worker thread and one device arena of
+ * hbm_budget_bytes, allocated at creation; nothing is allocated afterwards.
+ * Deployments (antenna positions) are uploaded once and stay resident.
+ * Each query:
+ *   - names a deployment and brings K user positions (host), a precoder
+ *     (MR / ZF / equal-gain MR at p_total, with the same scaling rules as
+ *     dmimo_beamform, gamma = 1), the evaluation points and caller-owned
+ *     device outputs power[N] and sinr[N] (FP32; sinr may be NULL);
+ *   - is admitted when a slot is free and its footprint fits the budget.
+ *     The footprint is the server scratch for H, W and the Gram plus the
+ *     4 or 8 bytes per point of its maps.
+ * The worker then computes the user channel and the precoder, and evaluates
+ * the maps in persistent launches.  Each launch loops over tiles of every
+ * active query, smallest remaining work first, so queries that arrive while
+ * others run share the device from the next launch on.  A query's maps are
+ * bitwise identical whether it runs alone or among others.
+ * Times are seconds of CLOCK_MONOTONIC.  The output buffers must stay valid
+ * until the query is done.
+ * -------------------------------------------------------------------------*/
+typedef struct dmimo_server dmimo_server;
+
+enum { DMIMO_Q_QUEUED = 0, DMIMO_Q_RUNNING = 1, DMIMO_Q_DONE = 2, DMIMO_Q_FAILED = 3 };
+
+/* Create a server on `device` with an arena of hbm_budget_bytes (>= 1 MiB)
+ * and at most max_inflight (1..4096) admitted queries. */
+dmimo_status dmimo_server_create(int32_t device, size_t hbm_budget_bytes, int32_t max_inflight,
+                                 dmimo_server** srv);
+/* Upload a deployment: host FP64 [M][3] antenna positions, LoS params.
+ * DMIMO_E_NOMEM if the geometry does not fit the budget. */
+dmimo_status dmimo_server_add_deployment(dmimo_server* srv, const dmimo_channel_params* params,
+                                         int32_t M, const double* ap_xyz_host, int32_t* dep_id);
+/* Queue a power-map query; returns at once with a ticket.
+ *   user_xyz_host  host FP64 [K][3] (copied); 1 <= K <= 32, K <= M for ZF.
+ *   pts            GRID, or LIST of device points that outlive the query.
+ *   prec           DMIMO_F32, DMIMO_MIX_F16X3 or DMIMO_MIX_BF16X3.
+ * DMIMO_E_NOMEM if the query could never fit the budget, DMIMO_E_BUSY if the
+ * pending queue (64 x max_inflight) is full, DMIMO_E_NOTFOUND for an unknown
+ * deployment. */
+dmimo_status dmimo_server_submit(dmimo_server* srv, int32_t dep_id, int32_t K,
+                                 const double* user_xyz_host, int32_t precoder,
+                                 const dmimo_points* pts, double sigma2, double p_total,
+                                 int32_t prec, float* power_out_dev, float* sinr_out_dev,
+                                 uint64_t* ticket);
+/* State (DMIMO_Q_*) and times of a ticket (t_done is 0 until done). */
+dmimo_status dmimo_server_poll(dmimo_server* srv, uint64_t ticket, int32_t* state,
+                               double* t_submit, double* t_done);
+/* Block until the ticket is done or failed, or timeout_s elapses. */
+dmimo_status dmimo_server_wait(dmimo_server* srv, uint64_t ticket, double timeout_s,
+                               int32_t* state);
+/* Forget a finished ticket (DMIMO_E_BUSY if it is not finished). */
+dmimo_status dmimo_server_release(dmimo_server* srv, uint64_t ticket);
+/* Counters: queries completed, channel terms completed, launches issued,
+ * queries queued and running now.  Any pointer may be NULL. */
+dmimo_status dmimo_server_stats(dmimo_server* srv, int64_t* completed, int64_t* terms,
+                                int64_t* ticks, int32_t* queued, int32_t* running);
+/* Finish every submitted query, then free everything. */
+dmimo_status dmimo_server_destroy(dmimo_server* srv);
+
 enum { DMIMO_CALL_CHANNEL = 0, DMIMO_CALL_GRAM = 1, DMIMO_CALL_BEAMFORM_MR = 2,
        DMIMO_CALL_BEAMFORM_ZF = 3, DMIMO_CALL_POWERMAP = 4 };
 

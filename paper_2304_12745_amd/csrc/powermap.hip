@@ -11,6 +11,7 @@
 // The reduction over antennas stays inside one lane in ascending m, so a
 // point's result does not depend on how points are grouped into launches.
 #include "kernels.h"
+#include "powermap_body.h"
 #include "powermap_mfma.h"
 
 namespace dmimo {
@@ -119,6 +120,11 @@ __global__ __launch_bounds__(256) void powermap_valu_kernel(PmDev a) {
     if (live) epilogue<F64, R>(a, n, zr, zi, K);
 }
 
+template <int KT>
+__global__ __launch_bounds__(256) void powermap_valu_f32_kernel(PmMapDev a) {
+    map_valu_wg<KT>(a, (int64_t)blockIdx.x * 256);
+}
+
 template <bool F64>
 dmimo_status launch_valu(const PmDev& d, hipStream_t s) {
     const int64_t blocks = ceil_div(d.P.n, 256);
@@ -151,7 +157,13 @@ dmimo_status launch_powermap(const PowermapArgs& a, hipStream_t s) {
     if (a.prec == DMIMO_F64) return launch_valu<true>(d, s);
     if (a.prec == DMIMO_F32) {
         // one or two streams: four or eight FMA per term stay on the VALU
-        if (a.K <= 2) return launch_valu<false>(d, s);
+        if (a.K <= 2) {
+            const PmMapDev m = make_map_dev(a);
+            dim3 grid((unsigned)ceil_div(a.P.n, 256)), block(256);
+            if (a.K == 1) powermap_valu_f32_kernel<1><<<grid, block, 0, s>>>(m);
+            else powermap_valu_f32_kernel<2><<<grid, block, 0, s>>>(m);
+            return check_launch("powermap_valu_f32_kernel");
+        }
         return launch_powermap_f32_mfma(a, s);
     }
     return launch_powermap_mfma(a, s);

@@ -59,6 +59,19 @@ _SIGS = {
     "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
+    "dmimo_server_create": [_i32, _sz, _i32, ctypes.POINTER(ctypes.c_void_p)],
+    "dmimo_server_add_deployment": [_vp, ctypes.POINTER(ChannelParams), _i32, _vp,
+                                    ctypes.POINTER(_i32)],
+    "dmimo_server_submit": [_vp, _i32, _i32, _vp, _i32, ctypes.POINTER(Points), _f64, _f64, _i32,
+                            _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
+    "dmimo_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
+                          ctypes.POINTER(_f64)],
+    "dmimo_server_wait": [_vp, ctypes.c_uint64, _f64, ctypes.POINTER(_i32)],
+    "dmimo_server_release": [_vp, ctypes.c_uint64],
+    "dmimo_server_stats": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i32),
+                           ctypes.POINTER(_i32)],
+    "dmimo_server_destroy": [_vp],
     "dmimo_status_string": [_i32],
     "dmimo_last_error": [],
     "dmimo_version": [],
@@ -268,6 +281,85 @@ def powermap(params: ChannelParams, ap_xyz, W, points: Points, sigma2=1e-12, pre
                                 _ptr(out.sinr), _ptr(out.best_k), _ptr(out.per_stream),
                                 _stream(stream)), "dmimo_powermap")
     return out
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+Q_QUEUED, Q_RUNNING, Q_DONE, Q_FAILED = 0, 1, 2, 3
+
+
+class Server:
+    """Continuous-batching power-map server (dmimo_server_*).
+
+    Output tensors passed to submit() are kept referenced until the ticket is
+    released, so their device memory outlives the query.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 64, device: int = 0):
+        self._h = ctypes.c_void_p()
+        self._keep = {}
+        _check(lib().dmimo_server_create(int(device), int(hbm_budget_bytes), int(max_inflight),
+                                         ctypes.byref(self._h)), "dmimo_server_create")
+
+    def add_deployment(self, params: ChannelParams, ap_xyz_host) -> int:
+        import numpy as np
+        ap = np.ascontiguousarray(ap_xyz_host, dtype=np.float64)
+        dep = _i32()
+        _check(lib().dmimo_server_add_deployment(self._h, ctypes.byref(params), ap.shape[0],
+                                                 ap.ctypes.data, ctypes.byref(dep)),
+               "dmimo_server_add_deployment")
+        return dep.value
+
+    def submit(self, dep: int, user_xyz_host, precoder, points: Points, sigma2: float,
+               p_total: float, prec, power, sinr=None) -> int:
+        import numpy as np
+        u = np.ascontiguousarray(user_xyz_host, dtype=np.float64)
+        pc = PRECODERS[precoder] if isinstance(precoder, str) else int(precoder)
+        t = ctypes.c_uint64()
+        _check(lib().dmimo_server_submit(self._h, int(dep), u.shape[0], u.ctypes.data, pc,
+                                         ctypes.byref(points), float(sigma2), float(p_total),
+                                         _prec(prec), _ptr(power), _ptr(sinr), ctypes.byref(t)),
+               "dmimo_server_submit")
+        self._keep[t.value] = (power, sinr, points)
+        return t.value
+
+    def poll(self, ticket: int):
+        st, ts, td = _i32(), _f64(), _f64()
+        _check(lib().dmimo_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(st),
+                                       ctypes.byref(ts), ctypes.byref(td)), "dmimo_server_poll")
+        return st.value, ts.value, td.value
+
+    def wait(self, ticket: int, timeout_s: float = 60.0) -> int:
+        st = _i32()
+        _check(lib().dmimo_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s),
+                                       ctypes.byref(st)), "dmimo_server_wait")
+        return st.value
+
+    def release(self, ticket: int):
+        _check(lib().dmimo_server_release(self._h, ctypes.c_uint64(ticket)), "dmimo_server_release")
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        c, tm, tk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        q, r = _i32(), _i32()
+        _check(lib().dmimo_server_stats(self._h, ctypes.byref(c), ctypes.byref(tm), ctypes.byref(tk),
+                                        ctypes.byref(q), ctypes.byref(r)), "dmimo_server_stats")
+        return {"completed": c.value, "terms": tm.value, "launches": tk.value, "queued": q.value,
+                "running": r.value}
+
+    def close(self):
+        if self._h:
+            _check(lib().dmimo_server_destroy(self._h), "dmimo_server_destroy")
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def version() -> str:

@@ -119,3 +119,20 @@ def test_gram_and_channel_validation(lib):
     assert lib.dmimo_channel(ctypes.byref(neg), 1, 4, FAKE, ctypes.byref(pts), FAKE, D.F32, FAKE, None) == 1
     assert lib.dmimo_channel(ctypes.byref(p), 0, 4, None, ctypes.byref(pts), None, D.F32, None, None) == 0
     assert lib.dmimo_channel(None, 1, 4, FAKE, ctypes.byref(pts), None, D.F32, FAKE, None) == 1
+
+
+def test_server_validation(lib):
+    # argument checks of the server calls return before any HIP call
+    srv = ctypes.c_void_p()
+    assert lib.dmimo_server_create(0, 1 << 30, 8, None) == 1
+    assert lib.dmimo_server_create(0, 1000, 8, ctypes.byref(srv)) == 1
+    assert lib.dmimo_server_create(0, 1 << 30, 0, ctypes.byref(srv)) == 1
+    assert lib.dmimo_server_create(-1, 1 << 30, 8, ctypes.byref(srv)) == 1
+    pts = D.Points(D.PTS_GRID, 4, 4, 0, 0, 1, 1, 1, None, 0)
+    t = ctypes.c_uint64()
+    u = (ctypes.c_double * 3)(1, 2, 3)
+    assert lib.dmimo_server_submit(None, 0, 1, u, 0, ctypes.byref(pts), 1e-12, 1.0, D.F32, FAKE,
+                                   None, ctypes.byref(t)) == 1
+    st = ctypes.c_int32()
+    assert lib.dmimo_server_poll(None, 1, ctypes.byref(st), None, None) == 1
+    assert lib.dmimo_server_destroy(None) == 0

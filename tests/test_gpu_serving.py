@@ -1,0 +1,167 @@
+"""GPU tests of the serving runtime (dmimo_server_*).
+
+* A served query matches the FP64 oracle chain: users -> precoder -> map.
+* A served query equals the one-shot calls (channel, beamform, powermap) bitwise.
+* Each query's maps are bitwise the same alone and inside a mix of queries of
+  different M, N, K, precoder and precision (continuous batching).
+* Admission by HBM footprint: everything completes under a small budget, and
+  a query that can never fit is refused with DMIMO_E_NOMEM.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dberror  # noqa: E402
+from oracle import dmimo_oracle as O  # noqa: E402
+from paper_2304_12745_amd import workloads as WL  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 0.01, "f16x3": 0.1, "bf16x3": 0.1}
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2304_12745_amd import dmimo
+    dmimo.lib()
+    return dmimo
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _room(rng, M, f):
+    return WL.uniform_positions(rng, M, 20.0, 20.0, 4.0)
+
+
+def _query_set(seed=5):
+    """Deployments and a mix of query shapes (M, N, K, precoder, precision)."""
+    rng = np.random.default_rng(seed)
+    deps = [(16, 0.92e9), (64, 3.5e9), (256, 5.8e9)]
+    aps = [_room(rng, M, f) for M, f in deps]
+    shapes = [(64, 64), (96, 80), (160, 160), (33, 47)]
+    qs = []
+    for i in range(12):
+        d = i % 3
+        K = (1, 4, 16)[i % 3] if deps[d][0] >= 16 else 1
+        nx, ny = shapes[i % 4]
+        prec = ("f32", "f16x3", "bf16x3")[(i // 3) % 3]
+        pc = "zf" if i % 2 else "mr"
+        users = WL.uniform_positions(rng, K, 20.0, 20.0, 1.2)
+        grid = WL.Grid(0.0, 0.0, 20.0 / nx, 20.0 / ny, 1.2, nx, ny)
+        qs.append(dict(dep=d, K=K, users=users, grid=grid, prec=prec, pc=pc))
+    return deps, aps, qs
+
+
+def _submit(D, srv, dep_ids, q, sigma2=1e-12):
+    N = q["grid"].n
+    power = torch.empty(N, device="cuda")
+    sinr = torch.empty(N, device="cuda")
+    t = srv.submit(dep_ids[q["dep"]], q["users"], q["pc"], D.grid_points(q["grid"]), sigma2, 1.0,
+                   q["prec"], power, sinr)
+    return t, power, sinr
+
+
+def test_served_query_matches_oracle(D):
+    rng = np.random.default_rng(3)
+    M, K, f = 64, 4, 3.5e9
+    aps = _room(rng, M, f)
+    users = WL.uniform_positions(rng, K, 20, 20, 1.2)
+    g = WL.Grid(0.0, 0.0, 20 / 90, 20 / 70, 1.2, 90, 70)      # 6300 points: ragged tiles
+    pts = O.grid_points(g.x0, g.y0, g.dx, g.dy, g.z, g.nx, g.ny)
+    Hu = O.los_channel(users, aps, f)
+    Hg = O.los_channel(pts, aps, f)
+    with D.Server(256 << 20, 8) as srv:
+        dep = srv.add_deployment(D.channel_params(f), aps)
+        for pc in ("mr", "zf"):
+            W = O.mr_precoder(Hu, 1.0) if pc == "mr" else O.zf_precoder(Hu, None, 1e-12, 1.0)[0]
+            y_ref = O.power_map(Hg, W)
+            s_ref, _ = O.sinr_map(Hg, W, 1e-12)
+            for prec in ("f32", "f16x3", "bf16x3"):
+                say(f"served {pc} {prec}")
+                t, power, sinr = _submit(D, srv, [dep], dict(dep=0, K=K, users=users, grid=g,
+                                                             prec=prec, pc=pc))
+                assert srv.wait(t, 60.0) == D.Q_DONE
+                sp = dberror.summary(power.cpu().numpy(), y_ref, TOL[prec])
+                ss = dberror.summary(sinr.cpu().numpy(), s_ref, TOL[prec])
+                say(f"    power max {sp['max_db']:.2e} dB, sinr max {ss['max_db']:.2e} dB")
+                assert sp["n_fail"] == 0 and ss["n_fail"] == 0
+                st, ts, td = srv.poll(t)
+                assert st == D.Q_DONE and td >= ts > 0
+                srv.release(t)
+
+
+def test_served_equals_one_shot_calls(D):
+    deps, aps, qs = _query_set(seed=11)
+    with D.Server(512 << 20, 16) as srv:
+        ids = [srv.add_deployment(D.channel_params(f), a) for (M, f), a in zip(deps, aps)]
+        for q in qs[:6]:
+            M, f = deps[q["dep"]]
+            say(f"one-shot vs served: M={M} K={q['K']} N={q['grid'].n} {q['pc']} {q['prec']}")
+            t, power, sinr = _submit(D, srv, ids, q)
+            assert srv.wait(t, 60.0) == D.Q_DONE
+            p = D.channel_params(f)
+            ap = torch.from_numpy(aps[q["dep"]]).cuda()
+            H = D.channel(p, ap[None].contiguous(), D.list_points(torch.from_numpy(q["users"]).cuda(), q["K"]),
+                          prec="f32")
+            r = D.beamform(H, q["pc"], None, 1e-12, 1.0, q["prec"], outputs=False)
+            m = D.powermap(p, ap, r.W[0], D.grid_points(q["grid"]), 1e-12, q["prec"], want_best=False)
+            torch.cuda.synchronize()
+            assert torch.equal(m.power, power) and torch.equal(m.sinr, sinr)
+            srv.release(t)
+
+
+def test_alone_equals_mix(D):
+    deps, aps, qs = _query_set(seed=7)
+    with D.Server(1 << 30, 32) as srv:
+        ids = [srv.add_deployment(D.channel_params(f), a) for (M, f), a in zip(deps, aps)]
+        alone = []
+        for q in qs:
+            t, power, sinr = _submit(D, srv, ids, q)
+            assert srv.wait(t, 60.0) == D.Q_DONE
+            alone.append((power.cpu().numpy(), sinr.cpu().numpy()))
+            srv.release(t)
+        say(f"alone: {len(alone)} queries done")
+        subs = [_submit(D, srv, ids, q) for q in qs]        # all in flight together
+        for i, (t, power, sinr) in enumerate(subs):
+            assert srv.wait(t, 120.0) == D.Q_DONE
+            np.testing.assert_array_equal(power.cpu().numpy(), alone[i][0])
+            np.testing.assert_array_equal(sinr.cpu().numpy(), alone[i][1])
+            srv.release(t)
+        st = srv.stats()
+        say(f"mix: {st}")
+        assert st["completed"] == 2 * len(qs)
+
+
+def test_admission_by_footprint(D):
+    rng = np.random.default_rng(9)
+    M, f = 64, 3.5e9
+    aps = _room(rng, M, f)
+    g = WL.Grid(0.0, 0.0, 20 / 256, 20 / 256, 1.2, 256, 256)   # outputs 2 x 256 KiB
+    with D.Server(4 << 20, 16) as srv:
+        dep = srv.add_deployment(D.channel_params(f), aps)
+        subs = []
+        for i in range(10):
+            users = WL.uniform_positions(rng, 4, 20, 20, 1.2)
+            subs.append(_submit(D, srv, [dep], dict(dep=0, K=4, users=users, grid=g, prec="f32",
+                                                    pc="zf")))
+        for t, _, _ in subs:
+            assert srv.wait(t, 60.0) == D.Q_DONE
+            srv.release(t)
+        # a query whose maps alone exceed the budget can never be admitted
+        big = WL.Grid(0.0, 0.0, 20 / 1024, 20 / 1024, 1.2, 1024, 1024)
+        with pytest.raises(D.DmimoError) as ei:
+            _submit(D, srv, [dep], dict(dep=0, K=4, users=WL.uniform_positions(rng, 4, 20, 20, 1.2),
+                                        grid=big, prec="f32", pc="mr"))
+        assert ei.value.status == 8
+        with pytest.raises(D.DmimoError) as ei:
+            srv.poll(987654321)
+        assert ei.value.status == 9
+        assert srv.stats()["completed"] == 10
