@@ -96,6 +96,12 @@ def parse_args():
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="budget of the oracle CPU baseline (0 disables it)")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--serve-seconds", type=float, default=5.0,
+                   help="measured window of the serving phase (0 disables it)")
+    p.add_argument("--serve-warmup", type=float, default=1.0)
+    p.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (1/s)")
+    p.add_argument("--serve-prec", default="f32", choices=["f32", "f16x3", "bf16x3"])
+    p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
     return p.parse_args()
 
 
@@ -164,6 +170,10 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     kernel_ms_total = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in events)
 
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_step(args, w, D, params, ap, ap0, upts, gpts, H, maps, ms_per_step)
+
     terms_per_step = 3 * K * M + 2 * N * M
     value = terms_per_step / (ms_per_step * 1e-3) / 1e9
     map_launch_ms = kernel_ms_total / (2 * args.steps)
@@ -211,10 +221,143 @@ def main():
         },
     }
 
+    if mixed is not None:
+        mixed["value"] = round(terms_per_step / (mixed["ms_per_step"] * 1e-3) / 1e9, 3)
+        out["mixed"] = mixed
+    if args.serve_seconds > 0:
+        out["serving"] = serving_phase(args, D, WL, torch)
     if not args.no_cpu and args.cpu_seconds > 0:
         out["cpu_baseline"], out["err_db"] = cpu_baseline(w, bf, maps, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+def mixed_step(args, w, D, params, ap, ap0, upts, gpts, H, maps_f32, f32_ms):
+    """The same step with the FP16 x3 split-precision Gram and maps (FP32
+    accumulation; FP64 distance / phase and Cholesky as before)."""
+    import torch
+    K, M, N = w.K, w.M, w.grid.n
+    dev = H.device
+    prec = "f16x3"
+    maps = {p: D.MapResult(torch.empty(N, device=dev), torch.empty(N, device=dev),
+                           torch.empty(N, dtype=torch.int32, device=dev), None)
+            for p in ("mr", "zf")}
+    bf = {p: D.beamform_outputs(1, K, M, prec, dev, precoder=p) for p in ("mr", "zf")}
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+
+    def step(e=None):
+        D.channel(params, ap, upts, prec="f32", out=H)
+        D.beamform(H, "mr", None, w.sigma2, w.p_total, prec, out=bf["mr"])
+        D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=bf["zf"])
+        for i, p in enumerate(("mr", "zf")):
+            if e is not None:
+                e[2 * i].record()
+            D.powermap(params, ap0, bf[p].W[0], gpts, w.sigma2, prec, out=maps[p])
+            if e is not None:
+                e[2 * i + 1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(ev[i])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    launch = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in ev) / (2 * args.steps)
+    # agreement of the mixed and FP32 maps of this step (same W up to the Gram precision)
+    dev_db = {}
+    for p in ("mr", "zf"):
+        a = maps[p].power.double()
+        b = maps_f32[p].power.double()
+        keep = b > 1e-6 * b.max()     # the -60 dB floor of the error rule
+        dev_db[p] = float((10 * torch.log10(a[keep] / b[keep])).abs().max())
+    return {"dtype": "f16x3 (FP16 hi/lo x3 MFMA, FP32 accumulate)", "ms_per_step": round(ms, 5),
+            "map_launch_ms": round(launch, 5), "speedup_vs_f32_step": round(f32_ms / ms, 3),
+            "max_db_vs_f32_maps": dev_db}
+
+
+def serving_phase(args, D, WL, torch):
+    """Poisson stream of power-map queries (M in {16,64,256,512}, N in
+    {64^2,256^2,1024^2}, K in {1,4,16}, f in {0.92,3.5,5.8} GHz, MR/ZF) into a
+    dmimo server with resident geometry.  Latency = completion - arrival."""
+    import numpy as np
+    pool = WL.serving_pool()
+    total_s = args.serve_warmup + args.serve_seconds
+    n_q = int(args.serve_rate * total_s * 1.2) + 16
+    qs = WL.serving_queries(pool, n_q, rate_hz=args.serve_rate)
+    qs = [q for q in qs if q.t_arrival < total_s]
+    dev = torch.device("cuda")
+    srv = D.Server(16 << 30, 64)
+    deps = [srv.add_deployment(D.channel_params(f), aps) for (M, f, aps) in pool]
+    # output buffers per grid side, recycled after completion
+    free = {s: [] for s in WL.SERVE_SIDE}
+    def get_buf(side):
+        if free[side]:
+            return free[side].pop()
+        n = side * side
+        return (torch.empty(n, device=dev), torch.empty(n, device=dev))
+    for side, cnt in ((64, 64), (256, 64), (1024, 64)):
+        free[side] = [(torch.empty(side * side, device=dev), torch.empty(side * side, device=dev))
+                      for _ in range(cnt)]
+    torch.cuda.synchronize()
+    outstanding = []          # (ticket, query, buf)
+    done = []                 # (arrival_abs, t_done, terms, measured)
+    t0 = time.monotonic() + 0.05
+    sigma2 = WL.NOISE_MINUS_90_DBM_W
+
+    def reap(block_one=False):
+        keep = []
+        for i, (tk, q, buf, ta) in enumerate(outstanding):
+            st, _, td = srv.poll(tk)
+            if st >= D.Q_DONE:
+                done.append((ta, td, q.M * q.side * q.side, q.t_arrival >= args.serve_warmup, st))
+                srv.release(tk)
+                free[q.side].append(buf)
+            else:
+                keep.append((tk, q, buf, ta))
+        outstanding[:] = keep
+
+    for q in qs:
+        ta = t0 + q.t_arrival
+        while True:
+            now = time.monotonic()
+            if now >= ta:
+                break
+            if ta - now > 2e-4 and outstanding:
+                reap()
+        buf = get_buf(q.side)
+        tk = srv.submit(deps[q.dep], q.user_xyz, q.precoder, D.grid_points(q.grid), sigma2, 1.0,
+                        args.serve_prec, buf[0], buf[1])
+        outstanding.append((tk, q, buf, ta))
+    while outstanding:
+        tk = outstanding[0][0]
+        srv.wait(tk, 30.0)
+        reap()
+    stats = srv.stats()
+    srv.close()
+    meas = [d for d in done if d[3]]
+    lat = np.array([d[1] - d[0] for d in meas]) * 1e3
+    failed = sum(1 for d in done if d[4] != D.Q_DONE)
+    t_first = min(d[0] for d in meas)
+    t_last = max(d[1] for d in meas)
+    terms = sum(d[2] for d in meas)
+    offered = sum(q.M * q.side * q.side for q in qs if q.t_arrival >= args.serve_warmup)
+    return {
+        "workload": "Poisson 2000 q/s power maps: M in {16,64,256,512}, N in {64^2,256^2,1024^2}, "
+                    "K in {1,4,16}, f in {0.92,3.5,5.8} GHz, MR/ZF; geometry resident",
+        "prec": args.serve_prec,
+        "rate_qps": args.serve_rate,
+        "measured_s": args.serve_seconds,
+        "queries": len(meas),
+        "failed": failed,
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "max_ms": round(float(lat.max()), 3),
+        "sustained_Gh_per_s": round(terms / (t_last - t_first) / 1e9, 2),
+        "offered_Gh_per_s": round(offered / args.serve_seconds / 1e9, 2),
+        "launches": stats["launches"],
+    }
 
 
 def cpu_baseline(w, bf, maps, budget_s):
