@@ -135,48 +135,31 @@ def main():
     upts = D.list_points(users, K)
     gpts = D.grid_points(w.grid)
     H = torch.empty((1, K, M), dtype=torch.complex64, device=dev)
-    maps = {p: D.MapResult(torch.empty(N, device=dev), torch.empty(N, device=dev),
-                           torch.empty(N, dtype=torch.int32, device=dev), None)
-            for p in ("mr", "zf")}
-    bf = {p: D.beamform_outputs(1, K, M, "f32", dev, precoder=p) for p in ("mr", "zf")}
 
     # a plain copy of known size, for scaling the HBM counters of a profiled run
     cp_src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
     cp_dst = torch.empty_like(cp_src)
     cp_dst.copy_(cp_src)
 
-    def step(evs=None):
-        D.channel(params, ap, upts, prec="f32", out=H)
-        D.beamform(H, "mr", None, w.sigma2, w.p_total, "f32", out=bf["mr"])
-        D.beamform(H, "zf", None, w.sigma2, w.p_total, "f32", out=bf["zf"])
-        for i, p in enumerate(("mr", "zf")):
-            if evs is not None:
-                evs[2 * i].record()
-            D.powermap(params, ap0, bf[p].W[0], gpts, w.sigma2, "f32", out=maps[p])
-            if evs is not None:
-                evs[2 * i + 1].record()
-
-    for _ in range(args.warmup):
-        step()
-    # HIP events around both map launches of every timed step, on the stream the
-    # kernels run on (torch's current stream); read after the final sync
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s_ in range(args.steps):
-        step(events[s_])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms_total = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in events)
-
+    ms_per_step, map_launch_ms, maps, bf = run_steps(args, "f32", w, D, params, ap, ap0, upts,
+                                                     gpts, H)
     mixed = None
     if not args.no_mixed:
-        mixed = mixed_step(args, w, D, params, ap, ap0, upts, gpts, H, maps, ms_per_step)
+        ms_mix, launch_mix, maps_mix, _ = run_steps(args, "f16x3", w, D, params, ap, ap0, upts,
+                                                    gpts, H)
+        dev_db = {}
+        for p in ("mr", "zf"):
+            a = maps_mix[p].power.double()
+            b = maps[p].power.double()
+            keep = b > 1e-6 * b.max()     # the -60 dB floor of the error rule
+            dev_db[p] = float((10 * torch.log10(a[keep] / b[keep])).abs().max())
+        mixed = {"dtype": "f16x3 (FP16 hi/lo x3 MFMA, FP32 accumulate)",
+                 "ms_per_step": round(ms_mix, 5), "map_launch_ms": round(launch_mix, 5),
+                 "speedup_vs_f32_step": round(ms_per_step / ms_mix, 3),
+                 "max_db_vs_f32_maps": dev_db}
 
     terms_per_step = 3 * K * M + 2 * N * M
     value = terms_per_step / (ms_per_step * 1e-3) / 1e9
-    map_launch_ms = kernel_ms_total / (2 * args.steps)
     alg = alg_slots_per_term(K) * N * M
     achieved = alg / (map_launch_ms * 1e-3) / 1e12
     peak = VALU_PEAK_SLOTS / 1e12
@@ -232,18 +215,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def mixed_step(args, w, D, params, ap, ap0, upts, gpts, H, maps_f32, f32_ms):
-    """The same step with the FP16 x3 split-precision Gram and maps (FP32
-    accumulation; FP64 distance / phase and Cholesky as before)."""
+def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
+    """Warm up, then time exactly args.steps steps of the room workload.
+
+    One step, in order on torch's current stream: the user channel, MR and
+    ZF precoders (Gram + FP64 Cholesky inside), the MR map, the ZF map.  HIP
+    events bracket every map launch on that stream.  (A variant with the MR
+    branch on a second stream was measured slower: 0.114 vs 0.094 ms/step,
+    because the cross-queue event waits cost more than the overlap saves.)
+    Returns (ms per step, mean map launch ms, maps, precoders).
+    """
     import torch
     K, M, N = w.K, w.M, w.grid.n
     dev = H.device
-    prec = "f16x3"
     maps = {p: D.MapResult(torch.empty(N, device=dev), torch.empty(N, device=dev),
                            torch.empty(N, dtype=torch.int32, device=dev), None)
             for p in ("mr", "zf")}
     bf = {p: D.beamform_outputs(1, K, M, prec, dev, precoder=p) for p in ("mr", "zf")}
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
 
     def step(e=None):
         D.channel(params, ap, upts, prec="f32", out=H)
@@ -258,23 +246,15 @@ def mixed_step(args, w, D, params, ap, ap0, upts, gpts, H, maps_f32, f32_ms):
 
     for _ in range(args.warmup):
         step()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(ev[i])
+        step(events[i])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    launch = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in ev) / (2 * args.steps)
-    # agreement of the mixed and FP32 maps of this step (same W up to the Gram precision)
-    dev_db = {}
-    for p in ("mr", "zf"):
-        a = maps[p].power.double()
-        b = maps_f32[p].power.double()
-        keep = b > 1e-6 * b.max()     # the -60 dB floor of the error rule
-        dev_db[p] = float((10 * torch.log10(a[keep] / b[keep])).abs().max())
-    return {"dtype": "f16x3 (FP16 hi/lo x3 MFMA, FP32 accumulate)", "ms_per_step": round(ms, 5),
-            "map_launch_ms": round(launch, 5), "speedup_vs_f32_step": round(f32_ms / ms, 3),
-            "max_db_vs_f32_maps": dev_db}
+    launch = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in events) / (2 * args.steps)
+    return ms, launch, maps, bf
 
 
 def serving_phase(args, D, WL, torch):
