@@ -169,6 +169,29 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M,
                             void* power, void* sinr, int32_t* best_k, void* per_stream,
                             void* stream);
 
+/* Proximal gradient descent on the PA-consumption Lagrangian
+ * lambda ||W||_{2,1} + ||H W^T - sigma D_gamma^{1/2}||_F^2 (Sec. III eq. l; Sec. IV
+ * eq. proxgd), and its deep-unfolded form with per-layer parameters (Sec. V,
+ * eq. unfoldednet).  Layer i, with sigma = sqrt(sigma2):
+ *   V   = W - eta_i (W H^T H^* - sigma D_gamma^{1/2} H^*)
+ *   w_m = (1 - lambda_i eta_i / max(||v_m||, lambda_i eta_i)) v_m   for every antenna m,
+ * starting from W(0) = H^* (W0 == NULL) or from W0.
+ *   H         device complex64 [B][K][M]; 1 <= K <= 16, 1 <= M <= 256.
+ *   gamma_lin host [K] SINR targets (linear), NULL = ones.
+ *   layers    I >= 0; lambdas, etas: device FP64 [I] (a constant schedule is
+ *             plain PGD; projections onto lambda >= 0 and the eta interval
+ *             are the caller's).
+ *   W0        device complex64 [B][K][M] or NULL.
+ *   prec      DMIMO_F32 (FP32 arithmetic; others: DMIMO_E_UNSUPPORTED).
+ *   W         device complex64 [B][K][M] output.
+ *   l21       device FP64 [B] or NULL: ||W||_{2,1} of the output (PA consumed
+ *             power / alpha, eq. effmodel).
+ *   rsum      device FP64 [B] or NULL: sum rate of the output, noise sigma2. */
+dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const double* gamma_lin,
+                       double sigma2, int32_t layers, const double* lambdas, const double* etas,
+                       const void* W0, int32_t prec, void* W, double* l21, double* rsum,
+                       void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of power-map queries on one GPU.
  *

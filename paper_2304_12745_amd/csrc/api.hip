@@ -252,4 +252,26 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const
     return launch_powermap(a, as_stream(stream));
 }
 
+dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const double* gamma_lin,
+                       double sigma2, int32_t layers, const double* lambdas, const double* etas,
+                       const void* W0, int32_t prec, void* W, double* l21, double* rsum,
+                       void* stream) {
+    clear_error();
+    if (B < 0 || layers < 0) return fail(DMIMO_E_SHAPE, "pgd: B and layers must be >= 0");
+    if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "pgd: K and M must be >= 1");
+    if (K > 16 || M > 256) return fail(DMIMO_E_SHAPE, "pgd: K <= 16 and M <= 256");
+    if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "pgd: unknown precision");
+    if (prec != DMIMO_F32) return fail(DMIMO_E_UNSUPPORTED, "pgd: FP32 only");
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return fail(DMIMO_E_ARG, "pgd: sigma2 must be >= 0");
+    if (rsum && !(sigma2 > 0.0)) return fail(DMIMO_E_ARG, "pgd: the sum rate needs sigma2 > 0");
+    for (int k = 0; gamma_lin && k < K; ++k)
+        if (!(gamma_lin[k] >= 0.0) || !std::isfinite(gamma_lin[k]))
+            return fail(DMIMO_E_ARG, "pgd: gamma_lin must be finite and >= 0");
+    if (B == 0) return DMIMO_OK;
+    if (!H || !W) return fail(DMIMO_E_ARG, "pgd: NULL H or W");
+    if (layers > 0 && (!lambdas || !etas)) return fail(DMIMO_E_ARG, "pgd: NULL lambdas or etas");
+    return launch_pgd(B, K, M, H, gamma_lin, sigma2, layers, lambdas, etas, W0, W, l21, rsum,
+                      as_stream(stream));
+}
+
 }  // extern "C"

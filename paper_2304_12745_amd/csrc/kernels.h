@@ -50,4 +50,8 @@ struct PowermapArgs {
 
 dmimo_status launch_powermap(const PowermapArgs& a, hipStream_t s);
 
+dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* gamma, double sigma2,
+                        int layers, const double* lambdas, const double* etas, const void* W0,
+                        void* W, double* l21, double* rsum, hipStream_t s);
+
 }  // namespace dmimo

@@ -59,6 +59,7 @@ _SIGS = {
     "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
+    "dmimo_pgd": [_i32, _i32, _i32, _vp, _vp, _f64, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "dmimo_server_create": [_i32, _sz, _i32, ctypes.POINTER(ctypes.c_void_p)],
     "dmimo_server_add_deployment": [_vp, ctypes.POINTER(ChannelParams), _i32, _vp,
                                     ctypes.POINTER(_i32)],
@@ -280,6 +281,40 @@ def powermap(params: ChannelParams, ap_xyz, W, points: Points, sigma2=1e-12, pre
                                 ctypes.byref(points), float(sigma2), prec, _ptr(out.power),
                                 _ptr(out.sinr), _ptr(out.best_k), _ptr(out.per_stream),
                                 _stream(stream)), "dmimo_powermap")
+    return out
+
+
+@dataclass
+class PgdResult:
+    W: object
+    l21: object
+    rsum: object
+
+
+def pgd(H, lambdas, etas, gamma_lin=None, sigma2=1.0, W0=None, prec="f32", out=None,
+        want_l21=True, want_rsum=True, stream=None) -> PgdResult:
+    """PGD / unfolded PGD (dmimo_pgd).  H complex64 [B][K][M]; lambdas, etas:
+    per-layer values (sequences or FP64 device tensors of length I)."""
+    import torch
+    B, K, M = H.shape
+    dev = H.device
+    lam = lambdas if torch.is_tensor(lambdas) else torch.tensor(list(lambdas), dtype=torch.float64)
+    eta = etas if torch.is_tensor(etas) else torch.tensor(list(etas), dtype=torch.float64)
+    lam = lam.to(device=dev, dtype=torch.float64).contiguous()
+    eta = eta.to(device=dev, dtype=torch.float64).contiguous()
+    if lam.numel() != eta.numel():
+        raise ValueError("lambdas and etas need the same length")
+    if out is None:
+        out = PgdResult(torch.empty((B, K, M), dtype=torch.complex64, device=dev),
+                        torch.empty((B,), dtype=torch.float64, device=dev) if want_l21 else None,
+                        torch.empty((B,), dtype=torch.float64, device=dev) if want_rsum else None)
+    g = None
+    if gamma_lin is not None:
+        g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+    out._keep = (lam, eta)
+    _check(lib().dmimo_pgd(B, K, M, _ptr(H), g, float(sigma2), lam.numel(), _ptr(lam), _ptr(eta),
+                           _ptr(W0), _prec(prec), _ptr(out.W), _ptr(out.l21), _ptr(out.rsum),
+                           _stream(stream)), "dmimo_pgd")
     return out
 
 

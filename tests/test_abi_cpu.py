@@ -136,3 +136,28 @@ def test_server_validation(lib):
     st = ctypes.c_int32()
     assert lib.dmimo_server_poll(None, 1, ctypes.byref(st), None, None) == 1
     assert lib.dmimo_server_destroy(None) == 0
+
+
+def test_pgd_validation(lib):
+    g = (ctypes.c_double * 2)(1.0, 1.0)
+
+    def pgd(B=2, K=2, M=8, H=FAKE, gamma=None, sigma2=1.0, layers=3, lam=FAKE, eta=FAKE,
+            prec=D.F32, W=FAKE, rsum=None):
+        return lib.dmimo_pgd(B, K, M, H, gamma, sigma2, layers, lam, eta, None, prec, W, None,
+                             rsum, None)
+
+    assert pgd(K=0) == 2
+    assert pgd(M=257) == 2
+    assert pgd(K=17, M=64) == 2
+    assert pgd(B=-1) == 2
+    assert pgd(layers=-1) == 2
+    assert pgd(prec=9) == 3
+    assert pgd(prec=D.F64) == 6
+    assert pgd(sigma2=-1.0) == 1
+    assert pgd(sigma2=0.0, rsum=FAKE) == 1
+    bad = (ctypes.c_double * 2)(1.0, float("nan"))
+    assert pgd(gamma=bad) == 1
+    assert pgd(H=None) == 1
+    assert pgd(W=None) == 1
+    assert pgd(lam=None) == 1
+    assert pgd(B=0, H=None, W=None, gamma=g) == 0

@@ -1,0 +1,119 @@
+"""GPU parity of dmimo_pgd (PGD / unfolded PGD, Sec. IV-V) against the FP64 oracle.
+
+FP32 on the GPU against FP64 in the oracle.  The iteration is a proximal
+gradient step with eta <= 1/L, hence non-expansive, so rounding differences
+stay at the FP32 level: W within 1e-4 relative after 20 layers and 1e-3
+after 5000 iterations.  PCG is also pinned directly to the paper's printed
+optimum 1.1160 (Sec. VI-C) after 5000 iterations.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dmimo_oracle as O  # noqa: E402
+from oracle import pgd_oracle as P  # noqa: E402
+from paper_2304_12745_amd import workloads as WL  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2304_12745_amd import dmimo
+    dmimo.lib()
+    return dmimo
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def c64(x):
+    return np.asarray(x).astype(np.complex64)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=(-2, -1)) / np.maximum(np.linalg.norm(b, axis=(-2, -1)), 1e-30)
+
+
+def test_unfolded_schedule_matches_oracle(D):
+    say("unfolded PGD, 20 layers, varying lambda/eta, paper setting")
+    w = WL.paper_workload(seed=31, B=256)
+    H = c64(w.H)
+    K, M = 8, 64
+    Lt = P.mp_edge(K, M)
+    rng = np.random.default_rng(0)
+    lams = P.project_lambda(rng.uniform(-0.02, 0.3, 20))
+    etas = P.project_eta(rng.uniform(0.3 / Lt, 1.2 / Lt, 20), K, M)
+    r = D.pgd(torch.from_numpy(H).cuda(), lams, etas, w.gamma_lin, 1.0)
+    torch.cuda.synchronize()
+    Wg = r.W.cpu().numpy()
+    Wo = P.unfolded(H.astype(np.complex128), w.gamma_lin, 1.0, lams, etas)
+    e = _rel(Wg, Wo)
+    say(f"    W rel err max {e.max():.2e}")
+    assert e.max() < 1e-4
+    np.testing.assert_allclose(r.l21.cpu().numpy(), O.l21_norm(Wo), rtol=1e-4)
+    np.testing.assert_allclose(r.rsum.cpu().numpy(), P.sum_rate(H.astype(np.complex128), Wo, 1.0),
+                               atol=2e-3)
+
+
+def test_lambda_zero_gives_zf(D):
+    say("PGD lambda=0, 400 iterations -> ZF")
+    w = WL.paper_workload(seed=32, B=64)
+    H = c64(w.H)
+    L = np.linalg.eigvalsh(O.gram(H.astype(np.complex128)))[:, -1].max()
+    r = D.pgd(torch.from_numpy(H).cuda(), [0.0] * 400, [1.0 / L] * 400, w.gamma_lin, 1.0)
+    Wzf, _ = O.zf_precoder(H.astype(np.complex128), w.gamma_lin, 1.0, 0.0)
+    e = _rel(r.W.cpu().numpy(), Wzf)
+    say(f"    W rel err vs ZF max {e.max():.2e}")
+    assert e.max() < 1e-4
+    np.testing.assert_allclose(r.rsum.cpu().numpy(), 8 * np.log2(11), atol=1e-3)
+
+
+@pytest.mark.parametrize("K,M", [(1, 5), (3, 100), (16, 256), (13, 64)])
+def test_shapes_and_initial_point(D, K, M):
+    say(f"unfolded PGD K={K} M={M}, W0 given")
+    rng = np.random.default_rng(K * 100 + M)
+    H = c64(WL.complex_normal(rng, (5, K, M)))
+    W0 = c64(WL.complex_normal(rng, (5, K, M)) * 0.1)
+    gamma = rng.uniform(1, 20, K)
+    Lt = P.mp_edge(K, M)
+    lams = rng.uniform(0, 0.5, 12)
+    etas = rng.uniform(0.5 / Lt, 1.0 / Lt, 12)
+    r = D.pgd(torch.from_numpy(H).cuda(), lams, etas, gamma, 0.8, W0=torch.from_numpy(W0).cuda())
+    Wo = P.unfolded(H.astype(np.complex128), gamma, np.sqrt(0.8), lams, etas,
+                    W0=W0.astype(np.complex128))
+    e = _rel(r.W.cpu().numpy(), Wo)
+    say(f"    W rel err max {e.max():.2e}")
+    assert e.max() < 1e-4
+    # zero layers returns the initial point
+    r0 = D.pgd(torch.from_numpy(H).cuda(), [], [], gamma, 0.8, W0=torch.from_numpy(W0).cuda())
+    np.testing.assert_array_equal(r0.W.cpu().numpy(), W0)
+
+
+def test_pgd_5000_iterations_reaches_the_paper_optimum(D):
+    say("PGD 5000 iterations, 100 channels: PCG vs the paper's 1.1160")
+    K, M = 8, 64
+    w = WL.paper_workload(seed=123, B=100)
+    H = c64(w.H)
+    Hc = H.astype(np.complex128)
+    Wzf, _ = O.zf_precoder(Hc, w.gamma_lin, 1.0, 0.0)
+    eta = 1.0 / P.mp_edge(K, M)
+    r = D.pgd(torch.from_numpy(H).cuda(), [1 / 15] * 5000, [eta] * 5000, w.gamma_lin, 1.0)
+    torch.cuda.synchronize()
+    pcg_gpu = O.l21_norm(Wzf) / r.l21.cpu().numpy()
+    Wo = P.pgd(Hc, w.gamma_lin, 1.0, 1 / 15, eta, 5000)
+    pcg_or = P.pcg(Wzf, Wo)
+    say(f"    mean PCG gpu {pcg_gpu.mean():.4f} oracle {pcg_or.mean():.4f}; "
+        f"max |diff| {np.abs(pcg_gpu - pcg_or).max():.2e}")
+    assert np.abs(pcg_gpu - pcg_or).max() < 2e-3
+    assert abs(pcg_gpu.mean() - 1.1160) < 0.02
+    e = _rel(r.W.cpu().numpy(), Wo)
+    say(f"    W rel err max {e.max():.2e}")
+    assert np.median(e) < 1e-3
