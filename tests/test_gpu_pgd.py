@@ -76,7 +76,7 @@ def test_lambda_zero_gives_zf(D):
     np.testing.assert_allclose(r.rsum.cpu().numpy(), 8 * np.log2(11), atol=1e-3)
 
 
-@pytest.mark.parametrize("K,M", [(1, 5), (3, 100), (16, 256), (13, 64)])
+@pytest.mark.parametrize("K,M", [(1, 5), (3, 100), (8, 256), (6, 129), (8, 64), (16, 256), (13, 64)])
 def test_shapes_and_initial_point(D, K, M):
     say(f"unfolded PGD K={K} M={M}, W0 given")
     rng = np.random.default_rng(K * 100 + M)
