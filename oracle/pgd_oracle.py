@@ -85,8 +85,13 @@ def wirtinger_gradient(H, W, gamma, sigma):
 
 
 def prox_l21(V, t):
-    """Column-wise group soft threshold: (1 - t / max(||v_m||, t)) v_m."""
+    """Column-wise group soft threshold: (1 - t / max(||v_m||, t)) v_m.
+
+    With t = 0 the operator is the identity (the formula's 0/0 on a zero
+    column reads as no shrinkage)."""
     V = np.asarray(V, np.complex128)
+    if t == 0:
+        return V
     norms = np.sqrt(np.sum(np.abs(V) ** 2, axis=-2, keepdims=True))
     return (1.0 - t / np.maximum(norms, t)) * V
 

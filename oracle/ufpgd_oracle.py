@@ -17,7 +17,8 @@ Gradients are computed by reverse-mode differentiation of the layer, derived
 here by hand.  Conventions: for a real function C of a complex matrix X the
 cotangent is Gbar_X = dC/dRe X + j dC/dIm X, so dC = Re sum(conj(Gbar_X) dX).
   cost:       Gbar_W = 2 (H W^T - S)^T H^* + lambda_c w_m / ||w_m||      (S = sigma D^{1/2})
-  prox:       w = (1 - t/n) v for n = ||v|| > t, else 0; with rho = Re(v^H gbar_w):
+  prox:       w = (1 - t/n) v for n = ||v|| > t, else 0 (identity at t = 0);
+              with rho = Re(v^H gbar_w):
               gbar_v = (1 - t/n) gbar_w + (t rho / n^3) v,  dC/dt = -rho / n
   step:       V = W - eta ((W H^T - S) H^*) is complex-linear in W with
               the Hermitian M x M map I - eta H^T H^*, so
@@ -81,9 +82,12 @@ def backward(H, tape, gamma, sigma, lams, etas, gbar):
         t = lam * eta
         n = np.sqrt(np.sum(np.abs(V) ** 2, axis=-2, keepdims=True))      # [..][1][M]
         rho = np.sum(np.real(np.conj(gbar) * V), axis=-2, keepdims=True)
-        active = (n > t) & (n > 0)
+        active = n > t
         ns = np.where(active, n, 1.0)
-        gv = np.where(active, (1.0 - t / ns) * gbar + (t * rho / ns ** 3) * V, 0.0)
+        # a column at or below the threshold maps to zero (zero cotangent), except
+        # at t = 0, where the prox is the identity
+        gv = np.where(active, (1.0 - t / ns) * gbar + (t * rho / ns ** 3) * V,
+                      gbar if t == 0 else 0.0)
         dt = -np.sum(np.where(active, rho / ns, 0.0), axis=(-2, -1))
         gf = P.wirtinger_gradient(H, W, gamma, sigma)
         d_eta_step = -np.sum(np.real(np.conj(gv) * gf), axis=(-2, -1))

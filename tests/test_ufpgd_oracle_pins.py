@@ -95,6 +95,29 @@ def test_initial_network_is_twenty_pgd_iterations_at_pcg_one():
     np.testing.assert_allclose(lams, 1.0 / 15.0)
 
 
+def test_zero_threshold_layer_is_the_plain_gradient_step():
+    """lambda^(i) = 0 (the projection's lower bound) makes the prox the identity,
+    also on a column that is exactly zero; its reverse pass is then that of the
+    linear gradient step alone."""
+    rng = np.random.default_rng(19)
+    H = _cn(rng, (2, 4))
+    H[:, 1] = 0.0                                    # column 1 of V stays exactly zero
+    W0 = _cn(rng, (2, 4))
+    W0[:, 1] = 0.0
+    gamma, sigma = np.array([1.0, 2.0]), 1.0
+    W, tape = U.forward(H, gamma, sigma, [0.0], [0.05], W0=W0)
+    np.testing.assert_array_equal(W, tape[0][1])
+    assert np.all(np.isfinite(W)) and np.all(W[:, 1] == 0)
+    gbar = _cn(rng, (2, 4))
+    dl, de = U.backward(H, tape, gamma, sigma, [0.0], [0.05], gbar)
+    gf = P.wirtinger_gradient(H, W0, gamma, sigma)
+    assert abs(de[0] + np.sum(np.real(np.conj(gbar) * gf))) < 1e-12
+    rho = np.sum(np.real(np.conj(gbar) * W), axis=0)
+    n = np.linalg.norm(W, axis=0)
+    keep = n > 0
+    assert abs(dl[0] - 0.05 * -np.sum(rho[keep] / n[keep])) < 1e-12
+
+
 def test_cost_cotangent_matches_finite_differences():
     rng = np.random.default_rng(12)
     H = _cn(rng, (3, 6))
