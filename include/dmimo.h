@@ -193,6 +193,71 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
                        void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Unsupervised training of the unfolded network (Sec. V; Sec. VI-A).
+ *
+ * The network is the layer of dmimo_pgd applied I times from W(0) = H^*,
+ * with per-layer lambda_i, eta_i.  Its cost on one channel (Sec. V,
+ * unsupervised cost) is
+ *   C = lam_c ||W(I)||_{2,1} + ||H W(I)^T - sigma D_gamma^{1/2}||_F^2,
+ * with lam_c the cost's fixed lambda (1/15 in Sec. VI-C).  Gradients are
+ * exact reverse-mode derivatives of the FP32 forward pass; at a prox
+ * threshold of 0 the prox is the identity.  K <= 8 (8 < K <= 16:
+ * DMIMO_E_UNSUPPORTED), M <= 256, FP32 only.
+ * --------------------------------------------------------------------------- */
+
+/* Scratch for dmimo_ufpgd_grad / dmimo_ufpgd_train with B channels (or a
+ * batch of B) and I layers: the per-layer tape (pre-prox V and the K x K
+ * step operand) plus per-channel gradients.  0 for unsupported shapes. */
+size_t dmimo_ufpgd_workspace_size(int32_t B, int32_t K, int32_t M, int32_t layers);
+
+/* Per-channel cost of the network output and its gradient with respect to
+ * every lambda_i and eta_i.
+ *   B          channels to evaluate; entry b uses channel idx[b] of H, or
+ *              channel b when idx == NULL (then n_channels >= B).  An idx entry
+ *              outside [0, n_channels) yields cost NaN and zero gradients.
+ *   H          device complex64 [n_channels][K][M].
+ *   idx        device int32 [B] or NULL.
+ *   gamma_lin  host [K] SINR targets (linear) or NULL (ones); sigma2 >= 0.
+ *   lambdas, etas  device FP64 [layers], used as given (no projection).
+ *   cost       device FP64 [B] or NULL.
+ *   dlam, deta device FP64 [B][layers], both or neither.  With neither, only
+ *              the forward pass and cost run and ws may be NULL.
+ *   ws         device scratch of dmimo_ufpgd_workspace_size(B, K, M, layers). */
+dmimo_status dmimo_ufpgd_grad(int32_t B, int32_t n_channels, int32_t K, int32_t M, const void* H,
+                              const int32_t* idx, const double* gamma_lin, double sigma2,
+                              double lam_c, int32_t layers, const double* lambdas,
+                              const double* etas, int32_t prec, double* cost, double* dlam,
+                              double* deta, void* ws, size_t ws_bytes, void* stream);
+
+/* Adam hyper-parameters (Kingma and Ba; the paper trains with lr = 1e-3). */
+typedef struct {
+    double lr;
+    double beta1;
+    double beta2;
+    double eps;
+} dmimo_adam_params;
+
+/* `steps` training steps, stream-ordered, no host synchronisation.  Step s:
+ *   1. the gradient of the mean cost over the batch idx[s][0..batch-1];
+ *   2. one Adam update of [lambda; eta] (bias correction with step number
+ *      t0 + s + 1; moments adam_m, adam_v of length 2 layers, lambdas first);
+ *   3. the projections lambda_i >= 0, eta_i in [1/(2 L~), 1/L~] with
+ *      L~ = (sqrt K + sqrt M)^2 (Sec. V).
+ *   lambdas, etas, adam_m, adam_v  device FP64, updated in place.
+ *   idx        device int32 [steps][batch], channel indices into H (the
+ *              caller draws the epoch permutations).
+ *   batch_cost device FP64 [steps] or NULL: mean cost of each step's batch,
+ *              before its update.
+ *   ws         dmimo_ufpgd_workspace_size(batch, K, M, layers) bytes. */
+dmimo_status dmimo_ufpgd_train(int32_t n_channels, int32_t K, int32_t M, const void* H,
+                               const double* gamma_lin, double sigma2, double lam_c,
+                               int32_t layers, double* lambdas, double* etas, double* adam_m,
+                               double* adam_v, int64_t t0, const dmimo_adam_params* opt,
+                               int32_t batch, int32_t steps, const int32_t* idx,
+                               double* batch_cost, int32_t prec, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* ---------------------------------------------------------------------------
  * Serving: continuous batching of power-map queries on one GPU.
  *
  * A server owns one HIP stream, one worker thread and one device arena of

@@ -2,6 +2,7 @@
 // Every check here runs before the first HIP runtime call of an entry point,
 // so argument errors are reported without touching the GPU.
 #include <cmath>
+#include <cstdio>
 #include <cstdarg>
 #include <cstring>
 
@@ -85,6 +86,41 @@ dmimo_status make_points(const dmimo_points* p, PointsDev* out) {
 static bool valid_prec(int32_t p) { return p >= DMIMO_F64 && p <= DMIMO_MIX_BF16X3; }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static dmimo_status check_ufpgd_common(const char* who, int32_t K, int32_t M, int32_t layers,
+                                const double* gamma_lin, double sigma2, double lam_c, int32_t prec) {
+    char msg[160];
+    if (K < 1 || M < 1 || layers < 0) {
+        std::snprintf(msg, sizeof msg, "%s: K, M must be >= 1 and layers >= 0", who);
+        return fail(DMIMO_E_SHAPE, msg);
+    }
+    if (M > 256 || K > 16) {
+        std::snprintf(msg, sizeof msg, "%s: K <= 8 and M <= 256", who);
+        return fail(DMIMO_E_SHAPE, msg);
+    }
+    if (K > 8) {
+        std::snprintf(msg, sizeof msg, "%s: training is provided for K <= 8", who);
+        return fail(DMIMO_E_UNSUPPORTED, msg);
+    }
+    if (!valid_prec(prec)) {
+        std::snprintf(msg, sizeof msg, "%s: unknown precision", who);
+        return fail(DMIMO_E_DTYPE, msg);
+    }
+    if (prec != DMIMO_F32) {
+        std::snprintf(msg, sizeof msg, "%s: FP32 only", who);
+        return fail(DMIMO_E_UNSUPPORTED, msg);
+    }
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2) || !(lam_c >= 0.0) || !std::isfinite(lam_c)) {
+        std::snprintf(msg, sizeof msg, "%s: sigma2 and lam_c must be finite and >= 0", who);
+        return fail(DMIMO_E_ARG, msg);
+    }
+    for (int k = 0; gamma_lin && k < K; ++k)
+        if (!(gamma_lin[k] >= 0.0) || !std::isfinite(gamma_lin[k])) {
+            std::snprintf(msg, sizeof msg, "%s: gamma_lin must be finite and >= 0", who);
+            return fail(DMIMO_E_ARG, msg);
+        }
+    return DMIMO_OK;
+}
 
 }  // namespace dmimo
 
@@ -272,6 +308,60 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
     if (layers > 0 && (!lambdas || !etas)) return fail(DMIMO_E_ARG, "pgd: NULL lambdas or etas");
     return launch_pgd(B, K, M, H, gamma_lin, sigma2, layers, lambdas, etas, W0, W, l21, rsum,
                       as_stream(stream));
+}
+
+size_t dmimo_ufpgd_workspace_size(int32_t B, int32_t K, int32_t M, int32_t layers) {
+    if (B < 1 || K < 1 || K > 8 || M < 1 || M > 256 || layers < 0) return 0;
+    return ufpgd_workspace_bytes(B, M, layers);
+}
+
+dmimo_status dmimo_ufpgd_grad(int32_t B, int32_t n_channels, int32_t K, int32_t M, const void* H,
+                              const int32_t* idx, const double* gamma_lin, double sigma2,
+                              double lam_c, int32_t layers, const double* lambdas,
+                              const double* etas, int32_t prec, double* cost, double* dlam,
+                              double* deta, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (B < 0 || n_channels < 0) return fail(DMIMO_E_SHAPE, "ufpgd_grad: B and n_channels must be >= 0");
+    dmimo_status st = check_ufpgd_common("ufpgd_grad", K, M, layers, gamma_lin, sigma2, lam_c, prec);
+    if (st) return st;
+    if (!idx && n_channels < B) return fail(DMIMO_E_SHAPE, "ufpgd_grad: without idx, n_channels >= B");
+    if ((dlam == nullptr) != (deta == nullptr))
+        return fail(DMIMO_E_ARG, "ufpgd_grad: give both dlam and deta, or neither");
+    if (B == 0) return DMIMO_OK;
+    if (!H) return fail(DMIMO_E_ARG, "ufpgd_grad: NULL H");
+    if (!cost && !dlam) return fail(DMIMO_E_ARG, "ufpgd_grad: nothing to compute");
+    if (layers > 0 && (!lambdas || !etas)) return fail(DMIMO_E_ARG, "ufpgd_grad: NULL lambdas or etas");
+    if (dlam && (!ws || ws_bytes < ufpgd_workspace_bytes(B, M, layers)))
+        return fail(DMIMO_E_WORKSPACE, "ufpgd_grad: workspace smaller than dmimo_ufpgd_workspace_size()");
+    UfpgdArgs g{B, K, M, layers, n_channels, H, idx, gamma_lin, sigma2, lam_c, lambdas, etas};
+    return launch_ufpgd_grad(g, cost, dlam, deta, ws, as_stream(stream));
+}
+
+dmimo_status dmimo_ufpgd_train(int32_t n_channels, int32_t K, int32_t M, const void* H,
+                               const double* gamma_lin, double sigma2, double lam_c,
+                               int32_t layers, double* lambdas, double* etas, double* adam_m,
+                               double* adam_v, int64_t t0, const dmimo_adam_params* opt,
+                               int32_t batch, int32_t steps, const int32_t* idx,
+                               double* batch_cost, int32_t prec, void* ws, size_t ws_bytes,
+                               void* stream) {
+    clear_error();
+    dmimo_status st = check_ufpgd_common("ufpgd_train", K, M, layers, gamma_lin, sigma2, lam_c, prec);
+    if (st) return st;
+    if (n_channels < 1 || batch < 1 || steps < 0 || layers < 1 || t0 < 0)
+        return fail(DMIMO_E_SHAPE, "ufpgd_train: n_channels, batch, layers >= 1; steps, t0 >= 0");
+    if (!opt) return fail(DMIMO_E_ARG, "ufpgd_train: NULL optimiser parameters");
+    if (!(opt->lr > 0.0) || !std::isfinite(opt->lr) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
+        !(opt->beta2 >= 0.0 && opt->beta2 < 1.0) || !(opt->eps > 0.0) || !std::isfinite(opt->eps))
+        return fail(DMIMO_E_ARG, "ufpgd_train: lr > 0, 0 <= beta < 1, eps > 0");
+    if (steps == 0) return DMIMO_OK;
+    if (!H || !lambdas || !etas || !adam_m || !adam_v || !idx)
+        return fail(DMIMO_E_ARG, "ufpgd_train: NULL H, parameters, Adam moments or idx");
+    if (!ws || ws_bytes < ufpgd_workspace_bytes(batch, M, layers))
+        return fail(DMIMO_E_WORKSPACE, "ufpgd_train: workspace smaller than dmimo_ufpgd_workspace_size()");
+    UfpgdArgs g{batch, K, M, layers, n_channels, H, nullptr, gamma_lin, sigma2, lam_c, lambdas, etas};
+    UfpgdTrainArgs t{lambdas, etas, adam_m, adam_v, t0, opt->lr, opt->beta1, opt->beta2, opt->eps,
+                     steps, idx, batch_cost};
+    return launch_ufpgd_train(g, t, ws, as_stream(stream));
 }
 
 }  // extern "C"

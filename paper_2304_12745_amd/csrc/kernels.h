@@ -54,4 +54,33 @@ dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* ga
                         int layers, const double* lambdas, const double* etas, const void* W0,
                         void* W, double* l21, double* rsum, hipStream_t s);
 
+struct UfpgdArgs {
+    int64_t B;              // channels per launch (the batch)
+    int K, M, layers, n_channels;
+    const void* H;          // complex64 [n_channels][K][M]
+    const int32_t* idx;     // [B] channel of each batch entry, or NULL (entry b = channel b)
+    const double* gamma;    // host [K] or NULL
+    double sigma2, lam_c;
+    const double* lambdas;  // device [layers]
+    const double* etas;
+};
+
+struct UfpgdTrainArgs {
+    double* lambdas;        // device [layers], updated in place
+    double* etas;
+    double* adam_m;         // device [2 layers]
+    double* adam_v;
+    int64_t t0;             // Adam steps already taken
+    double lr, beta1, beta2, eps;
+    int64_t steps;
+    const int32_t* idx;     // device [steps][B]
+    double* batch_cost;     // device [steps] or NULL
+};
+
+size_t ufpgd_workspace_bytes(int64_t B, int M, int layers);
+dmimo_status launch_ufpgd_grad(const UfpgdArgs& g, double* cost, double* dlam, double* deta,
+                               void* ws, hipStream_t s);
+dmimo_status launch_ufpgd_train(const UfpgdArgs& g, const UfpgdTrainArgs& t, void* ws,
+                                hipStream_t s);
+
 }  // namespace dmimo

@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "pgd_mfma.h"
 
 namespace dmimo {
 
@@ -178,115 +179,41 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
 }
 
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kPgdMfmaMaxWaves = 4;     // 256 antennas
-
-// Planar LDS image of a K x M complex matrix: row p*8 + k holds part p (0 re,
-// 1 im) of row k; rows >= K and antennas >= M are zero.  Row stride 64 nw + 4
-// floats keeps the four 16-lane groups of a wave on distinct banks.
-__device__ __forceinline__ int pl_stride(int nw) { return 64 * nw + 4; }
-
 __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev a, int nw) {
     extern __shared__ float smem[];
     const int stride = pl_stride(nw);
     float* sX = smem;                          // [16][stride]   H, then W
-    float* sD = smem + 16 * stride;            // [2][nw][16][17] step-1 partials
+    float* sD = smem + 16 * stride;            // [2][nw][16][17] D1 partials
 
+    const PgdLane L;
     const int64_t b = blockIdx.x;
     const int K = a.K, M = a.M;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int lo = lane & 15, hi = lane >> 4;
-    const int c0 = 64 * wave;                  // first antenna of this wave
     const float2* Hb = a.H + b * K * M;
-    const int ncol = 64 * nw;
 
-    // H, planar, zero padded
-    for (int e = tid; e < 8 * ncol; e += blockDim.x) {
-        const int k = e / ncol, m = e - k * ncol;
-        float2 h = make_float2(0.f, 0.f);
-        if (k < K && m < M) h = Hb[k * M + m];
-        sX[k * stride + m] = h.x;
-        sX[(8 + k) * stride + m] = h.y;
-    }
+    load_planar(sX, stride, nw, Hb, K, M, false);
     __syncthreads();
-    // step-1 operand layout (both operands): lane (hi, lo) holds row lo at
-    // antennas c0 + 16 hi + c, c = 0..15
-    float HA[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) HA[c] = sX[lo * stride + c0 + 16 * hi + c];
-    // step-2 B operand: block q, k-step s: lane (hi, lo) holds row 4 s + hi at antenna c0 + 16 q + lo
-    float HB[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) HB[q][s] = sX[(4 * s + hi) * stride + c0 + 16 * q + lo];
+    float HA[16], HB[4][4];
+    read_op_a(sX, stride, L, HA);
+    read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    // W(0): W0, or H^* (negate the imaginary rows in place)
-    for (int e = tid; e < 8 * ncol; e += blockDim.x) {
-        const int k = e / ncol, m = e - k * ncol;
-        if (a.W0) {
-            float2 w = make_float2(0.f, 0.f);
-            if (k < K && m < M) w = a.W0[b * K * M + k * M + m];
-            sX[k * stride + m] = w.x;
-            sX[(8 + k) * stride + m] = w.y;
-        } else {
-            sX[(8 + k) * stride + m] = -sX[(8 + k) * stride + m];
-        }
-    }
+    load_planar(sX, stride, nw, a.W0 ? a.W0 + b * K * M : Hb, K, M, a.W0 == nullptr);   // W(0) = W0 or H^*
     __syncthreads();
-    // W in the step-2 output layout: lane (hi, lo) reg (q, r) holds row 4 hi + r at antenna c0 + 16 q + lo
-    float WD[4][4];
-    float WA[16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) WD[q][r] = sX[(4 * hi + r) * stride + c0 + 16 * q + lo];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) WA[c] = sX[lo * stride + c0 + 16 * hi + c];
-
-    // this lane's entries of [[Ar~, Ai], [Ai, -Ar~]]: row i = lo, column l = 4 s + hi
-    const int ia = lo & 7;
-    const bool itop = lo < 8;
-    const float dia = a.d[ia];
+    float WD[4][4], WA[16];
+    read_out_d(sX, stride, L, WD);
+    read_op_a(sX, stride, L, WA);
+    const float dg = a.d[L.lo & 7];
 
     for (int layer = 0; layer < a.layers; ++layer) {
         const float eta = (float)a.etas[layer];
         const float thr = (float)(a.lambdas[layer] * a.etas[layer]);
-        // step 1
-        f32x4 d1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < 16; ++c) d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(WA[c], HA[c], d1, 0, 0, 0);
-        float* part = sD + ((layer & 1) * nw + wave) * (16 * 17);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) part[(4 * hi + r) * 17 + lo] = d1[r];
+        float* part = sD + ((layer & 1) * nw + L.wave) * kPartFloats;
+        put_partial(part, L, d1_partial(WA, HA));
         __syncthreads();
-        const float* parts = sD + (layer & 1) * nw * (16 * 17);
-        float A2[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int l = 4 * s + hi;
-            const int lb = l & 7;
-            const bool ltop = l < 8;
-            float v = 0.0f;
-            if (itop == ltop) {          // +-(Ar - D)[ia][lb]
-                for (int p = 0; p < nw; ++p)
-                    v += parts[p * 272 + ia * 17 + lb] - parts[p * 272 + (8 + ia) * 17 + 8 + lb];
-                if (ia == lb) v -= dia;
-                if (!itop) v = -v;
-            } else {                     // Ai[ia][lb]
-                for (int p = 0; p < nw; ++p)
-                    v += parts[p * 272 + ia * 17 + 8 + lb] + parts[p * 272 + (8 + ia) * 17 + lb];
-            }
-            A2[s] = v;
-        }
-        // step 2, gradient step and prox, one block of 16 antennas at a time
+        float E[4];                            // (A - D), embedded
+        embed_operand(sD + (layer & 1) * nw * kPartFloats, nw, L, dg, E);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            f32x4 g = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < 4; ++s) g = __builtin_amdgcn_mfma_f32_16x16x4f32(A2[s], HB[q][s], g, 0, 0, 0);
+            const f32x4 g = apply_block(E, HB, q);
             float v[4];
             float n2 = 0.0f;
 #pragma unroll
@@ -294,31 +221,25 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
                 v[r] = fmaf(-eta, g[r], WD[q][r]);
                 n2 = fmaf(v[r], v[r], n2);
             }
-            n2 += __shfl_xor(n2, 16, 64);
-            n2 += __shfl_xor(n2, 32, 64);
-            const float nrm = sqrtf(n2);
+            const float nrm = sqrtf(column_sum(n2));
             const float sc = thr > 0.0f ? 1.0f - thr / fmaxf(nrm, thr) : 1.0f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                WD[q][r] = sc * v[r];
-                sX[(4 * hi + r) * stride + c0 + 16 * q + lo] = WD[q][r];
-            }
+            for (int r = 0; r < 4; ++r) WD[q][r] = sc * v[r];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int c = 0; c < 16; ++c) WA[c] = sX[lo * stride + c0 + 16 * hi + c];
+        write_out_d(sX, stride, L, WD);
+        wave_lds_sync();
+        read_op_a(sX, stride, L, WA);
     }
     __syncthreads();
 
     // outputs from the planar W
+    const int tid = L.tid;
     float2* Wb = a.W + b * K * M;
     for (int e = tid; e < K * M; e += blockDim.x) {
         const int k = e / M, m = e - k * M;
         Wb[e] = make_float2(sX[k * stride + m], sX[(8 + k) * stride + m]);
     }
-    double* red = reinterpret_cast<double*>(sD);   // sD is free now: [nw] doubles
+    double* red = reinterpret_cast<double*>(sD);   // sD is free now
     if (a.l21) {
         double s = 0.0;
         for (int m = tid; m < M; m += blockDim.x) {
@@ -330,7 +251,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
             s += sqrt(p);
         }
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) red[wave] = s;
+        if (L.lane == 0) red[L.wave] = s;
         __syncthreads();
         if (tid == 0) {
             double t = 0.0;
@@ -339,38 +260,30 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
         }
         __syncthreads();
     }
-    if (a.rsum) {
-        // gains A = H W^T in FP64 on wave 0, entry (k, j) on lane 8 k + j
-        double* P = red;                        // [64] |A_kj|^2, after red is consumed
-        if (wave == 0) {
-            const int k = lane >> 3, j = lane & 7;
-            double gx = 0.0, gy = 0.0;
-            if (k < K && j < K)
-                for (int m = 0; m < M; ++m) {
-                    const float2 h = Hb[k * M + m];
-                    const double wx = sX[j * stride + m], wy = sX[(8 + j) * stride + m];
-                    gx += (double)h.x * wx - (double)h.y * wy;
-                    gy += (double)h.x * wy + (double)h.y * wx;
-                }
-            P[lane] = gx * gx + gy * gy;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane == 0) {
-                double r = 0.0;
-                for (int kk = 0; kk < K; ++kk) {
-                    double sig = 0.0, intf = 0.0;
-                    for (int jj = 0; jj < K; ++jj) (jj == kk ? sig : intf) += P[kk * 8 + jj];
-                    r += log2(1.0 + sig / (intf + a.sigma2));
-                }
-                a.rsum[b] = r;
+    if (a.rsum && L.wave == 0) {
+        // gains A = H W^T in FP64, entry (k, j) on lane 8 k + j
+        double* P = red;
+        const int k = L.lane >> 3, j = L.lane & 7;
+        double gx = 0.0, gy = 0.0;
+        if (k < K && j < K)
+            for (int m = 0; m < M; ++m) {
+                const float2 h = Hb[k * M + m];
+                const double wx = sX[j * stride + m], wy = sX[(8 + j) * stride + m];
+                gx += (double)h.x * wx - (double)h.y * wy;
+                gy += (double)h.x * wy + (double)h.y * wx;
             }
+        P[L.lane] = gx * gx + gy * gy;
+        wave_lds_sync();
+        if (L.lane == 0) {
+            double r = 0.0;
+            for (int kk = 0; kk < K; ++kk) {
+                double sig = 0.0, intf = 0.0;
+                for (int jj = 0; jj < K; ++jj) (jj == kk ? sig : intf) += P[kk * 8 + jj];
+                r += log2(1.0 + sig / (intf + a.sigma2));
+            }
+            a.rsum[b] = r;
         }
     }
-}
-
-size_t pgd_mfma_lds_bytes(int nw) {
-    return sizeof(float) * (16 * (size_t)(64 * nw + 4) + 2 * (size_t)nw * 16 * 17);
 }
 
 }  // namespace

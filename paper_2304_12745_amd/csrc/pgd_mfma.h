@@ -1,0 +1,155 @@
+// Register layouts and building blocks shared by the PGD / unfolded-PGD
+// kernels that run the layer's two complex products on
+// v_mfma_f32_16x16x4_f32 (K <= 8 users).
+//
+// Real embedding.  A K x M complex matrix X is held as 16 real rows
+// X16 = [Xr; Xi] (rows K..7 and 8+K..15 are zero).  Then, with H16 = [Hr; Hi]:
+//   D1 = X16 H16^T (16 x 16)  gives A = X H^T as
+//        Ar = D1[a][b] - D1[8+a][8+b],  Ai = D1[a][8+b] + D1[8+a][b];
+//   with E = [[Br, Bi], [Bi, -Br]] for a K x K complex B,
+//        E H16 = [Re(B H^*); Im(B H^*)]   (16 x M).
+// Both are exact 16 x 16 MFMA tiles at K = 8.
+//
+// One wave owns 64 antennas c0 .. c0+63.  Lane (hi, lo) = (lane >> 4, lane & 15).
+//   operand layout  "A":  16 floats, row lo at antennas c0 + 16 hi + c, c = 0..15;
+//                         serves as both operands of D1 (the antenna order
+//                         inside a sum is free).
+//   operand layout  "B2": [q][s], row 4 s + hi at antenna c0 + 16 q + lo
+//                         (B operand of E H16, block q of 16 antennas, k-step s).
+//   output layout   "D":  [q][r], row 4 hi + r at antenna c0 + 16 q + lo
+//                         (the MFMA result layout of E H16).
+//   E operand:            [s], E[lo][4 s + hi].
+// MFMA 16x16x4 f32: A[i][k] in lane 16 k + i, B[k][j] in lane 16 k + j,
+// D[i][j] in lane 16 (i / 4) + j, register i % 4.
+#pragma once
+
+#include "dmimo_internal.h"
+
+namespace dmimo {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPgdMfmaMaxWaves = 4;     // 256 antennas
+constexpr int kPartFloats = 16 * 17;    // one wave's D1 partial, padded rows
+
+// Planar LDS image: row p * 8 + k holds part p (0 re, 1 im) of row k.  Row
+// stride 64 nw + 4 floats puts the four 16-lane groups of a wave on distinct banks.
+__device__ __forceinline__ int pl_stride(int nw) { return 64 * nw + 4; }
+
+struct PgdLane {
+    int tid, wave, lane, lo, hi, c0;
+    __device__ PgdLane() {
+        tid = threadIdx.x;
+        wave = tid >> 6;
+        lane = tid & 63;
+        lo = lane & 15;
+        hi = lane >> 4;
+        c0 = 64 * wave;
+    }
+};
+
+// X (K x M, complex64, row-major) into the planar image, zero padded to
+// 8 x 64 nw, optionally conjugated.  All threads of the block take part.
+__device__ __forceinline__ void load_planar(float* sX, int stride, int nw, const float2* X, int K,
+                                            int M, bool conj) {
+    const int ncol = 64 * nw;
+    for (int e = threadIdx.x; e < 8 * ncol; e += blockDim.x) {
+        const int k = e / ncol, m = e - k * ncol;
+        float2 x = make_float2(0.f, 0.f);
+        if (k < K && m < M) x = X[k * M + m];
+        sX[k * stride + m] = x.x;
+        sX[(8 + k) * stride + m] = conj ? -x.y : x.y;
+    }
+}
+
+__device__ __forceinline__ void read_op_a(const float* sX, int stride, const PgdLane& L, float (&XA)[16]) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) XA[c] = sX[L.lo * stride + L.c0 + 16 * L.hi + c];
+}
+
+__device__ __forceinline__ void read_op_b2(const float* sX, int stride, const PgdLane& L, float (&XB)[4][4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) XB[q][s] = sX[(4 * s + L.hi) * stride + L.c0 + 16 * q + L.lo];
+}
+
+__device__ __forceinline__ void read_out_d(const float* sX, int stride, const PgdLane& L, float (&XD)[4][4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) XD[q][r] = sX[(4 * L.hi + r) * stride + L.c0 + 16 * q + L.lo];
+}
+
+__device__ __forceinline__ void write_out_d(float* sX, int stride, const PgdLane& L, const float (&XD)[4][4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sX[(4 * L.hi + r) * stride + L.c0 + 16 * q + L.lo] = XD[q][r];
+}
+
+// Orders this wave's LDS writes before its later LDS reads of other lanes' data.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// This wave's share of D1 = X16 H16^T over its 64 antennas.
+__device__ __forceinline__ f32x4 d1_partial(const float (&XA)[16], const float (&HA)[16]) {
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 16; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(XA[c], HA[c], d, 0, 0, 0);
+    return d;
+}
+
+__device__ __forceinline__ void put_partial(float* part, const PgdLane& L, f32x4 d) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[(4 * L.hi + r) * 17 + L.lo] = d[r];
+}
+
+// E operand of B = (X H^T) - diag(dg) from the nw partials of D1 (summed in
+// wave order); dg is this lane's diagonal entry d[lo & 7], zero for no shift.
+__device__ __forceinline__ void embed_operand(const float* parts, int nw, const PgdLane& L, float dg,
+                                              float (&E)[4]) {
+    const int ia = L.lo & 7;
+    const bool itop = L.lo < 8;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int l = 4 * s + L.hi;
+        const int lb = l & 7;
+        const bool ltop = l < 8;
+        float v = 0.0f;
+        if (itop == ltop) {          // +-(Br)[ia][lb]
+            for (int p = 0; p < nw; ++p)
+                v += parts[p * kPartFloats + ia * 17 + lb] - parts[p * kPartFloats + (8 + ia) * 17 + 8 + lb];
+            if (ia == lb) v -= dg;
+            if (!itop) v = -v;
+        } else {                     // Bi[ia][lb]
+            for (int p = 0; p < nw; ++p)
+                v += parts[p * kPartFloats + ia * 17 + 8 + lb] + parts[p * kPartFloats + (8 + ia) * 17 + lb];
+        }
+        E[s] = v;
+    }
+}
+
+// Block q of E H16 = [Re(B H^*); Im(B H^*)] in the output layout.
+__device__ __forceinline__ f32x4 apply_block(const float (&E)[4], const float (&HB)[4][4], int q) {
+    f32x4 g = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) g = __builtin_amdgcn_mfma_f32_16x16x4f32(E[s], HB[q][s], g, 0, 0, 0);
+    return g;
+}
+
+// Sum over the four lanes of an antenna column (hi = 0..3).
+__device__ __forceinline__ float column_sum(float x) {
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
+inline size_t pgd_mfma_lds_bytes(int nw) {
+    return sizeof(float) * (16 * (size_t)(64 * nw + 4) + 2 * (size_t)nw * kPartFloats);
+}
+
+}  // namespace dmimo

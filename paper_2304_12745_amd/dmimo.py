@@ -60,6 +60,12 @@ _SIGS = {
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
     "dmimo_pgd": [_i32, _i32, _i32, _vp, _vp, _f64, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "dmimo_ufpgd_workspace_size": [_i32, _i32, _i32, _i32],
+    "dmimo_ufpgd_grad": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _i32,
+                         _vp, _vp, _vp, _vp, _sz, _vp],
+    "dmimo_ufpgd_train": [_i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _vp, _vp,
+                          ctypes.c_int64, ctypes.c_void_p, _i32, _i32, _vp, _vp, _i32, _vp, _sz,
+                          _vp],
     "dmimo_server_create": [_i32, _sz, _i32, ctypes.POINTER(ctypes.c_void_p)],
     "dmimo_server_add_deployment": [_vp, ctypes.POINTER(ChannelParams), _i32, _vp,
                                     ctypes.POINTER(_i32)],
@@ -77,7 +83,7 @@ _SIGS = {
     "dmimo_last_error": [],
     "dmimo_version": [],
 }
-_RESTYPES = {"dmimo_workspace_size": _sz, "dmimo_status_string": ctypes.c_char_p,
+_RESTYPES = {"dmimo_workspace_size": _sz, "dmimo_ufpgd_workspace_size": _sz, "dmimo_status_string": ctypes.c_char_p,
              "dmimo_last_error": ctypes.c_char_p, "dmimo_version": ctypes.c_char_p}
 
 
@@ -316,6 +322,123 @@ def pgd(H, lambdas, etas, gamma_lin=None, sigma2=1.0, W0=None, prec="f32", out=N
                            _ptr(W0), _prec(prec), _ptr(out.W), _ptr(out.l21), _ptr(out.rsum),
                            _stream(stream)), "dmimo_pgd")
     return out
+
+
+# ---------------------------------------------------------------------------
+# unsupervised training of the unfolded network
+# ---------------------------------------------------------------------------
+
+LAM_COST = 1.0 / 15.0     # the cost's lambda in the paper's simulations
+
+
+class AdamParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+def ufpgd_workspace_size(B: int, K: int, M: int, layers: int) -> int:
+    return int(lib().dmimo_ufpgd_workspace_size(B, K, M, layers))
+
+
+def _gamma(gamma_lin, K):
+    if gamma_lin is None:
+        return None
+    return (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+
+
+def _f64_dev(x, dev):
+    import torch
+    t = x if torch.is_tensor(x) else torch.tensor(list(x), dtype=torch.float64)
+    return t.to(device=dev, dtype=torch.float64).contiguous()
+
+
+@dataclass
+class UfpgdGrad:
+    cost: object     # [B]
+    dlam: object     # [B][I] or None
+    deta: object
+
+
+def ufpgd_grad(H, lambdas, etas, gamma_lin=None, sigma2=1.0, lam_c=LAM_COST, idx=None,
+               want_grad=True, ws=None, stream=None) -> UfpgdGrad:
+    """Per-channel cost and gradients of the unfolded network (dmimo_ufpgd_grad).
+    H complex64 [n][K][M]; idx optional device int32 [B] selecting channels."""
+    import torch
+    n, K, M = H.shape
+    dev = H.device
+    B = n if idx is None else idx.numel()
+    lam = _f64_dev(lambdas, dev)
+    eta = _f64_dev(etas, dev)
+    I = lam.numel()
+    if eta.numel() != I:
+        raise ValueError("lambdas and etas need the same length")
+    out = UfpgdGrad(torch.empty((B,), dtype=torch.float64, device=dev),
+                    torch.empty((B, I), dtype=torch.float64, device=dev) if want_grad else None,
+                    torch.empty((B, I), dtype=torch.float64, device=dev) if want_grad else None)
+    nbytes = 0
+    if want_grad:
+        nbytes = ufpgd_workspace_size(max(B, 1), K, M, I)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=dev)
+    out._keep = (lam, eta, ws, idx)
+    _check(lib().dmimo_ufpgd_grad(B, n, K, M, _ptr(H), _ptr(idx), _gamma(gamma_lin, K),
+                                  float(sigma2), float(lam_c), I, _ptr(lam), _ptr(eta), F32,
+                                  _ptr(out.cost), _ptr(out.dlam), _ptr(out.deta),
+                                  _ptr(ws) if want_grad else None, nbytes,
+                                  _stream(stream)), "dmimo_ufpgd_grad")
+    return out
+
+
+class UfpgdState:
+    """Trainable parameters lambda_i, eta_i and the Adam moments, on the device."""
+
+    def __init__(self, lambdas, etas, device):
+        import torch
+        self.lambdas = _f64_dev(lambdas, device)
+        self.etas = _f64_dev(etas, device)
+        I = self.lambdas.numel()
+        if self.etas.numel() != I:
+            raise ValueError("lambdas and etas need the same length")
+        self.m = torch.zeros(2 * I, dtype=torch.float64, device=device)
+        self.v = torch.zeros(2 * I, dtype=torch.float64, device=device)
+        self.t = 0
+
+    @property
+    def layers(self) -> int:
+        return self.lambdas.numel()
+
+    def clone(self) -> "UfpgdState":
+        c = UfpgdState(self.lambdas.clone(), self.etas.clone(), self.lambdas.device)
+        c.m.copy_(self.m)
+        c.v.copy_(self.v)
+        c.t = self.t
+        return c
+
+
+def ufpgd_train(H, state: UfpgdState, idx, gamma_lin=None, sigma2=1.0, lam_c=LAM_COST, lr=1e-3,
+                beta1=0.9, beta2=0.999, eps=1e-8, batch_cost=None, ws=None, stream=None):
+    """Run idx.shape[0] Adam steps (dmimo_ufpgd_train); idx device int32
+    [steps][batch].  Updates `state` in place; returns the per-step mean batch cost."""
+    import torch
+    n, K, M = H.shape
+    dev = H.device
+    steps, batch = idx.shape
+    idx = idx.to(device=dev, dtype=torch.int32).contiguous()
+    if batch_cost is None:
+        batch_cost = torch.empty((steps,), dtype=torch.float64, device=dev)
+    nbytes = ufpgd_workspace_size(batch, K, M, state.layers)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=dev)
+    opt = AdamParams(lr, beta1, beta2, eps)
+    _check(lib().dmimo_ufpgd_train(n, K, M, _ptr(H), _gamma(gamma_lin, K), float(sigma2),
+                                   float(lam_c), state.layers, _ptr(state.lambdas),
+                                   _ptr(state.etas), _ptr(state.m), _ptr(state.v), state.t,
+                                   ctypes.addressof(opt), batch, steps, _ptr(idx),
+                                   _ptr(batch_cost), F32, _ptr(ws), nbytes, _stream(stream)),
+           "dmimo_ufpgd_train")
+    state.t += steps
+    state._keep = (idx, ws, batch_cost)
+    return batch_cost
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,131 @@
+"""GPU parity of unfolded-PGD training (dmimo_ufpgd_grad / dmimo_ufpgd_train)
+against the FP64 training oracle (Sec. V; Sec. VI-A).
+
+FP32 forward and reverse pass on the GPU against FP64 in the oracle.  The
+reverse pass contracts (it multiplies by I - eta H^T H^* with eta <= 1/L and by
+the prox Jacobian), so FP32 rounding stays near 1e-6 relative; gradients are
+compared per channel against 2e-4 of the largest entry of that channel's row.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import pgd_oracle as P  # noqa: E402
+from oracle import ufpgd_oracle as U  # noqa: E402
+from paper_2304_12745_amd import workloads as WL  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+LAM_C = 1.0 / 15.0
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2304_12745_amd import dmimo
+    dmimo.lib()
+    return dmimo
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _schedule(rng, I, K, M, zero_some=True):
+    L = P.mp_edge(K, M)
+    lams = rng.uniform(0.0, 3.0, I)
+    if zero_some:
+        lams[rng.choice(I, size=max(1, I // 4), replace=False)] = 0.0
+    etas = rng.uniform(0.5 / L, 1.0 / L, I)
+    return lams, etas
+
+
+def _check_grads(name, got, ref, rel=2e-4):
+    scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-12
+    err = (np.abs(got - ref) / scale).max()
+    say(f"    {name}: max err / row scale {err:.2e}")
+    assert err < rel
+
+
+def test_grad_matches_oracle_paper_shape(D):
+    say("ufpgd_grad K=8 M=64 I=20, 32 channels, schedule with zero lambdas")
+    K, M, I = 8, 64, 20
+    w = WL.paper_workload(seed=41, B=32)
+    H = w.H.astype(np.complex64)
+    lams, etas = _schedule(np.random.default_rng(1), I, K, M)
+    r = D.ufpgd_grad(torch.from_numpy(H).cuda(), lams, etas, w.gamma_lin, 1.0, LAM_C)
+    torch.cuda.synchronize()
+    C, dl, de = U.grad(H.astype(np.complex128), w.gamma_lin, 1.0, lams, etas, LAM_C)
+    np.testing.assert_allclose(r.cost.cpu().numpy(), C, rtol=2e-5)
+    _check_grads("dlam", r.dlam.cpu().numpy(), dl)
+    _check_grads("deta", r.deta.cpu().numpy(), de)
+    # cost-only mode gives the same cost
+    r0 = D.ufpgd_grad(torch.from_numpy(H).cuda(), lams, etas, w.gamma_lin, 1.0, LAM_C,
+                      want_grad=False)
+    np.testing.assert_array_equal(r0.cost.cpu().numpy(), r.cost.cpu().numpy())
+
+
+@pytest.mark.parametrize("K,M,I", [(3, 100, 7), (8, 256, 12), (5, 37, 9), (1, 64, 5), (8, 129, 20)])
+def test_grad_shapes_and_index_selection(D, K, M, I):
+    say(f"ufpgd_grad K={K} M={M} I={I}, idx selection with repeats")
+    rng = np.random.default_rng(K * 1000 + M)
+    n = 11
+    H = WL.complex_normal(rng, (n, K, M)).astype(np.complex64)
+    gamma = rng.uniform(1.0, 20.0, K)
+    sigma2 = 0.7
+    idx = np.array([3, 0, 10, 3, 7, 1], dtype=np.int32)
+    lams, etas = _schedule(rng, I, K, M)
+    r = D.ufpgd_grad(torch.from_numpy(H).cuda(), lams, etas, gamma, sigma2, 0.2,
+                     idx=torch.from_numpy(idx).cuda())
+    C, dl, de = U.grad(H[idx].astype(np.complex128), gamma, np.sqrt(sigma2), lams, etas, 0.2)
+    np.testing.assert_allclose(r.cost.cpu().numpy(), C, rtol=2e-5)
+    _check_grads("dlam", r.dlam.cpu().numpy(), dl)
+    _check_grads("deta", r.deta.cpu().numpy(), de)
+    g = r.dlam.cpu().numpy()
+    np.testing.assert_array_equal(g[0], g[3])            # the same channel twice
+
+
+def test_out_of_range_index_is_flagged_and_isolated(D):
+    say("ufpgd_grad with one idx entry out of range")
+    K, M, I = 8, 64, 4
+    rng = np.random.default_rng(5)
+    H = WL.complex_normal(rng, (4, K, M)).astype(np.complex64)
+    lams, etas = _schedule(rng, I, K, M, zero_some=False)
+    Hd = torch.from_numpy(H).cuda()
+    good = D.ufpgd_grad(Hd, lams, etas, None, 1.0, LAM_C, idx=torch.tensor([2, 1], dtype=torch.int32).cuda())
+    mixed = D.ufpgd_grad(Hd, lams, etas, None, 1.0, LAM_C,
+                         idx=torch.tensor([2, 4, 1], dtype=torch.int32).cuda())
+    c = mixed.cost.cpu().numpy()
+    assert np.isnan(c[1]) and np.all(mixed.dlam[1].cpu().numpy() == 0)
+    np.testing.assert_array_equal(c[[0, 2]], good.cost.cpu().numpy())
+    np.testing.assert_array_equal(mixed.deta.cpu().numpy()[[0, 2]], good.deta.cpu().numpy())
+
+
+def test_train_steps_match_oracle(D):
+    say("ufpgd_train: 10 Adam steps, batch 64, paper shape, vs the oracle")
+    K, M, I = 8, 64, 20
+    w = WL.paper_workload(seed=42, B=512)
+    H = w.H.astype(np.complex64)
+    rng = np.random.default_rng(3)
+    batches = np.stack([rng.permutation(512)[:64] for _ in range(10)]).astype(np.int32)
+    lams, etas = U.initial_params(I, K, M)
+    st = D.UfpgdState(lams, etas, torch.device("cuda"))
+    bc = D.ufpgd_train(torch.from_numpy(H).cuda(), st, torch.from_numpy(batches).cuda(),
+                       w.gamma_lin, 1.0, LAM_C, lr=1e-3)
+    torch.cuda.synchronize()
+    lo, eo, opt, costs = U.train_steps(H.astype(np.complex128), w.gamma_lin, 1.0, LAM_C, lams,
+                                       etas, list(batches), lr=1e-3)
+    say(f"    lambda max |diff| {np.abs(st.lambdas.cpu().numpy() - lo).max():.2e}, "
+        f"eta max |diff| {np.abs(st.etas.cpu().numpy() - eo).max():.2e}")
+    np.testing.assert_allclose(bc.cpu().numpy(), costs, rtol=2e-5)
+    np.testing.assert_allclose(st.lambdas.cpu().numpy(), lo, atol=1e-6)
+    np.testing.assert_allclose(st.etas.cpu().numpy(), eo, atol=1e-9)
+    np.testing.assert_allclose(st.m.cpu().numpy(), opt.m, rtol=1e-3, atol=1e-9)
+    assert st.t == 10
+    L = P.mp_edge(K, M)
+    assert np.all(st.lambdas.cpu().numpy() >= 0)
+    assert np.all(st.etas.cpu().numpy() <= 1 / L) and np.all(st.etas.cpu().numpy() >= 0.5 / L)
