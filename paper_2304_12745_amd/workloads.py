@@ -142,6 +142,26 @@ def paper_workload(seed=0, B=5000, K=8, M=64, gamma_db=10.0, sigma=1.0,
                     precoders=("mr", "zf"))
 
 
+@dataclass
+class UfpgdDatasets:
+    train: np.ndarray     # complex64 [n_train][K][M]
+    val: np.ndarray
+    test: np.ndarray
+    gamma_lin: np.ndarray
+    sigma2: float
+
+
+def ufpgd_datasets(n_train=100000, n_val=5000, n_test=5000, K=8, M=64, gamma_db=10.0, seed=0):
+    """Training, validation and test channels of the paper's unfolding
+    experiment (Sec. VI-A): independent Rayleigh draws H ~ CN(0, 1), drawn
+    in that order from one seeded generator."""
+    rng = np.random.default_rng(1000 + seed)
+    tr = complex_normal(rng, (n_train, K, M), np.complex64)
+    va = complex_normal(rng, (n_val, K, M), np.complex64)
+    te = complex_normal(rng, (n_test, K, M), np.complex64)
+    return UfpgdDatasets(tr, va, te, np.full(K, 10.0 ** (gamma_db / 10.0)), 1.0)
+
+
 def focus_workload(seed=1, M=16, nx=64, ny=64):
     """Single-room MR focusing map at 920 MHz, computed in FP64."""
     rng = np.random.default_rng(seed)

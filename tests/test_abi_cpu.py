@@ -161,3 +161,56 @@ def test_pgd_validation(lib):
     assert pgd(W=None) == 1
     assert pgd(lam=None) == 1
     assert pgd(B=0, H=None, W=None, gamma=g) == 0
+
+
+def test_ufpgd_validation(lib):
+    assert lib.dmimo_ufpgd_workspace_size(64, 8, 64, 20) > 64 * 20 * 64 * 16 * 4
+    assert lib.dmimo_ufpgd_workspace_size(64, 9, 64, 20) == 0
+    assert lib.dmimo_ufpgd_workspace_size(64, 8, 257, 20) == 0
+    ws_need = lib.dmimo_ufpgd_workspace_size(4, 8, 64, 3)
+
+    def grad(B=4, n=4, K=8, M=64, H=FAKE, idx=None, sigma2=1.0, lam_c=0.1, layers=3, lam=FAKE,
+             eta=FAKE, prec=D.F32, cost=FAKE, dl=FAKE, de=FAKE, ws=FAKE, nbytes=ws_need):
+        return lib.dmimo_ufpgd_grad(B, n, K, M, H, idx, None, sigma2, lam_c, layers, lam, eta,
+                                    prec, cost, dl, de, ws, nbytes, None)
+
+    assert grad(K=0) == 2
+    assert grad(M=300) == 2
+    assert grad(K=12) == 6                 # valid for dmimo_pgd, not provided for training
+    assert grad(K=20) == 2
+    assert grad(B=-1) == 2
+    assert grad(n=3) == 2                  # without idx, n_channels >= B
+    assert grad(prec=D.F64) == 6
+    assert grad(prec=7) == 3
+    assert grad(sigma2=-1.0) == 1
+    assert grad(lam_c=float("inf")) == 1
+    assert grad(de=None) == 1              # dlam without deta
+    assert grad(H=None) == 1
+    assert grad(lam=None) == 1
+    assert grad(cost=None, dl=None, de=None) == 1
+    assert grad(nbytes=ws_need - 1) == 4
+    assert grad(ws=None) == 4
+    assert grad(B=0, H=None, cost=None, dl=None, de=None, ws=None) == 0
+
+    opt = D.AdamParams(1e-3, 0.9, 0.999, 1e-8)
+    ws_b = lib.dmimo_ufpgd_workspace_size(64, 8, 64, 20)
+
+    def train(n=100, K=8, M=64, layers=20, batch=64, steps=5, t0=0, o=opt, idx=FAKE,
+              nbytes=ws_b, lam=FAKE):
+        return lib.dmimo_ufpgd_train(n, K, M, FAKE, None, 1.0, 0.1, layers, lam, FAKE, FAKE, FAKE,
+                                     t0, ctypes.addressof(o) if o is not None else None, batch,
+                                     steps, idx, None, D.F32, FAKE, nbytes, None)
+
+    assert train(layers=0) == 2
+    assert train(batch=0) == 2
+    assert train(steps=-1) == 2
+    assert train(t0=-1) == 2
+    assert train(n=0) == 2
+    assert train(o=None) == 1
+    assert train(o=D.AdamParams(0.0, 0.9, 0.999, 1e-8)) == 1
+    assert train(o=D.AdamParams(1e-3, 1.0, 0.999, 1e-8)) == 1
+    assert train(o=D.AdamParams(1e-3, 0.9, 0.999, 0.0)) == 1
+    assert train(idx=None) == 1
+    assert train(lam=None) == 1
+    assert train(nbytes=ws_b - 1) == 4
+    assert train(steps=0, idx=None, lam=None) == 0
