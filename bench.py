@@ -102,6 +102,7 @@ def parse_args():
     p.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (1/s)")
     p.add_argument("--serve-prec", default="f32", choices=["f32", "f16x3", "bf16x3"])
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
+    p.add_argument("--no-pgd", action="store_true", help="skip the PGD / unfolded-PGD phase")
     return p.parse_args()
 
 
@@ -209,6 +210,8 @@ def main():
         out["mixed"] = mixed
     if args.serve_seconds > 0:
         out["serving"] = serving_phase(args, D, WL, torch)
+    if not args.no_pgd:
+        out["pgd"] = pgd_phase(args, D, WL, torch)
     if not args.no_cpu and args.cpu_seconds > 0:
         out["cpu_baseline"], out["err_db"] = cpu_baseline(w, bf, maps, args.cpu_seconds)
 
@@ -338,6 +341,101 @@ def serving_phase(args, D, WL, torch):
         "offered_Gh_per_s": round(offered / args.serve_seconds / 1e9, 2),
         "launches": stats["launches"],
     }
+
+
+def pgd_phase(args, D, WL, torch):
+    """The paper's solver on its own workload (Sec. VI): 5000 Rayleigh channels
+    H ~ CN(0, 1), K = 8, M = 64, gamma = 10 dB, sigma = 1, W(0) = H^*.
+
+    * UfPGD inference, 20 layers (one dmimo_pgd launch over all channels);
+    * PGD, 5000 iterations, lambda = 1/15, eta = 1/L~ (the paper's reference
+      solution), with its mean PCG against ZF and sum rate;
+    * ZF with the paper's scaling (the PCG reference), dmimo_beamform;
+    * one training step of the unfolded network (batch 64, 20 layers, forward
+      + reverse pass + Adam), dmimo_ufpgd_train;
+    * the FP64 oracle's UfPGD inference, single-threaded, on a sample.
+    HIP events on the launching stream time every call.  The roofline is that
+    of pgd_mfma_kernel: 16 K^2 M real flops per layer and channel (the two
+    complex K x K x M products of the layer) on FP32 MFMA."""
+    import math
+
+    import numpy as np
+
+    K, M, B, I = 8, 64, 5000, 20
+    L = (math.sqrt(K) + math.sqrt(M)) ** 2
+    w = WL.paper_workload(seed=0, B=B)
+    H = torch.from_numpy(w.H.astype(np.complex64)).cuda()
+    g = w.gamma_lin
+
+    def timed(fn, reps, warm=2):
+        for _ in range(warm):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        torch.cuda.synchronize()
+        for r in range(reps):
+            ev[2 * r].record()
+            fn()
+            ev[2 * r + 1].record()
+        torch.cuda.synchronize()
+        return sum(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps)) / reps
+
+    lam20 = torch.full((I,), 1.0 / 15.0, dtype=torch.float64, device="cuda")
+    eta20 = torch.full((I,), 1.0 / L, dtype=torch.float64, device="cuda")
+    out20 = D.pgd(H, lam20, eta20, g, 1.0)
+    ms20 = timed(lambda: D.pgd(H, lam20, eta20, g, 1.0, out=out20), 50)
+    lam5k = torch.full((5000,), 1.0 / 15.0, dtype=torch.float64, device="cuda")
+    eta5k = torch.full((5000,), 1.0 / L, dtype=torch.float64, device="cuda")
+    out5k = D.pgd(H, lam5k, eta5k, g, 1.0)
+    ms5k = timed(lambda: D.pgd(H, lam5k, eta5k, g, 1.0, out=out5k), 3, warm=1)
+    zf = D.beamform(H, "zf", g, 1.0, 0.0, "f32")
+    mszf = timed(lambda: D.beamform(H, "zf", g, 1.0, 0.0, "f32", out=zf), 20)
+    pcg5k = (zf.l21 / out5k.l21).mean().item()
+
+    Htr = torch.from_numpy(WL.complex_normal(np.random.default_rng(9), (20000, K, M),
+                                             np.complex64)).cuda()
+    st = D.UfpgdState([1.0 / 15.0] * I, [1.0 / L] * I, torch.device("cuda"))
+    rng = np.random.default_rng(10)
+    steps = 300
+    idx = torch.from_numpy(np.stack([rng.permutation(20000)[:64] for _ in range(steps)])
+                           .astype(np.int32)).cuda()
+    ws = torch.empty((D.ufpgd_workspace_size(64, K, M, I),), dtype=torch.uint8, device="cuda")
+    ms_train = timed(lambda: D.ufpgd_train(Htr, st, idx, g, 1.0, ws=ws), 3, warm=1) / steps
+
+    flops20 = 16 * K * K * M * I * B
+    achieved = flops20 / (ms20 * 1e-3) / 1e12
+    res = {
+        "workload": f"paper: {B} Rayleigh channels CN(0,1), K={K}, M={M}, gamma 10 dB, sigma 1",
+        "ufpgd20_ms": round(ms20, 4),
+        "ufpgd20_channels_per_s": round(B / (ms20 * 1e-3)),
+        "pgd5000_ms": round(ms5k, 3),
+        "pgd5000_mean_pcg": round(pcg5k, 4),
+        "pgd5000_mean_rsum": round(out5k.rsum.mean().item(), 4),
+        "zf_ms": round(mszf, 4),
+        "train_step_ms": round(ms_train, 4),
+        "train_step": "batch 64, 20 layers: forward + reverse pass + Adam + projections",
+        "roofline": {"bound": "mfma", "kernel": "pgd_mfma_kernel", "unit": "TFLOP/s",
+                     "achieved": round(achieved, 3), "peak": MFMA_F32_PEAK / 1e12,
+                     "frac": round(achieved * 1e12 / MFMA_F32_PEAK, 4),
+                     "flops_per_launch": flops20, "launch_ms": round(ms20, 4),
+                     "pgd5000_frac": round(16 * K * K * M * 5000 * B / (ms5k * 1e-3)
+                                           / MFMA_F32_PEAK, 4)},
+    }
+    if not args.no_cpu and args.cpu_seconds > 0:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import pgd_oracle as P
+        Hc = w.H.astype(np.complex128)
+        lam, eta = [1.0 / 15.0] * I, [1.0 / L] * I
+        n = 0
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < min(args.cpu_seconds, 5.0):
+                P.unfolded(Hc[n % B:n % B + 250], g, 1.0, lam, eta)
+                n += 250
+            el = time.perf_counter() - t0
+        res["cpu_oracle"] = {"ufpgd20_ms_per_5000": round(el / n * B * 1e3, 2), "cores": 1,
+                             "kind": "oracle", "sample": f"{n} channels in {el:.1f} s"}
+    return res
 
 
 def cpu_baseline(w, bf, maps, budget_s):

@@ -179,38 +179,40 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
 }
 
 
-__global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev a, int nw) {
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     extern __shared__ float smem[];
-    const int stride = pl_stride(nw);
+    const int stride = pl_stride(NW);
     float* sX = smem;                          // [16][stride]   H, then W
-    float* sD = smem + 16 * stride;            // [2][nw][16][17] D1 partials
+    float* sD = smem + 16 * stride;            // [2][NW][16][17] D1 partials
 
     const PgdLane L;
     const int64_t b = blockIdx.x;
     const int K = a.K, M = a.M;
     const float2* Hb = a.H + b * K * M;
 
-    load_planar(sX, stride, nw, Hb, K, M, false);
+    load_planar(sX, stride, NW, Hb, K, M, false);
     __syncthreads();
     float HA[16], HB[4][4];
     read_op_a(sX, stride, L, HA);
     read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    load_planar(sX, stride, nw, a.W0 ? a.W0 + b * K * M : Hb, K, M, a.W0 == nullptr);   // W(0) = W0 or H^*
+    load_planar(sX, stride, NW, a.W0 ? a.W0 + b * K * M : Hb, K, M, a.W0 == nullptr);   // W(0) = W0 or H^*
     __syncthreads();
     float WD[4][4], WA[16];
     read_out_d(sX, stride, L, WD);
     read_op_a(sX, stride, L, WA);
     const float dg = a.d[L.lo & 7];
 
+    int ph = 0;
     for (int layer = 0; layer < a.layers; ++layer) {
         const float eta = (float)a.etas[layer];
         const float thr = (float)(a.lambdas[layer] * a.etas[layer]);
-        float* part = sD + ((layer & 1) * nw + L.wave) * kPartFloats;
-        put_partial(part, L, d1_partial(WA, HA));
+        put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
         __syncthreads();
         float E[4];                            // (A - D), embedded
-        embed_operand(sD + (layer & 1) * nw * kPartFloats, nw, L, dg, E);
+        embed_operand<NW>(sD + ph * NW * kPartFloats, L, dg, E);
+        ph ^= 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const f32x4 g = apply_block(E, HB, q);
@@ -221,8 +223,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
                 v[r] = fmaf(-eta, g[r], WD[q][r]);
                 n2 = fmaf(v[r], v[r], n2);
             }
-            const float nrm = sqrtf(column_sum(n2));
-            const float sc = thr > 0.0f ? 1.0f - thr / fmaxf(nrm, thr) : 1.0f;
+            const float sc = prox_scale(col_norm(column_sum(n2)), thr);
 #pragma unroll
             for (int r = 0; r < 4; ++r) WD[q][r] = sc * v[r];
         }
@@ -230,6 +231,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
         wave_lds_sync();
         read_op_a(sX, stride, L, WA);
     }
+    if (a.rsum) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
     __syncthreads();
 
     // outputs from the planar W
@@ -239,7 +241,8 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
         const int k = e / M, m = e - k * M;
         Wb[e] = make_float2(sX[k * stride + m], sX[(8 + k) * stride + m]);
     }
-    double* red = reinterpret_cast<double*>(sD);   // sD is free now
+    // scratch for the reductions: the partial buffer of the other parity
+    double* red = reinterpret_cast<double*>(sD + (ph ^ 1) * NW * kPartFloats);
     if (a.l21) {
         double s = 0.0;
         for (int m = tid; m < M; m += blockDim.x) {
@@ -251,38 +254,30 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void pgd_mfma_kernel(PgdDev 
             s += sqrt(p);
         }
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (L.lane == 0) red[L.wave] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < nw; ++w) t += red[w];
-            a.l21[b] = t;
-        }
-        __syncthreads();
+        if (L.lane == 0) red[64 + L.wave] = s;
     }
     if (a.rsum && L.wave == 0) {
-        // gains A = H W^T in FP64, entry (k, j) on lane 8 k + j
-        double* P = red;
+        // gains G = H W^T = A^T with A = W H^T from the last MFMA pass:
+        // lane 8 k + j holds |G_kj|^2 = |A_jk|^2
         const int k = L.lane >> 3, j = L.lane & 7;
-        double gx = 0.0, gy = 0.0;
-        if (k < K && j < K)
-            for (int m = 0; m < M; ++m) {
-                const float2 h = Hb[k * M + m];
-                const double wx = sX[j * stride + m], wy = sX[(8 + j) * stride + m];
-                gx += (double)h.x * wx - (double)h.y * wy;
-                gy += (double)h.x * wy + (double)h.y * wx;
-            }
-        P[L.lane] = gx * gx + gy * gy;
-        wave_lds_sync();
-        if (L.lane == 0) {
-            double r = 0.0;
-            for (int kk = 0; kk < K; ++kk) {
-                double sig = 0.0, intf = 0.0;
-                for (int jj = 0; jj < K; ++jj) (jj == kk ? sig : intf) += P[kk * 8 + jj];
-                r += log2(1.0 + sig / (intf + a.sigma2));
-            }
-            a.rsum[b] = r;
+        red[L.lane] = (k < K && j < K) ? (double)gain_sq<NW>(sD + ph * NW * kPartFloats, j, k) : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0 && a.l21) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += red[64 + w];
+        a.l21[b] = t;
+    }
+    if (a.rsum && L.wave == 0) {
+        // user k = lane < K: log2(1 + SINR_k), then a sum over the 8 lanes
+        double r = 0.0;
+        if (L.lane < K) {
+            double sig = 0.0, intf = 0.0;
+            for (int jj = 0; jj < K; ++jj) (jj == L.lane ? sig : intf) += red[L.lane * 8 + jj];
+            r = log2(1.0 + sig / (intf + a.sigma2));
         }
+        for (int off = 4; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+        if (L.lane == 0) a.rsum[b] = r;
     }
 }
 
@@ -309,7 +304,13 @@ dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* ga
     dim3 grid((unsigned)B), block(kPgdThreads);
     if (K <= 8) {
         const int nw = (M + 63) / 64;
-        pgd_mfma_kernel<<<grid, dim3(64 * nw), pgd_mfma_lds_bytes(nw), s>>>(d, nw);
+        const size_t lds = pgd_mfma_lds_bytes(nw);
+        switch (nw) {
+            case 1: pgd_mfma_kernel<1><<<grid, dim3(64), lds, s>>>(d); break;
+            case 2: pgd_mfma_kernel<2><<<grid, dim3(128), lds, s>>>(d); break;
+            case 3: pgd_mfma_kernel<3><<<grid, dim3(192), lds, s>>>(d); break;
+            default: pgd_mfma_kernel<4><<<grid, dim3(256), lds, s>>>(d); break;
+        }
         return check_launch("pgd_mfma_kernel");
     }
     pgd_kernel<16><<<grid, block, 0, s>>>(d);

@@ -63,8 +63,16 @@ __device__ __forceinline__ void load_planar(float* sX, int stride, int nw, const
 }
 
 __device__ __forceinline__ void read_op_a(const float* sX, int stride, const PgdLane& L, float (&XA)[16]) {
+    // 16-byte aligned: stride and c0 + 16 hi are multiples of 4 floats
+    const float4* src = reinterpret_cast<const float4*>(sX + L.lo * stride + L.c0 + 16 * L.hi);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) XA[c] = sX[L.lo * stride + L.c0 + 16 * L.hi + c];
+    for (int t = 0; t < 4; ++t) {
+        const float4 v = src[t];
+        XA[4 * t] = v.x;
+        XA[4 * t + 1] = v.y;
+        XA[4 * t + 2] = v.z;
+        XA[4 * t + 3] = v.w;
+    }
 }
 
 __device__ __forceinline__ void read_op_b2(const float* sX, int stride, const PgdLane& L, float (&XB)[4][4]) {
@@ -108,29 +116,44 @@ __device__ __forceinline__ void put_partial(float* part, const PgdLane& L, f32x4
     for (int r = 0; r < 4; ++r) part[(4 * L.hi + r) * 17 + L.lo] = d[r];
 }
 
-// E operand of B = (X H^T) - diag(dg) from the nw partials of D1 (summed in
-// wave order); dg is this lane's diagonal entry d[lo & 7], zero for no shift.
-__device__ __forceinline__ void embed_operand(const float* parts, int nw, const PgdLane& L, float dg,
+// E operand of B = (X H^T) - diag(dg) from the NW partials of D1 (each
+// entry summed over the partials in wave order); dg is this lane's diagonal
+// entry d[lo & 7], zero for no shift.  Column l = 4 s + hi lies in the top
+// half exactly for s < 2, so the block of every entry is known per s.
+template <int NW>
+__device__ __forceinline__ void embed_operand(const float* parts, const PgdLane& L, float dg,
                                               float (&E)[4]) {
     const int ia = L.lo & 7;
     const bool itop = L.lo < 8;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const int l = 4 * s + L.hi;
-        const int lb = l & 7;
-        const bool ltop = l < 8;
-        float v = 0.0f;
-        if (itop == ltop) {          // +-(Br)[ia][lb]
-            for (int p = 0; p < nw; ++p)
-                v += parts[p * kPartFloats + ia * 17 + lb] - parts[p * kPartFloats + (8 + ia) * 17 + 8 + lb];
-            if (ia == lb) v -= dg;
-            if (!itop) v = -v;
-        } else {                     // Bi[ia][lb]
-            for (int p = 0; p < nw; ++p)
-                v += parts[p * kPartFloats + ia * 17 + 8 + lb] + parts[p * kPartFloats + (8 + ia) * 17 + lb];
+        const int lb = (4 * s + L.hi) & 7;
+        const bool same = (s < 2) == itop;          // +-(Br)[ia][lb], else Bi[ia][lb]
+        const int a1 = ia * 17 + (same ? lb : 8 + lb);
+        const int a2 = (8 + ia) * 17 + (same ? 8 + lb : lb);
+        float x = 0.0f, y = 0.0f;
+#pragma unroll
+        for (int p = 0; p < NW; ++p) {
+            x += parts[p * kPartFloats + a1];
+            y += parts[p * kPartFloats + a2];
         }
-        E[s] = v;
+        float v = same ? x - y : x + y;
+        if (same && ia == lb) v -= dg;
+        E[s] = (same && !itop) ? -v : v;
     }
+}
+
+// |A_jk|^2 of A = X H^T (j = row, k = column, both < 8) from the NW partials.
+template <int NW>
+__device__ __forceinline__ float gain_sq(const float* parts, int j, int k) {
+    float re = 0.0f, im = 0.0f;
+#pragma unroll
+    for (int p = 0; p < NW; ++p) {
+        const float* q = parts + p * kPartFloats;
+        re += q[j * 17 + k] - q[(8 + j) * 17 + 8 + k];
+        im += q[j * 17 + 8 + k] + q[(8 + j) * 17 + k];
+    }
+    return re * re + im * im;
 }
 
 // Block q of E H16 = [Re(B H^*); Im(B H^*)] in the output layout.
@@ -141,11 +164,23 @@ __device__ __forceinline__ f32x4 apply_block(const float (&E)[4], const float (&
     return g;
 }
 
-// Sum over the four lanes of an antenna column (hi = 0..3).
+// Sum over the four lanes of an antenna column (hi = 0..3), with the gfx950
+// row swaps: after permlane16_swap / permlane32_swap of x with itself the
+// two results of a lane are x of the lane and x of its partner in the other
+// row (16 apart) / half (32 apart).  Every lane of a column gets the same
+// bits: (x0 + x1) + (x2 + x3), each pair added in the same order.
 __device__ __forceinline__ float column_sum(float x) {
-    x += __shfl_xor(x, 16, 64);
-    x += __shfl_xor(x, 32, 64);
-    return x;
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
+// Column norm and prox scale 1 - thr / max(n, thr) (1 at thr = 0), with the
+// hardware square root and reciprocal (about 1 ulp each).
+__device__ __forceinline__ float col_norm(float n2) { return __builtin_amdgcn_sqrtf(n2); }
+__device__ __forceinline__ float prox_scale(float nrm, float thr) {
+    return thr > 0.0f ? 1.0f - thr * __builtin_amdgcn_rcpf(fmaxf(nrm, thr)) : 1.0f;
 }
 
 inline size_t pgd_mfma_lds_bytes(int nw) {

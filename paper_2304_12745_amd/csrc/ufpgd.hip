@@ -17,9 +17,11 @@
 //   dC/dlambda = eta dC/dt,  dC/deta = dC/deta_step + lambda dC/dt.
 // The reverse pass costs the same three MFMA products as two forward layers.
 //
-// ufpgd_adam_kernel: batch mean of the per-channel gradients (fixed order),
+// ufpgd_adam_kernel: batch mean of the per-channel gradients (fixed order,
+// one wave per parameter),
 // one Adam update (Kingma and Ba, Algorithm 1) of [lambda; eta] in FP64, then
 // the projections lambda >= 0 and eta in [1/(2 L~), 1/L~], L~ = (sqrt K + sqrt M)^2.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -50,7 +52,9 @@ __device__ __forceinline__ double wave_sum_d(double x) {
     return x;
 }
 
-__global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(UfpgdDev a, int nw) {
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
+    constexpr int nw = NW;
     extern __shared__ float smem[];
     const int stride = pl_stride(nw);
     float* sX = smem;                                   // [16][stride]
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
         put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial(WA, HA));
         __syncthreads();
         float E[4];
-        embed_operand(sD + ph * nw * kPartFloats, nw, L, dg, E);
+        embed_operand<NW>(sD + ph * nw * kPartFloats, L, dg, E);
         ph ^= 1;
         if (grad && L.wave == 0)
             *reinterpret_cast<float4*>(a.tapeE + ((b * I + i) * 64 + L.lane) * 4) =
@@ -108,8 +112,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
                 n2 = fmaf(v[r], v[r], n2);
             }
             if (grad) *reinterpret_cast<float4*>(tv + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
-            const float nrm = sqrtf(column_sum(n2));
-            const float sc = thr > 0.0f ? 1.0f - thr / fmaxf(nrm, thr) : 1.0f;
+            const float sc = prox_scale(col_norm(column_sum(n2)), thr);
 #pragma unroll
             for (int r = 0; r < 4; ++r) WD[q][r] = sc * v[r];
         }
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
         float n2 = 0.0f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) n2 = fmaf(WD[q][r], WD[q][r], n2);
-        nrm[q] = sqrtf(column_sum(n2));
+        nrm[q] = col_norm(column_sum(n2));
         if (L.hi == 0) l21 += nrm[q];
     }
     l21 = wave_sum_d(l21);
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
     put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial(WA, HA));
     __syncthreads();
     float E[4];
-    embed_operand(sD + ph * nw * kPartFloats, nw, L, dg, E);
+    embed_operand<NW>(sD + ph * nw * kPartFloats, L, dg, E);
     double fro = 0.0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) fro += (double)E[s] * E[s];
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const f32x4 g = apply_block(E, HB, q);
-        const float inv = nrm[q] > 0.0f ? a.lam_c / nrm[q] : 0.0f;
+        const float inv = nrm[q] > 0.0f ? a.lam_c * __builtin_amdgcn_rcpf(nrm[q]) : 0.0f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) Gb[q][r] = fmaf(2.0f, g[r], inv * WD[q][r]);
     }
@@ -176,9 +179,9 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
             }
             n2 = column_sum(n2);
             rho = column_sum(rho);
-            const float n = sqrtf(n2);
+            const float n = col_norm(n2);
             if (n > t) {
-                const float inv = 1.0f / n;
+                const float inv = __builtin_amdgcn_rcpf(n);
                 const float s = 1.0f - t * inv;
                 const float coef = t * rho * inv * inv * inv;
 #pragma unroll
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(64 * kPgdMfmaMaxWaves) void ufpgd_grad_kernel(Ufpgd
         if (L.lane == 0) sT[ph * nw + L.wave] = dtp;
         __syncthreads();
         float E2[4];                                     // A' = Gv H^T, embedded, no shift
-        embed_operand(sD + ph * nw * kPartFloats, nw, L, 0.0f, E2);
+        embed_operand<NW>(sD + ph * nw * kPartFloats, L, 0.0f, E2);
         if (L.wave == 0) {
             const float4 ee = *reinterpret_cast<const float4*>(a.tapeE + ((b * I + i) * 64 + L.lane) * 4);
             double de = (double)ee.x * E2[0] + (double)ee.y * E2[1] + (double)ee.z * E2[2] +
@@ -234,30 +237,39 @@ struct AdamDev {
     const double* cost; // [B]
 };
 
-__global__ __launch_bounds__(256) void ufpgd_adam_kernel(AdamDev a, int64_t t, double* batch_cost) {
+// One wave per parameter (waves stride over the 2I parameters): lanes sum
+// the batch entries b = lane, lane + 64, ... in order, then a fixed xor tree;
+// the result does not depend on timing.
+__device__ __forceinline__ double batch_mean(const double* src, int stride, int B, int lane) {
+    double s = 0.0;
+    for (int b = lane; b < B; b += 64) s += src[(int64_t)b * stride];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s / B;
+}
+
+__global__ __launch_bounds__(1024) void ufpgd_adam_kernel(AdamDev a, int64_t t, double* batch_cost) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int n = 2 * a.I;
     const double bc1 = 1.0 - pow(a.beta1, (double)t);
     const double bc2 = 1.0 - pow(a.beta2, (double)t);
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int j = wave; j < n; j += nwaves) {
         const bool is_lam = j < a.I;
         const int col = is_lam ? j : j - a.I;
-        const double* src = is_lam ? a.dlam : a.deta;
-        double g = 0.0;
-        for (int b = 0; b < a.B; ++b) g += src[(int64_t)b * a.I + col];
-        g /= a.B;
-        const double m = a.beta1 * a.m[j] + (1.0 - a.beta1) * g;
-        const double v = a.beta2 * a.v[j] + (1.0 - a.beta2) * g * g;
-        a.m[j] = m;
-        a.v[j] = v;
-        double* p = is_lam ? a.lambdas + col : a.etas + col;
-        double x = *p - a.lr * (m / bc1) / (sqrt(v / bc2) + a.eps);
-        x = is_lam ? fmax(x, 0.0) : fmin(fmax(x, a.eta_lo), a.eta_hi);
-        *p = x;
+        const double g = batch_mean((is_lam ? a.dlam : a.deta) + col, a.I, a.B, lane);
+        if (lane == 0) {
+            const double m = a.beta1 * a.m[j] + (1.0 - a.beta1) * g;
+            const double v = a.beta2 * a.v[j] + (1.0 - a.beta2) * g * g;
+            a.m[j] = m;
+            a.v[j] = v;
+            double* p = is_lam ? a.lambdas + col : a.etas + col;
+            double x = *p - a.lr * (m / bc1) / (sqrt(v / bc2) + a.eps);
+            x = is_lam ? fmax(x, 0.0) : fmin(fmax(x, a.eta_lo), a.eta_hi);
+            *p = x;
+        }
     }
-    if (threadIdx.x == 0 && batch_cost) {
-        double s = 0.0;
-        for (int b = 0; b < a.B; ++b) s += a.cost[b];
-        *batch_cost = s / a.B;
+    if (wave == nwaves - 1 && batch_cost) {
+        const double c = batch_mean(a.cost, 1, a.B, lane);
+        if (lane == 0) *batch_cost = c;
     }
 }
 
@@ -287,6 +299,17 @@ UfpgdWs ufpgd_ws_layout(int64_t B, int M, int layers) {
 }
 
 size_t ufpgd_lds_bytes(int nw) { return pgd_mfma_lds_bytes(nw) + sizeof(double) * 2 * nw; }
+
+void launch_grad(const UfpgdDev& d, int64_t B, int nw, hipStream_t s) {
+    const dim3 grid((unsigned)B);
+    const size_t lds = ufpgd_lds_bytes(nw);
+    switch (nw) {
+        case 1: ufpgd_grad_kernel<1><<<grid, dim3(64), lds, s>>>(d); break;
+        case 2: ufpgd_grad_kernel<2><<<grid, dim3(128), lds, s>>>(d); break;
+        case 3: ufpgd_grad_kernel<3><<<grid, dim3(192), lds, s>>>(d); break;
+        default: ufpgd_grad_kernel<4><<<grid, dim3(256), lds, s>>>(d); break;
+    }
+}
 
 UfpgdDev make_dev(const UfpgdArgs& g) {
     UfpgdDev d;
@@ -327,7 +350,7 @@ dmimo_status launch_ufpgd_grad(const UfpgdArgs& g, double* cost, double* dlam, d
         d.dlam = dlam;
         d.deta = deta;
     }
-    ufpgd_grad_kernel<<<dim3((unsigned)g.B), dim3(64 * nw), ufpgd_lds_bytes(nw), s>>>(d, nw);
+    launch_grad(d, g.B, nw, s);
     return check_launch("ufpgd_grad_kernel");
 }
 
@@ -360,11 +383,11 @@ dmimo_status launch_ufpgd_train(const UfpgdArgs& g, const UfpgdTrainArgs& t, voi
     a.dlam = d.dlam;
     a.deta = d.deta;
     a.cost = d.cost;
-    const size_t lds = ufpgd_lds_bytes(nw);
+    const int adam_threads = 64 * std::min(16, 2 * g.layers);
     for (int64_t step = 0; step < t.steps; ++step) {
         d.idx = t.idx + step * g.B;
-        ufpgd_grad_kernel<<<dim3((unsigned)g.B), dim3(64 * nw), lds, s>>>(d, nw);
-        ufpgd_adam_kernel<<<dim3(1), dim3(256), 0, s>>>(a, t.t0 + step + 1,
+        launch_grad(d, g.B, nw, s);
+        ufpgd_adam_kernel<<<dim3(1), dim3(adam_threads), 0, s>>>(a, t.t0 + step + 1,
                                                         t.batch_cost ? t.batch_cost + step : nullptr);
     }
     return check_launch("ufpgd_train");
