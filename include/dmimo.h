@@ -192,6 +192,33 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
                        const void* W0, int32_t prec, void* W, double* l21, double* rsum,
                        void* stream);
 
+/* PA-consumption-aware precoder of distributed deployments: eq. (optim1)
+ * (Sec. III) solved by PGD / unfolded PGD (Sec. IV-V) on channels of any
+ * scale and correlation, in the deployment's own units.  Per deployment:
+ *   s = RMS |h_km|, Hn = H / s, L = largest eigenvalue of Hn Hn^H (FP64
+ *   power iteration), the layers of dmimo_pgd on Hn with unit noise
+ *   (d_k = sqrt(gamma_k)), step eta_i = eta_rel[i] / L, threshold
+ *   lambdas[i] eta_i, from W(0) = Hn^*; then W = (sqrt(sigma2) / s) Wn.
+ * The back-mapping is exact for the constraint: H W^T = sqrt(sigma2) Hn Wn^T.
+ * lambdas keep the meaning they have for unit-variance channels (1/15 in
+ * Sec. VI-C); eta_rel = 1 is the largest step of Sec. IV.
+ *   H          device complex64 [B][K][M]; 1 <= K <= 16, 1 <= M <= 256.
+ *   gamma_lin  host [K] SINR targets (linear) or NULL (ones); sigma2 > 0.
+ *   lambdas, eta_rel  device FP64 [layers].
+ *   W          device complex64 [B][K][M] output.
+ *   p_ant      device FP64 [B][M] or NULL: p_m = sum_k |w_km|^2 (zero for
+ *              antennas the precoder switches off).
+ *   l21        device FP64 [B] or NULL: ||W||_{2,1} (consumed PA power / alpha).
+ *   sinr       device FP64 [B][K] or NULL; rsum device FP64 [B] or NULL.
+ *   ws         device workspace of dmimo_workspace_size(DMIMO_CALL_PA_PRECODER,
+ *              B, K, M, 0, DMIMO_F32) bytes.
+ * An all-zero channel gives W = 0.  FP32 only. */
+dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
+                               const double* gamma_lin, double sigma2, int32_t layers,
+                               const double* lambdas, const double* eta_rel, int32_t prec,
+                               void* W, double* p_ant, double* l21, double* sinr, double* rsum,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Unsupervised training of the unfolded network (Sec. V; Sec. VI-A).
  *
@@ -319,7 +346,7 @@ dmimo_status dmimo_server_stats(dmimo_server* srv, int64_t* completed, int64_t* 
 dmimo_status dmimo_server_destroy(dmimo_server* srv);
 
 enum { DMIMO_CALL_CHANNEL = 0, DMIMO_CALL_GRAM = 1, DMIMO_CALL_BEAMFORM_MR = 2,
-       DMIMO_CALL_BEAMFORM_ZF = 3, DMIMO_CALL_POWERMAP = 4 };
+       DMIMO_CALL_BEAMFORM_ZF = 3, DMIMO_CALL_POWERMAP = 4, DMIMO_CALL_PA_PRECODER = 5 };
 
 /* Workspace bytes a call needs (0 if none).  Pure host function. */
 size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32_t N,

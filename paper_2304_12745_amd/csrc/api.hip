@@ -158,6 +158,8 @@ size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32
             const size_t elem = prec == DMIMO_F64 ? 16 : 8;
             return align256((size_t)B * K * K * elem);
         }
+        case DMIMO_CALL_PA_PRECODER:
+            return align256((size_t)B * 2 * sizeof(double));
         default:
             return 0;
     }
@@ -308,6 +310,30 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
     if (layers > 0 && (!lambdas || !etas)) return fail(DMIMO_E_ARG, "pgd: NULL lambdas or etas");
     return launch_pgd(B, K, M, H, gamma_lin, sigma2, layers, lambdas, etas, W0, W, l21, rsum,
                       as_stream(stream));
+}
+
+dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
+                               const double* gamma_lin, double sigma2, int32_t layers,
+                               const double* lambdas, const double* eta_rel, int32_t prec,
+                               void* W, double* p_ant, double* l21, double* sinr, double* rsum,
+                               void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (B < 0 || layers < 0) return fail(DMIMO_E_SHAPE, "pa_precoder: B and layers must be >= 0");
+    if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "pa_precoder: K and M must be >= 1");
+    if (K > 16 || M > 256) return fail(DMIMO_E_SHAPE, "pa_precoder: K <= 16 and M <= 256");
+    if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "pa_precoder: unknown precision");
+    if (prec != DMIMO_F32) return fail(DMIMO_E_UNSUPPORTED, "pa_precoder: FP32 only");
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(DMIMO_E_ARG, "pa_precoder: sigma2 must be > 0");
+    for (int k = 0; gamma_lin && k < K; ++k)
+        if (!(gamma_lin[k] >= 0.0) || !std::isfinite(gamma_lin[k]))
+            return fail(DMIMO_E_ARG, "pa_precoder: gamma_lin must be finite and >= 0");
+    if (B == 0) return DMIMO_OK;
+    if (!H || !W) return fail(DMIMO_E_ARG, "pa_precoder: NULL H or W");
+    if (layers > 0 && (!lambdas || !eta_rel)) return fail(DMIMO_E_ARG, "pa_precoder: NULL lambdas or eta_rel");
+    if (!ws || ws_bytes < dmimo_workspace_size(DMIMO_CALL_PA_PRECODER, B, K, M, 0, prec))
+        return fail(DMIMO_E_WORKSPACE, "pa_precoder: workspace smaller than dmimo_workspace_size()");
+    return launch_pa_precoder(B, K, M, H, gamma_lin, sigma2, layers, lambdas, eta_rel, W, p_ant,
+                              l21, sinr, rsum, ws, as_stream(stream));
 }
 
 size_t dmimo_ufpgd_workspace_size(int32_t B, int32_t K, int32_t M, int32_t layers) {

@@ -54,6 +54,12 @@ dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* ga
                         int layers, const double* lambdas, const double* etas, const void* W0,
                         void* W, double* l21, double* rsum, hipStream_t s);
 
+// ws: [B][2] FP64 normalisation factors, written here
+dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const double* gamma,
+                                double sigma2, int layers, const double* lambdas,
+                                const double* eta_rel, void* W, double* p_ant, double* l21,
+                                double* sinr, double* rsum, void* ws, hipStream_t s);
+
 struct UfpgdArgs {
     int64_t B;              // channels per launch (the batch)
     int K, M, layers, n_channels;

@@ -44,11 +44,99 @@ struct PgdDev {
     float2* W;
     const double* lambdas;
     const double* etas;
-    float d[16];          // sigma sqrt(gamma_k)
-    double sigma2;
+    float d[16];          // sigma sqrt(gamma_k); sqrt(gamma_k) in the normalised mode
+    double sigma2;        // noise power of sinr / rsum (1 in the normalised mode)
     double* l21;
     double* rsum;
+    // normalised mode (the PA-aware precoder on any deployment): per channel
+    // {1/s, 1/L} of Hn = H / s; steps are eta_i / L; W = (sigma / s) Wn on output
+    const double* pa;     // [B][2] or NULL
+    double sigma;         // sqrt of the deployment's noise power
+    double* p_ant;        // [B][M] or NULL: per-antenna power of the output W
+    double* sinr;         // [B][K] or NULL
 };
+
+// Per-channel factors of the normalised mode.
+struct PgdScale {
+    float hs;             // H -> Hn
+    double es;            // eta_i -> eta_i / L
+    double ws;            // Wn -> W
+};
+
+__device__ __forceinline__ PgdScale pgd_scale(const PgdDev& a, int64_t b) {
+    PgdScale c{1.0f, 1.0, 1.0};
+    if (a.pa) {
+        c.hs = (float)a.pa[2 * b];
+        c.es = a.pa[2 * b + 1];
+        c.ws = a.sigma * a.pa[2 * b];
+    }
+    return c;
+}
+
+// Normalisation of the PA-aware precoder, one wave per channel: s^2 = mean
+// |h|^2, G = H H^H in FP64, and the largest eigenvalue of G by 200 power
+// iterations from a fixed generic start (the Rayleigh quotient of the last
+// iterate).  Writes {1/s, s^2 / lambda_max(G)} = {1/s, 1/lambda_max(Hn Hn^H)};
+// an all-zero channel gets {0, 0}, which makes its output W = 0.
+__global__ __launch_bounds__(64) void pa_prepare_kernel(const float2* H, int K, int M, double* pa) {
+    __shared__ double Gr[16][17], Gi[16][17];
+    __shared__ double vr[16], vi[16];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const float2* Hb = H + b * K * M;
+    double p = 0.0;
+    for (int e = lane; e < K * M; e += 64) {
+        const float2 h = Hb[e];
+        p += (double)h.x * h.x + (double)h.y * h.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
+    for (int e = lane; e < K * K; e += 64) {
+        const int k = e / K, j = e - k * K;
+        double gr = 0.0, gi = 0.0;
+        for (int m = 0; m < M; ++m) {
+            const float2 hk = Hb[k * M + m], hj = Hb[j * M + m];
+            gr += (double)hk.x * hj.x + (double)hk.y * hj.y;
+            gi += (double)hk.y * hj.x - (double)hk.x * hj.y;
+        }
+        Gr[k][j] = gr;
+        Gi[k][j] = gi;
+    }
+    if (lane < 16) {
+        vr[lane] = lane < K ? 1.0 + 0.125 * lane : 0.0;
+        vi[lane] = 0.0;
+    }
+    __syncthreads();
+    double lam = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        double yr = 0.0, yi = 0.0;
+        if (lane < K)
+            for (int j = 0; j < K; ++j) {
+                yr += Gr[lane][j] * vr[j] - Gi[lane][j] * vi[j];
+                yi += Gr[lane][j] * vi[j] + Gi[lane][j] * vr[j];
+            }
+        // Rayleigh quotient v^H G v (v has unit norm after the first pass)
+        double rq = lane < K ? vr[lane] * yr + vi[lane] * yi : 0.0;
+        double n2 = yr * yr + yi * yi;
+        for (int off = 32; off > 0; off >>= 1) {
+            rq += __shfl_xor(rq, off, 64);
+            n2 += __shfl_xor(n2, off, 64);
+        }
+        lam = rq;
+        __syncthreads();
+        if (lane < K && n2 > 0.0) {
+            const double inv = 1.0 / sqrt(n2);
+            vr[lane] = yr * inv;
+            vi[lane] = yi * inv;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        const double s2 = p / ((double)K * M);
+        const bool ok = s2 > 0.0 && lam > 0.0;
+        pa[2 * b] = ok ? 1.0 / sqrt(s2) : 0.0;
+        pa[2 * b + 1] = ok ? s2 / lam : 0.0;
+    }
+}
 
 __device__ __forceinline__ void cfmaf(float2& acc, float2 a, float2 b) {   // acc += a b
     acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
@@ -71,10 +159,11 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
     const int K = a.K, M = a.M;
     const int tid = threadIdx.x;
     const float2* Hb = a.H + b * K * M;
+    const PgdScale cs = pgd_scale(a, b);
 
     for (int e = tid; e < K * M; e += kPgdThreads) {
         const int k = e / M, m = e - k * M;
-        const float2 h = Hb[e];
+        const float2 h = make_float2(cs.hs * Hb[e].x, cs.hs * Hb[e].y);
         sH[k][m] = h;
         sW[k][m] = a.W0 ? a.W0[b * K * M + e] : make_float2(h.x, -h.y);   // W(0) = H^*
     }
@@ -88,8 +177,8 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
     const int cc = tid >> 2, rg = tid & 3;
 
     for (int layer = 0; layer < a.layers; ++layer) {
-        const float eta = (float)a.etas[layer];
-        const float thr = (float)(a.lambdas[layer] * a.etas[layer]);
+        const float eta = (float)(a.etas[layer] * cs.es);
+        const float thr = (float)(a.lambdas[layer] * a.etas[layer] * cs.es);
         // A = W H^T
         float2 acc = make_float2(0.f, 0.f);
         if (ae < KT * KT && ak < K && aj < K)
@@ -137,23 +226,29 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
         __syncthreads();
     }
 
-    // outputs: W, ||W||_{2,1}, sum rate
+    // outputs: W, p_m, ||W||_{2,1}, SINR_k, sum rate (SINR from the normalised
+    // gains with unit noise in the normalised mode, which is the same SINR)
     float2* Wb = a.W + b * K * M;
-    for (int e = tid; e < K * M; e += kPgdThreads) Wb[e] = sW[e / M][e % M];
-    if (a.l21) {
+    const float wsf = (float)cs.ws;
+    for (int e = tid; e < K * M; e += kPgdThreads) {
+        const float2 w = sW[e / M][e % M];
+        Wb[e] = make_float2(wsf * w.x, wsf * w.y);
+    }
+    if (a.l21 || a.p_ant) {
         double s = 0.0;
         for (int m = tid; m < M; m += kPgdThreads) {
             double p = 0.0;
             for (int k = 0; k < K; ++k) p += (double)sW[k][m].x * sW[k][m].x + (double)sW[k][m].y * sW[k][m].y;
+            if (a.p_ant) a.p_ant[b * M + m] = cs.ws * cs.ws * p;
             s += sqrt(p);
         }
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
         if ((tid & 63) == 0) red[tid >> 6] = s;
         __syncthreads();
-        if (tid == 0) a.l21[b] = red[0] + red[1] + red[2] + red[3];
+        if (tid == 0 && a.l21) a.l21[b] = cs.ws * (red[0] + red[1] + red[2] + red[3]);
         __syncthreads();
     }
-    if (a.rsum) {
+    if (a.rsum || a.sinr) {
         // gains A = H W^T in FP64, one entry per thread
         double2 g = make_double2(0.0, 0.0);
         const int k = tid / KT, j = tid % KT;
@@ -171,9 +266,11 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
             for (int kk = 0; kk < K; ++kk) {
                 double sig = 0.0, intf = 0.0;
                 for (int jj = 0; jj < K; ++jj) (jj == kk ? sig : intf) += sP[kk][jj];
-                r += log2(1.0 + sig / (intf + a.sigma2));
+                const double sn = sig / (intf + a.sigma2);
+                if (a.sinr) a.sinr[b * K + kk] = sn;
+                r += log2(1.0 + sn);
             }
-            a.rsum[b] = r;
+            if (a.rsum) a.rsum[b] = r;
         }
     }
 }
@@ -190,14 +287,16 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     const int64_t b = blockIdx.x;
     const int K = a.K, M = a.M;
     const float2* Hb = a.H + b * K * M;
+    const PgdScale cs = pgd_scale(a, b);
 
-    load_planar(sX, stride, NW, Hb, K, M, false);
+    load_planar(sX, stride, NW, Hb, K, M, false, cs.hs);
     __syncthreads();
     float HA[16], HB[4][4];
     read_op_a(sX, stride, L, HA);
     read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    load_planar(sX, stride, NW, a.W0 ? a.W0 + b * K * M : Hb, K, M, a.W0 == nullptr);   // W(0) = W0 or H^*
+    if (a.W0) load_planar(sX, stride, NW, a.W0 + b * K * M, K, M, false, 1.0f);
+    else load_planar(sX, stride, NW, Hb, K, M, true, cs.hs);              // W(0) = H^*
     __syncthreads();
     float WD[4][4], WA[16];
     read_out_d(sX, stride, L, WD);
@@ -206,8 +305,8 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
 
     int ph = 0;
     for (int layer = 0; layer < a.layers; ++layer) {
-        const float eta = (float)a.etas[layer];
-        const float thr = (float)(a.lambdas[layer] * a.etas[layer]);
+        const float eta = (float)(a.etas[layer] * cs.es);
+        const float thr = (float)(a.lambdas[layer] * a.etas[layer] * cs.es);
         put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
         __syncthreads();
         float E[4];                            // (A - D), embedded
@@ -231,19 +330,21 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
         wave_lds_sync();
         read_op_a(sX, stride, L, WA);
     }
-    if (a.rsum) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
+    const bool gains = a.rsum || a.sinr;
+    if (gains) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
     __syncthreads();
 
-    // outputs from the planar W
+    // outputs from the planar W (scaled back in the normalised mode)
     const int tid = L.tid;
     float2* Wb = a.W + b * K * M;
+    const float wsf = (float)cs.ws;
     for (int e = tid; e < K * M; e += blockDim.x) {
         const int k = e / M, m = e - k * M;
-        Wb[e] = make_float2(sX[k * stride + m], sX[(8 + k) * stride + m]);
+        Wb[e] = make_float2(wsf * sX[k * stride + m], wsf * sX[(8 + k) * stride + m]);
     }
     // scratch for the reductions: the partial buffer of the other parity
     double* red = reinterpret_cast<double*>(sD + (ph ^ 1) * NW * kPartFloats);
-    if (a.l21) {
+    if (a.l21 || a.p_ant) {
         double s = 0.0;
         for (int m = tid; m < M; m += blockDim.x) {
             double p = 0.0;
@@ -251,12 +352,13 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
                 const double x = sX[k * stride + m], y = sX[(8 + k) * stride + m];
                 p += x * x + y * y;
             }
+            if (a.p_ant) a.p_ant[b * M + m] = cs.ws * cs.ws * p;
             s += sqrt(p);
         }
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
         if (L.lane == 0) red[64 + L.wave] = s;
     }
-    if (a.rsum && L.wave == 0) {
+    if (gains && L.wave == 0) {
         // gains G = H W^T = A^T with A = W H^T from the last MFMA pass:
         // lane 8 k + j holds |G_kj|^2 = |A_jk|^2
         const int k = L.lane >> 3, j = L.lane & 7;
@@ -266,26 +368,30 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     if (tid == 0 && a.l21) {
         double t = 0.0;
         for (int w = 0; w < NW; ++w) t += red[64 + w];
-        a.l21[b] = t;
+        a.l21[b] = cs.ws * t;
     }
-    if (a.rsum && L.wave == 0) {
-        // user k = lane < K: log2(1 + SINR_k), then a sum over the 8 lanes
+    if (gains && L.wave == 0) {
+        // user k = lane < K: SINR_k and log2(1 + SINR_k), then a sum over the 8 lanes
         double r = 0.0;
         if (L.lane < K) {
             double sig = 0.0, intf = 0.0;
             for (int jj = 0; jj < K; ++jj) (jj == L.lane ? sig : intf) += red[L.lane * 8 + jj];
-            r = log2(1.0 + sig / (intf + a.sigma2));
+            const double sn = sig / (intf + a.sigma2);
+            if (a.sinr) a.sinr[b * K + L.lane] = sn;
+            r = log2(1.0 + sn);
         }
         for (int off = 4; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
-        if (L.lane == 0) a.rsum[b] = r;
+        if (L.lane == 0 && a.rsum) a.rsum[b] = r;
     }
 }
 
 }  // namespace
 
-dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* gamma, double sigma2,
-                        int layers, const double* lambdas, const double* etas, const void* W0,
-                        void* W, double* l21, double* rsum, hipStream_t s) {
+namespace {
+
+PgdDev make_pgd_dev(int K, int M, const void* H, const double* gamma, double sigma2, int layers,
+                    const double* lambdas, const double* etas, const void* W0, void* W, double* l21,
+                    double* rsum) {
     PgdDev d;
     d.K = K;
     d.M = M;
@@ -300,10 +406,18 @@ dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* ga
     d.sigma2 = sigma2;
     d.l21 = l21;
     d.rsum = rsum;
+    d.pa = nullptr;
+    d.sigma = sigma;
+    d.p_ant = nullptr;
+    d.sinr = nullptr;
+    return d;
+}
+
+dmimo_status run_pgd(const PgdDev& d, int64_t B, hipStream_t s) {
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pgd: B too large");
-    dim3 grid((unsigned)B), block(kPgdThreads);
-    if (K <= 8) {
-        const int nw = (M + 63) / 64;
+    const dim3 grid((unsigned)B);
+    if (d.K <= 8) {
+        const int nw = (d.M + 63) / 64;
         const size_t lds = pgd_mfma_lds_bytes(nw);
         switch (nw) {
             case 1: pgd_mfma_kernel<1><<<grid, dim3(64), lds, s>>>(d); break;
@@ -313,8 +427,34 @@ dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* ga
         }
         return check_launch("pgd_mfma_kernel");
     }
-    pgd_kernel<16><<<grid, block, 0, s>>>(d);
+    pgd_kernel<16><<<grid, dim3(kPgdThreads), 0, s>>>(d);
     return check_launch("pgd_kernel");
+}
+
+}  // namespace
+
+dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* gamma, double sigma2,
+                        int layers, const double* lambdas, const double* etas, const void* W0,
+                        void* W, double* l21, double* rsum, hipStream_t s) {
+    const PgdDev d = make_pgd_dev(K, M, H, gamma, sigma2, layers, lambdas, etas, W0, W, l21, rsum);
+    return run_pgd(d, B, s);
+}
+
+dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const double* gamma,
+                                double sigma2, int layers, const double* lambdas,
+                                const double* eta_rel, void* W, double* p_ant, double* l21,
+                                double* sinr, double* rsum, void* ws, hipStream_t s) {
+    // the normalised problem has unit noise: d_k = sqrt(gamma_k), SINR with noise 1
+    PgdDev d = make_pgd_dev(K, M, H, gamma, 1.0, layers, lambdas, eta_rel, nullptr, W, l21, rsum);
+    d.pa = static_cast<const double*>(ws);
+    d.sigma = std::sqrt(sigma2);
+    d.p_ant = p_ant;
+    d.sinr = sinr;
+    if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pa_precoder: B too large");
+    pa_prepare_kernel<<<dim3((unsigned)B), dim3(64), 0, s>>>(d.H, K, M, static_cast<double*>(ws));
+    dmimo_status st = check_launch("pa_prepare_kernel");
+    if (st) return st;
+    return run_pgd(d, B, s);
 }
 
 }  // namespace dmimo

@@ -48,17 +48,17 @@ struct PgdLane {
     }
 };
 
-// X (K x M, complex64, row-major) into the planar image, zero padded to
-// 8 x 64 nw, optionally conjugated.  All threads of the block take part.
+// scale * X (K x M, complex64, row-major) into the planar image, zero padded
+// to 8 x 64 nw, optionally conjugated.  All threads of the block take part.
 __device__ __forceinline__ void load_planar(float* sX, int stride, int nw, const float2* X, int K,
-                                            int M, bool conj) {
+                                            int M, bool conj, float scale = 1.0f) {
     const int ncol = 64 * nw;
     for (int e = threadIdx.x; e < 8 * ncol; e += blockDim.x) {
         const int k = e / ncol, m = e - k * ncol;
         float2 x = make_float2(0.f, 0.f);
         if (k < K && m < M) x = X[k * M + m];
-        sX[k * stride + m] = x.x;
-        sX[(8 + k) * stride + m] = conj ? -x.y : x.y;
+        sX[k * stride + m] = scale * x.x;
+        sX[(8 + k) * stride + m] = conj ? -(scale * x.y) : scale * x.y;
     }
 }
 
@@ -176,11 +176,14 @@ __device__ __forceinline__ float column_sum(float x) {
     return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
-// Column norm and prox scale 1 - thr / max(n, thr) (1 at thr = 0), with the
-// hardware square root and reciprocal (about 1 ulp each).
+// Column norm and prox scale 1 - thr / max(n, thr), with the hardware square
+// root and reciprocal (about 1 ulp each).  The branch on n > thr keeps a
+// switched-off column exactly zero (thr * rcp(thr) need not round to 1);
+// at thr = 0 the prox is the identity.
 __device__ __forceinline__ float col_norm(float n2) { return __builtin_amdgcn_sqrtf(n2); }
 __device__ __forceinline__ float prox_scale(float nrm, float thr) {
-    return thr > 0.0f ? 1.0f - thr * __builtin_amdgcn_rcpf(fmaxf(nrm, thr)) : 1.0f;
+    if (!(thr > 0.0f)) return 1.0f;
+    return nrm > thr ? 1.0f - thr * __builtin_amdgcn_rcpf(nrm) : 0.0f;
 }
 
 inline size_t pgd_mfma_lds_bytes(int nw) {

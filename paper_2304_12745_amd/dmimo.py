@@ -20,7 +20,8 @@ F64, F32, MIX_F16X3, MIX_BF16X3 = 0, 1, 2, 3
 CH_LOS, CH_RICIAN = 0, 1
 MR, ZF, MR_PHASE = 0, 1, 2
 PTS_GRID, PTS_LIST = 0, 1
-CALL_CHANNEL, CALL_GRAM, CALL_BEAMFORM_MR, CALL_BEAMFORM_ZF, CALL_POWERMAP = 0, 1, 2, 3, 4
+CALL_CHANNEL, CALL_GRAM, CALL_BEAMFORM_MR, CALL_BEAMFORM_ZF, CALL_POWERMAP, CALL_PA_PRECODER = \
+    0, 1, 2, 3, 4, 5
 K_MAX = 32
 
 PRECISIONS = {"f64": F64, "f32": F32, "f16x3": MIX_F16X3, "bf16x3": MIX_BF16X3}
@@ -60,6 +61,8 @@ _SIGS = {
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
     "dmimo_pgd": [_i32, _i32, _i32, _vp, _vp, _f64, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "dmimo_pa_precoder": [_i32, _i32, _i32, _vp, _vp, _f64, _i32, _vp, _vp, _i32, _vp, _vp, _vp,
+                          _vp, _vp, _vp, _sz, _vp],
     "dmimo_ufpgd_workspace_size": [_i32, _i32, _i32, _i32],
     "dmimo_ufpgd_grad": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _i32,
                          _vp, _vp, _vp, _vp, _sz, _vp],
@@ -321,6 +324,44 @@ def pgd(H, lambdas, etas, gamma_lin=None, sigma2=1.0, W0=None, prec="f32", out=N
     _check(lib().dmimo_pgd(B, K, M, _ptr(H), g, float(sigma2), lam.numel(), _ptr(lam), _ptr(eta),
                            _ptr(W0), _prec(prec), _ptr(out.W), _ptr(out.l21), _ptr(out.rsum),
                            _stream(stream)), "dmimo_pgd")
+    return out
+
+
+@dataclass
+class PaResult:
+    W: object       # [B][K][M] complex64
+    p_ant: object   # [B][M] FP64
+    l21: object     # [B]
+    sinr: object    # [B][K]
+    rsum: object    # [B]
+
+
+def pa_precoder(H, lambdas, eta_rel, gamma_lin=None, sigma2=1.0, out=None, ws=None,
+                stream=None) -> PaResult:
+    """PA-aware precoder of deployments with channels of any scale
+    (dmimo_pa_precoder).  H complex64 [B][K][M] on the GPU; lambdas, eta_rel
+    per layer (steps relative to 1 / lambda_max of the normalised Gram)."""
+    import torch
+    B, K, M = H.shape
+    dev = H.device
+    lam = _f64_dev(lambdas, dev)
+    er = _f64_dev(eta_rel, dev)
+    if lam.numel() != er.numel():
+        raise ValueError("lambdas and eta_rel need the same length")
+    if out is None:
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = PaResult(torch.empty((B, K, M), dtype=torch.complex64, device=dev),
+                       torch.empty((B, M), **f64), torch.empty((B,), **f64),
+                       torch.empty((B, K), **f64), torch.empty((B,), **f64))
+    nbytes = workspace_size(CALL_PA_PRECODER, B, K, M, 0, F32)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=dev)
+    out._keep = (lam, er, ws)
+    _check(lib().dmimo_pa_precoder(B, K, M, _ptr(H), _gamma(gamma_lin, K), float(sigma2),
+                                   lam.numel(), _ptr(lam), _ptr(er), F32, _ptr(out.W),
+                                   _ptr(out.p_ant), _ptr(out.l21), _ptr(out.sinr),
+                                   _ptr(out.rsum), _ptr(ws), nbytes, _stream(stream)),
+           "dmimo_pa_precoder")
     return out
 
 

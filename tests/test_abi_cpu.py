@@ -214,3 +214,31 @@ def test_ufpgd_validation(lib):
     assert train(lam=None) == 1
     assert train(nbytes=ws_b - 1) == 4
     assert train(steps=0, idx=None, lam=None) == 0
+
+
+def test_pa_precoder_validation(lib):
+    need = lib.dmimo_workspace_size(D.CALL_PA_PRECODER, 4, 8, 64, 0, D.F32)
+    assert need == 256
+
+    def pa(B=4, K=8, M=64, H=FAKE, sigma2=1e-12, layers=3, lam=FAKE, er=FAKE, prec=D.F32,
+           W=FAKE, ws=FAKE, nbytes=need):
+        return lib.dmimo_pa_precoder(B, K, M, H, None, sigma2, layers, lam, er, prec, W, None,
+                                     None, None, None, ws, nbytes, None)
+
+    assert pa(K=0) == 2
+    assert pa(K=17) == 2
+    assert pa(M=257) == 2
+    assert pa(B=-1) == 2
+    assert pa(prec=D.F64) == 6
+    assert pa(prec=11) == 3
+    assert pa(sigma2=0.0) == 1
+    assert pa(sigma2=float("nan")) == 1
+    assert pa(H=None) == 1
+    assert pa(W=None) == 1
+    assert pa(er=None) == 1
+    assert pa(ws=None) == 4
+    assert pa(nbytes=need - 1) == 4
+    assert pa(B=0, H=None, W=None, ws=None) == 0
+    bad = (ctypes.c_double * 8)(*([1.0] * 7 + [-2.0]))
+    assert lib.dmimo_pa_precoder(4, 8, 64, FAKE, bad, 1e-12, 3, FAKE, FAKE, D.F32, FAKE, None,
+                                 None, None, None, FAKE, need, None) == 1
