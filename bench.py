@@ -103,6 +103,7 @@ def parse_args():
     p.add_argument("--serve-prec", default="f32", choices=["f32", "f16x3", "bf16x3"])
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
     p.add_argument("--no-pgd", action="store_true", help="skip the PGD / unfolded-PGD phase")
+    p.add_argument("--no-pa", action="store_true", help="skip the PA-aware precoder phase")
     return p.parse_args()
 
 
@@ -212,6 +213,8 @@ def main():
         out["serving"] = serving_phase(args, D, WL, torch)
     if not args.no_pgd:
         out["pgd"] = pgd_phase(args, D, WL, torch)
+    if not args.no_pa:
+        out["pa"] = pa_phase(w, D, WL, torch, params, ap0, gpts)
     if not args.no_cpu and args.cpu_seconds > 0:
         out["cpu_baseline"], out["err_db"] = cpu_baseline(w, bf, maps, args.cpu_seconds)
 
@@ -436,6 +439,80 @@ def pgd_phase(args, D, WL, torch):
         res["cpu_oracle"] = {"ufpgd20_ms_per_5000": round(el / n * B * 1e3, 2), "cores": 1,
                              "kind": "oracle", "sample": f"{n} channels in {el:.1f} s"}
     return res
+
+
+def pa_phase(w, D, WL, torch, params, ap0, gpts):
+    """The PA-consumption-aware precoder (eq. optim1 by normalised PGD, lambda =
+    1/15, 5000 iterations) on the benchmark room: the step's K = 8 users, SINR
+    targets 10 dB, noise -90 dBm.  Reports its PCG against ZF with the same
+    targets, the APs it switches off and the SINR range; times the precoder
+    and the 512 x 512 power + SINR map of the sparse W; then the precoder's
+    throughput over 1024 user draws in the same room (one launch)."""
+    import numpy as np
+
+    K, M, N = w.K, w.M, w.grid.n
+    gamma = np.full(K, 10.0)
+    it = 5000
+    lam = torch.full((it,), 1.0 / 15.0, dtype=torch.float64, device="cuda")
+    er = torch.ones((it,), dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ap = torch.from_numpy(w.ap_xyz).cuda()                  # [1][M][3]
+    users = torch.from_numpy(w.user_xyz).cuda()             # [1][K][3]
+    H = D.channel(params, ap, D.list_points(users, K), prec="f32")
+    r = D.pa_precoder(H, lam, er, gamma, w.sigma2)
+    ms_pa = timed(lambda: D.pa_precoder(H, lam, er, gamma, w.sigma2, out=r), 3)
+    zf = D.beamform(H, "zf", gamma, w.sigma2, 0.0, "f32")
+    mp = D.MapResult(torch.empty(N, device="cuda"), torch.empty(N, device="cuda"),
+                     torch.empty(N, dtype=torch.int32, device="cuda"), None)
+    Wpa = r.W[0].contiguous()
+    ms_map = timed(lambda: D.powermap(params, ap0, Wpa, gpts, w.sigma2, "f32", out=mp), 20)
+    mz = D.powermap(params, ap0, zf.W[0].contiguous(), gpts, w.sigma2, "f32")
+    sinr_db = 10 * torch.log10(r.sinr[0])
+    ratio_db = 10 * torch.log10(mp.power.double() / mz.power.double())
+
+    B = 1024
+    rng = np.random.default_rng(11)
+    ub = torch.from_numpy(np.stack([WL.uniform_positions(rng, K, 20.0, 20.0, 1.2)
+                                    for _ in range(B)])).cuda()
+    apb = ap.expand(B, M, 3).contiguous()
+    Hb = D.channel(params, apb, D.list_points(ub, K), prec="f32")
+    rb = D.pa_precoder(Hb, lam, er, gamma, w.sigma2)
+    ms_b = timed(lambda: D.pa_precoder(Hb, lam, er, gamma, w.sigma2, out=rb), 1)
+    zfb = D.beamform(Hb, "zf", gamma, w.sigma2, 0.0, "f32")
+    pcg_b = (zfb.l21 / rb.l21)
+    off_b = (rb.p_ant == 0).sum(dim=1).double()
+    flops = 16 * K * K * M * it
+    return {
+        "workload": f"room deployment: M={M} jittered ceiling APs, the step's K={K} users, "
+                    "SINR targets 10 dB, noise -90 dBm; lambda 1/15, eta = 1/lambda_max, "
+                    f"{it} iterations",
+        "precoder_ms": round(ms_pa, 3),
+        "pcg_vs_zf": round((zf.l21[0] / r.l21[0]).item(), 4),
+        "aps_off": int((r.p_ant[0] == 0).sum().item()),
+        "sinr_db_min": round(sinr_db.min().item(), 3),
+        "sinr_db_max": round(sinr_db.max().item(), 3),
+        "map_ms": round(ms_map, 4),
+        "map_power_vs_zf_db": {"median": round(ratio_db.median().item(), 3),
+                               "p5": round(ratio_db.quantile(0.05).item(), 3),
+                               "p95": round(ratio_db.quantile(0.95).item(), 3)},
+        "batched": {"deployments": B, "ms": round(ms_b, 3),
+                    "deployments_per_s": round(B / (ms_b * 1e-3), 1),
+                    "tflops": round(flops * B / (ms_b * 1e-3) / 1e12, 2),
+                    "mean_pcg": round(pcg_b.mean().item(), 4),
+                    "min_pcg": round(pcg_b.min().item(), 4),
+                    "mean_aps_off": round(off_b.mean().item(), 2)},
+    }
 
 
 def cpu_baseline(w, bf, maps, budget_s):
