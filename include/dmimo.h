@@ -67,7 +67,8 @@ typedef enum { DMIMO_CH_LOS = 0, DMIMO_CH_RICIAN = 1 } dmimo_chmodel;
 typedef enum {
     DMIMO_MR = 0,        /* W = c H^*                                  */
     DMIMO_ZF = 1,        /* W = scale * conj(G^-1 H), G = H H^H        */
-    DMIMO_MR_PHASE = 2   /* equal-gain MR, w_km = a exp(-j angle h_km) */
+    DMIMO_MR_PHASE = 2,  /* equal-gain MR, w_km = a exp(-j angle h_km) */
+    DMIMO_PA = 3         /* PA-consumption-aware (dmimo_pa_precoder); serving only */
 } dmimo_precoder;
 
 typedef enum { DMIMO_PTS_GRID = 0, DMIMO_PTS_LIST = 1 } dmimo_points_kind;
@@ -336,6 +337,15 @@ dmimo_status dmimo_server_poll(dmimo_server* srv, uint64_t ticket, int32_t* stat
 /* Block until the ticket is done or failed, or timeout_s elapses. */
 dmimo_status dmimo_server_wait(dmimo_server* srv, uint64_t ticket, double timeout_s,
                                int32_t* state);
+/* Layer schedule of DMIMO_PA queries (eq. optim1 by normalised PGD, as in
+ * dmimo_pa_precoder): lambdas and eta_rel, host FP64 [layers], and one SINR
+ * target gamma_lin > 0 for every user.  Copied into the server's memory;
+ * set once per server, before the first DMIMO_PA query (a second call:
+ * DMIMO_E_BUSY).  DMIMO_PA queries need K <= 16, M <= 256, sigma2 > 0, and
+ * their p_total is unused. */
+dmimo_status dmimo_server_set_pa_schedule(dmimo_server* srv, int32_t layers,
+                                          const double* lambdas, const double* eta_rel,
+                                          double gamma_lin);
 /* Forget a finished ticket (DMIMO_E_BUSY if it is not finished). */
 dmimo_status dmimo_server_release(dmimo_server* srv, uint64_t ticket);
 /* Counters: queries completed, channel terms completed, launches issued,

@@ -204,6 +204,11 @@ struct ServerImpl {
     int64_t ticks_issued = 0, ticks_done = 0;
     double tick_terms = 6.0e7;
     int grid = 512;
+    // schedule of DMIMO_PA queries (device FP64 [2][layers] in the arena)
+    int pa_layers = -1;
+    const double* pa_lam = nullptr;
+    const double* pa_eta = nullptr;
+    double pa_gamma[DMIMO_K_MAX];
     // queries
     std::mutex mu;
     std::condition_variable cv;
@@ -237,7 +242,8 @@ bool ServerImpl::admit_one(Query* q) {
     const size_t h_b = align256((size_t)K * M * 8);
     const size_t w_b = align256((size_t)K * M * 8);
     const size_t g_b = align256((size_t)K * K * 8);
-    q->bytes = users_b + h_b + w_b + g_b;
+    const size_t pa_b = q->precoder == DMIMO_PA ? align256(2 * sizeof(double)) : 0;
+    q->bytes = users_b + h_b + w_b + g_b + pa_b;
     if (in_use + q->footprint > budget) return false;
     if (free_slots.empty()) return false;
     size_t off;
@@ -263,20 +269,27 @@ bool ServerImpl::admit_one(Query* q) {
     up.n = K;
     const double* ap = reinterpret_cast<const double*>(arena_base + d.off);
     ok = ok && launch_channel(d.w, up, false, 1, d.M, ap, nullptr, false, H, stream) == DMIMO_OK;
-    BeamformArgs ba;
-    std::memset(&ba, 0, sizeof(ba));
-    ba.precoder = q->precoder;
-    ba.B = 1;
-    ba.K = K;
-    ba.M = d.M;
-    ba.H = H;
-    for (int k = 0; k < DMIMO_K_MAX; ++k) ba.gamma[k] = 1.0;
-    ba.sigma2 = q->sigma2;
-    ba.p_total = q->p_total;
-    ba.prec = q->prec;
-    ba.W = W;
-    ba.ws = G;
-    ok = ok && launch_beamform(ba, stream) == DMIMO_OK;
+    if (q->precoder == DMIMO_PA) {
+        void* pa_ws = base + users_b + h_b + w_b + g_b;
+        ok = ok && launch_pa_precoder(1, K, d.M, H, pa_gamma, q->sigma2, pa_layers, pa_lam, pa_eta,
+                                      W, nullptr, nullptr, nullptr, nullptr, pa_ws,
+                                      stream) == DMIMO_OK;
+    } else {
+        BeamformArgs ba;
+        std::memset(&ba, 0, sizeof(ba));
+        ba.precoder = q->precoder;
+        ba.B = 1;
+        ba.K = K;
+        ba.M = d.M;
+        ba.H = H;
+        for (int k = 0; k < DMIMO_K_MAX; ++k) ba.gamma[k] = 1.0;
+        ba.sigma2 = q->sigma2;
+        ba.p_total = q->p_total;
+        ba.prec = q->prec;
+        ba.W = W;
+        ba.ws = G;
+        ok = ok && launch_beamform(ba, stream) == DMIMO_OK;
+    }
     // map descriptor of the slot
     PmMapDev& m = h_slots[q->slot];
     m.P = q->P;
@@ -530,8 +543,11 @@ dmimo_status dmimo_server_submit(dmimo_server* srv, int32_t dep_id, int32_t K,
     dmimo_status st = make_points(pts, &P);
     if (st) return st;
     if (P.n < 1) return fail(DMIMO_E_SHAPE, "submit: empty point set");
-    if (precoder != DMIMO_MR && precoder != DMIMO_ZF && precoder != DMIMO_MR_PHASE)
+    if (precoder != DMIMO_MR && precoder != DMIMO_ZF && precoder != DMIMO_MR_PHASE &&
+        precoder != DMIMO_PA)
         return fail(DMIMO_E_DTYPE, "submit: unknown precoder");
+    if (precoder == DMIMO_PA && !(sigma2 > 0.0))
+        return fail(DMIMO_E_ARG, "submit: DMIMO_PA needs sigma2 > 0");
     if (prec != DMIMO_F32 && prec != DMIMO_MIX_F16X3 && prec != DMIMO_MIX_BF16X3)
         return fail(DMIMO_E_UNSUPPORTED, "submit: serving runs FP32 or mixed precision");
     if (!(sigma2 >= 0.0) || (sinr_out_dev && !(sigma2 > 0.0)))
@@ -547,6 +563,14 @@ dmimo_status dmimo_server_submit(dmimo_server* srv, int32_t dep_id, int32_t K,
         if (K < 1 || K > DMIMO_K_MAX || (precoder == DMIMO_ZF && K > M)) {
             delete q;
             return fail(DMIMO_E_SHAPE, "submit: K must be in [1, min(32, M)] (ZF)");
+        }
+        if (precoder == DMIMO_PA && (K > 16 || M > 256)) {
+            delete q;
+            return fail(DMIMO_E_SHAPE, "submit: DMIMO_PA needs K <= 16 and M <= 256");
+        }
+        if (precoder == DMIMO_PA && S.pa_layers < 0) {
+            delete q;
+            return fail(DMIMO_E_ARG, "submit: no DMIMO_PA schedule (dmimo_server_set_pa_schedule)");
         }
         if (S.pending.size() >= (size_t)(S.max_inflight) * 64) {
             delete q;
@@ -564,7 +588,8 @@ dmimo_status dmimo_server_submit(dmimo_server* srv, int32_t dep_id, int32_t K,
         q->sinr = sinr_out_dev;
         q->terms = P.n * (int64_t)M;
         const size_t scratch = align256((size_t)K * 24) + 2 * align256((size_t)K * M * 8) +
-                               align256((size_t)K * K * 8);
+                               align256((size_t)K * K * 8) +
+                               (precoder == DMIMO_PA ? align256(2 * sizeof(double)) : 0);
         q->footprint = scratch + (size_t)P.n * 4 * (sinr_out_dev ? 2 : 1);
         if (q->footprint > S.budget - S.geom_bytes) {
             delete q;
@@ -577,6 +602,38 @@ dmimo_status dmimo_server_submit(dmimo_server* srv, int32_t dep_id, int32_t K,
         *ticket = q->ticket;
     }
     S.cv.notify_all();
+    return DMIMO_OK;
+}
+
+dmimo_status dmimo_server_set_pa_schedule(dmimo_server* srv, int32_t layers,
+                                          const double* lambdas, const double* eta_rel,
+                                          double gamma_lin) {
+    clear_error();
+    if (!srv) return fail(DMIMO_E_ARG, "set_pa_schedule: NULL server");
+    if (layers < 0) return fail(DMIMO_E_SHAPE, "set_pa_schedule: layers must be >= 0");
+    if (layers > 0 && (!lambdas || !eta_rel)) return fail(DMIMO_E_ARG, "set_pa_schedule: NULL schedule");
+    if (!(gamma_lin > 0.0) || !std::isfinite(gamma_lin))
+        return fail(DMIMO_E_ARG, "set_pa_schedule: gamma_lin must be > 0");
+    ServerImpl& S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.pa_layers >= 0) return fail(DMIMO_E_BUSY, "set_pa_schedule: already set");
+    const size_t bytes = sizeof(double) * 2 * (size_t)std::max(layers, 1);
+    size_t off;
+    if (S.in_use + align256(bytes) > S.budget || !S.arena.alloc(bytes, &off))
+        return fail(DMIMO_E_NOMEM, "set_pa_schedule: schedule does not fit the budget");
+    double* dev = reinterpret_cast<double*>(S.arena_base + off);
+    if (layers > 0 &&
+        (hipMemcpy(dev, lambdas, sizeof(double) * layers, hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy(dev + layers, eta_rel, sizeof(double) * layers, hipMemcpyHostToDevice) != hipSuccess)) {
+        S.arena.release(off, bytes);
+        return fail(DMIMO_E_HIP, "set_pa_schedule: upload failed");
+    }
+    S.in_use += align256(bytes);
+    S.geom_bytes += align256(bytes);
+    for (int k = 0; k < DMIMO_K_MAX; ++k) S.pa_gamma[k] = gamma_lin;
+    S.pa_lam = dev;
+    S.pa_eta = dev + layers;
+    S.pa_layers = layers;
     return DMIMO_OK;
 }
 

@@ -18,14 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libdmimo.so")
 # precision / model / precoder / points enums (include/dmimo.h)
 F64, F32, MIX_F16X3, MIX_BF16X3 = 0, 1, 2, 3
 CH_LOS, CH_RICIAN = 0, 1
-MR, ZF, MR_PHASE = 0, 1, 2
+MR, ZF, MR_PHASE, PA = 0, 1, 2, 3
 PTS_GRID, PTS_LIST = 0, 1
 CALL_CHANNEL, CALL_GRAM, CALL_BEAMFORM_MR, CALL_BEAMFORM_ZF, CALL_POWERMAP, CALL_PA_PRECODER = \
     0, 1, 2, 3, 4, 5
 K_MAX = 32
 
 PRECISIONS = {"f64": F64, "f32": F32, "f16x3": MIX_F16X3, "bf16x3": MIX_BF16X3}
-PRECODERS = {"mr": MR, "zf": ZF, "mr_phase": MR_PHASE}
+PRECODERS = {"mr": MR, "zf": ZF, "mr_phase": MR_PHASE, "pa": PA}
 
 STATUS = {0: "DMIMO_OK", 1: "DMIMO_E_ARG", 2: "DMIMO_E_SHAPE", 3: "DMIMO_E_DTYPE",
           4: "DMIMO_E_WORKSPACE", 5: "DMIMO_E_HIP", 6: "DMIMO_E_UNSUPPORTED",
@@ -78,6 +78,7 @@ _SIGS = {
                           ctypes.POINTER(_f64)],
     "dmimo_server_wait": [_vp, ctypes.c_uint64, _f64, ctypes.POINTER(_i32)],
     "dmimo_server_release": [_vp, ctypes.c_uint64],
+    "dmimo_server_set_pa_schedule": [_vp, _i32, _vp, _vp, _f64],
     "dmimo_server_stats": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i32),
                            ctypes.POINTER(_i32)],
@@ -523,6 +524,17 @@ class Server:
                "dmimo_server_submit")
         self._keep[t.value] = (power, sinr, points)
         return t.value
+
+    def set_pa_schedule(self, lambdas, eta_rel, gamma_lin: float):
+        """Layer schedule of "pa" queries (host sequences), and their SINR target."""
+        import numpy as np
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        er = np.ascontiguousarray(eta_rel, dtype=np.float64)
+        if lam.shape != er.shape:
+            raise ValueError("lambdas and eta_rel need the same length")
+        _check(lib().dmimo_server_set_pa_schedule(self._h, lam.size, lam.ctypes.data,
+                                                  er.ctypes.data, float(gamma_lin)),
+               "dmimo_server_set_pa_schedule")
 
     def poll(self, ticket: int):
         st, ts, td = _i32(), _f64(), _f64()

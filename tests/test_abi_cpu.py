@@ -135,7 +135,11 @@ def test_server_validation(lib):
                                    None, ctypes.byref(t)) == 1
     st = ctypes.c_int32()
     assert lib.dmimo_server_poll(None, 1, ctypes.byref(st), None, None) == 1
+    assert lib.dmimo_server_set_pa_schedule(None, 3, u, u, 10.0) == 1
     assert lib.dmimo_server_destroy(None) == 0
+    # DMIMO_PA is a serving precoder only
+    assert lib.dmimo_beamform(D.PA, 1, 2, 8, FAKE, None, 1.0, 1.0, D.F32, FAKE, None, None, None,
+                              None, None, None, 0, None) == 3
 
 
 def test_pgd_validation(lib):

@@ -16,6 +16,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import dberror  # noqa: E402
 from oracle import dmimo_oracle as O  # noqa: E402
+from oracle import pa_oracle as PA  # noqa: E402
 from paper_2304_12745_amd import workloads as WL  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -165,3 +166,63 @@ def test_admission_by_footprint(D):
             srv.poll(987654321)
         assert ei.value.status == 9
         assert srv.stats()["completed"] == 10
+
+
+def test_pa_queries_equal_one_shot_and_mix(D):
+    """DMIMO_PA queries (the PA-aware precoder, eq. optim1 by normalised PGD):
+    their maps equal the one-shot chain channel -> dmimo_pa_precoder ->
+    dmimo_powermap bitwise, alone and inside a mix with MR/ZF queries, and
+    match the oracle chain."""
+    rng = np.random.default_rng(13)
+    deps = [(64, 3.5e9), (256, 5.8e9), (16, 0.92e9)]
+    aps = [_room(rng, M, f) for M, f in deps]
+    lams, er, gamma = [1 / 15] * 400, [1.0] * 400, 10.0
+    pa_qs, other = [], []
+    for i in range(6):
+        d = i % 3
+        K = (8, 16, 4)[d]
+        nx, ny = ((64, 64), (96, 80), (33, 47))[d]
+        grid = WL.Grid(0.0, 0.0, 20.0 / nx, 20.0 / ny, 1.2, nx, ny)
+        users = WL.uniform_positions(rng, K, 20.0, 20.0, 1.2)
+        pa_qs.append(dict(dep=d, K=K, users=users, grid=grid, prec=("f32", "f16x3")[i % 2], pc="pa"))
+        other.append(dict(dep=d, K=K, users=users, grid=grid, prec="f32", pc=("mr", "zf")[i % 2]))
+    with D.Server(1 << 30, 32) as srv:
+        ids = [srv.add_deployment(D.channel_params(f), a) for (M, f), a in zip(deps, aps)]
+        with pytest.raises(D.DmimoError):       # no schedule yet
+            _submit(D, srv, ids, pa_qs[0])
+        srv.set_pa_schedule(lams, er, gamma)
+        with pytest.raises(D.DmimoError):       # set once
+            srv.set_pa_schedule(lams, er, gamma)
+        alone = []
+        for q in pa_qs:
+            M, f = deps[q["dep"]]
+            say(f"PA query alone: M={M} K={q['K']} N={q['grid'].n} {q['prec']}")
+            t, power, sinr = _submit(D, srv, ids, q)
+            assert srv.wait(t, 60.0) == D.Q_DONE
+            p = D.channel_params(f)
+            ap = torch.from_numpy(aps[q["dep"]]).cuda()
+            H = D.channel(p, ap[None].contiguous(),
+                          D.list_points(torch.from_numpy(q["users"]).cuda(), q["K"]), prec="f32")
+            r = D.pa_precoder(H, lams, er, [gamma] * q["K"], 1e-12)
+            m = D.powermap(p, ap, r.W[0], D.grid_points(q["grid"]), 1e-12, q["prec"], want_best=False)
+            torch.cuda.synchronize()
+            assert torch.equal(m.power, power) and torch.equal(m.sinr, sinr)
+            alone.append((power.cpu().numpy(), sinr.cpu().numpy()))
+            srv.release(t)
+            if q["prec"] == "f32" and q["K"] == 8:
+                # oracle chain: oracle H -> oracle PA precoder -> oracle map
+                g = q["grid"]
+                Hu = O.los_channel(q["users"], aps[q["dep"]], f)
+                Wo, _, _ = PA.pa_precoder(Hu[None], np.full(q["K"], gamma), 1e-12, lams, er)
+                pts = O.grid_points(g.x0, g.y0, g.dx, g.dy, g.z, g.nx, g.ny)
+                y = O.power_map(O.los_channel(pts, aps[q["dep"]], f), Wo[0])
+                sp = dberror.summary(alone[-1][0], y, 0.01)
+                say(f"    oracle chain: power max {sp['max_db']:.2e} dB")
+                assert sp["n_fail"] == 0
+        subs = [_submit(D, srv, ids, q) for pair in zip(pa_qs, other) for q in pair]
+        for i, (t, power, sinr) in enumerate(subs):
+            assert srv.wait(t, 120.0) == D.Q_DONE
+            if i % 2 == 0:
+                np.testing.assert_array_equal(power.cpu().numpy(), alone[i // 2][0])
+                np.testing.assert_array_equal(sinr.cpu().numpy(), alone[i // 2][1])
+            srv.release(t)
