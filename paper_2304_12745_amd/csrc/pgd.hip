@@ -74,13 +74,19 @@ __device__ __forceinline__ PgdScale pgd_scale(const PgdDev& a, int64_t b) {
 }
 
 // Normalisation of the PA-aware precoder, one wave per channel: s^2 = mean
-// |h|^2, G = H H^H in FP64, and the largest eigenvalue of G by 200 power
-// iterations from a fixed generic start (the Rayleigh quotient of the last
-// iterate).  Writes {1/s, s^2 / lambda_max(G)} = {1/s, 1/lambda_max(Hn Hn^H)};
-// an all-zero channel gets {0, 0}, which makes its output W = 0.
+// |h|^2, G = H H^H in FP64, and the largest eigenvalue of G.  The eigenvalue
+// comes from repeated squaring, S <- S^2 / tr(S^2) from S = G / tr G, twelve
+// times (S ~ G^4096 / tr, a projector onto the top eigenspace unless the top
+// two eigenvalues agree to ~1e-3 relative, when any vector of their span
+// gives a Rayleigh quotient within that of lambda_max), then the Rayleigh
+// quotient of G at the largest-norm column of S.  Writes {1/s, s^2 /
+// lambda_max(G)} = {1/s, 1/lambda_max(Hn Hn^H)}; an all-zero channel gets
+// {0, 0}, which makes its output W = 0.
 __global__ __launch_bounds__(64) void pa_prepare_kernel(const float2* H, int K, int M, double* pa) {
-    __shared__ double Gr[16][17], Gi[16][17];
-    __shared__ double vr[16], vi[16];
+    __shared__ double Gr[16][17], Gi[16][17];     // G
+    __shared__ double Sr[16][17], Si[16][17];     // S
+    __shared__ double Tr[16][17], Ti[16][17];     // S^2
+    __shared__ double colnorm[16];
     const int64_t b = blockIdx.x;
     const int lane = threadIdx.x;
     const float2* Hb = H + b * K * M;
@@ -101,36 +107,64 @@ __global__ __launch_bounds__(64) void pa_prepare_kernel(const float2* H, int K, 
         Gr[k][j] = gr;
         Gi[k][j] = gi;
     }
-    if (lane < 16) {
-        vr[lane] = lane < K ? 1.0 + 0.125 * lane : 0.0;
-        vi[lane] = 0.0;
+    __syncthreads();
+    // S = G / tr G  (tr G = sum |h|^2 = p)
+    const double inv_tr = p > 0.0 ? 1.0 / p : 0.0;
+    for (int e = lane; e < K * K; e += 64) {
+        const int k = e / K, j = e - k * K;
+        Sr[k][j] = Gr[k][j] * inv_tr;
+        Si[k][j] = Gi[k][j] * inv_tr;
     }
     __syncthreads();
-    double lam = 0.0;
-    for (int it = 0; it < 200; ++it) {
-        double yr = 0.0, yi = 0.0;
-        if (lane < K)
-            for (int j = 0; j < K; ++j) {
-                yr += Gr[lane][j] * vr[j] - Gi[lane][j] * vi[j];
-                yi += Gr[lane][j] * vi[j] + Gi[lane][j] * vr[j];
+    for (int it = 0; it < 12; ++it) {
+        double dpart = 0.0;                        // this lane's share of tr(S^2)
+        for (int e = lane; e < K * K; e += 64) {
+            const int k = e / K, j = e - k * K;
+            double tr = 0.0, ti = 0.0;
+            for (int l = 0; l < K; ++l) {
+                tr += Sr[k][l] * Sr[l][j] - Si[k][l] * Si[l][j];
+                ti += Sr[k][l] * Si[l][j] + Si[k][l] * Sr[l][j];
             }
-        // Rayleigh quotient v^H G v (v has unit norm after the first pass)
-        double rq = lane < K ? vr[lane] * yr + vi[lane] * yi : 0.0;
-        double n2 = yr * yr + yi * yi;
-        for (int off = 32; off > 0; off >>= 1) {
-            rq += __shfl_xor(rq, off, 64);
-            n2 += __shfl_xor(n2, off, 64);
+            Tr[k][j] = tr;
+            Ti[k][j] = ti;
+            if (k == j) dpart += tr;
         }
-        lam = rq;
+        for (int off = 32; off > 0; off >>= 1) dpart += __shfl_xor(dpart, off, 64);
+        const double inv = dpart > 0.0 ? 1.0 / dpart : 0.0;
         __syncthreads();
-        if (lane < K && n2 > 0.0) {
-            const double inv = 1.0 / sqrt(n2);
-            vr[lane] = yr * inv;
-            vi[lane] = yi * inv;
+        for (int e = lane; e < K * K; e += 64) {
+            const int k = e / K, j = e - k * K;
+            Sr[k][j] = Tr[k][j] * inv;
+            Si[k][j] = Ti[k][j] * inv;
         }
         __syncthreads();
     }
+    if (lane < K) {
+        double c = 0.0;
+        for (int k = 0; k < K; ++k) c += Sr[k][lane] * Sr[k][lane] + Si[k][lane] * Si[k][lane];
+        colnorm[lane] = c;
+    }
+    __syncthreads();
+    int jb = 0;
+    for (int j = 1; j < K; ++j)
+        if (colnorm[j] > colnorm[jb]) jb = j;
+    // Rayleigh quotient of G at v = S[:, jb]: lane k holds v_k and (G v)_k
+    double num = 0.0, den = 0.0;
+    if (lane < K) {
+        double yr = 0.0, yi = 0.0;
+        for (int j = 0; j < K; ++j) {
+            yr += Gr[lane][j] * Sr[j][jb] - Gi[lane][j] * Si[j][jb];
+            yi += Gr[lane][j] * Si[j][jb] + Gi[lane][j] * Sr[j][jb];
+        }
+        num = Sr[lane][jb] * yr + Si[lane][jb] * yi;
+        den = Sr[lane][jb] * Sr[lane][jb] + Si[lane][jb] * Si[lane][jb];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        num += __shfl_xor(num, off, 64);
+        den += __shfl_xor(den, off, 64);
+    }
     if (lane == 0) {
+        const double lam = den > 0.0 ? num / den : 0.0;
         const double s2 = p / ((double)K * M);
         const bool ok = s2 > 0.0 && lam > 0.0;
         pa[2 * b] = ok ? 1.0 / sqrt(s2) : 0.0;
