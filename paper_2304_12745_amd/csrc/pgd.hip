@@ -310,29 +310,30 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
 }
 
 
-template <int NW>
+template <int AW, int NW>
 __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
+    constexpr int NQ = AW / 16;                // 16-antenna blocks per wave
     extern __shared__ float smem[];
-    const int stride = pl_stride(NW);
+    const int stride = pl_stride(AW * NW);
     float* sX = smem;                          // [16][stride]   H, then W
     float* sD = smem + 16 * stride;            // [2][NW][16][17] D1 partials
 
-    const PgdLane L;
+    const PgdLane<AW> L;
     const int64_t b = blockIdx.x;
     const int K = a.K, M = a.M;
     const float2* Hb = a.H + b * K * M;
     const PgdScale cs = pgd_scale(a, b);
 
-    load_planar(sX, stride, NW, Hb, K, M, false, cs.hs);
+    load_planar(sX, stride, AW * NW, Hb, K, M, false, cs.hs);
     __syncthreads();
-    float HA[16], HB[4][4];
+    float HA[AW / 4], HB[NQ][4];
     read_op_a(sX, stride, L, HA);
     read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    if (a.W0) load_planar(sX, stride, NW, a.W0 + b * K * M, K, M, false, 1.0f);
-    else load_planar(sX, stride, NW, Hb, K, M, true, cs.hs);              // W(0) = H^*
+    if (a.W0) load_planar(sX, stride, AW * NW, a.W0 + b * K * M, K, M, false, 1.0f);
+    else load_planar(sX, stride, AW * NW, Hb, K, M, true, cs.hs);         // W(0) = H^*
     __syncthreads();
-    float WD[4][4], WA[16];
+    float WD[NQ][4], WA[AW / 4];
     read_out_d(sX, stride, L, WD);
     read_op_a(sX, stride, L, WA);
     const float dg = a.d[L.lo & 7];
@@ -341,13 +342,13 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     for (int layer = 0; layer < a.layers; ++layer) {
         const float eta = (float)(a.etas[layer] * cs.es);
         const float thr = (float)(a.lambdas[layer] * a.etas[layer] * cs.es);
-        put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
+        put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial<AW>(WA, HA));
         __syncthreads();
         float E[4];                            // (A - D), embedded
         embed_operand<NW>(sD + ph * NW * kPartFloats, L, dg, E);
         ph ^= 1;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const f32x4 g = apply_block(E, HB, q);
             float v[4];
             float n2 = 0.0f;
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
         read_op_a(sX, stride, L, WA);
     }
     const bool gains = a.rsum || a.sinr;
-    if (gains) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial(WA, HA));
+    if (gains) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial<AW>(WA, HA));
     __syncthreads();
 
     // outputs from the planar W (scaled back in the normalised mode)
@@ -447,18 +448,26 @@ PgdDev make_pgd_dev(int K, int M, const void* H, const double* gamma, double sig
     return d;
 }
 
+template <int AW>
+void launch_mfma(const PgdDev& d, dim3 grid, int nw, hipStream_t s) {
+    const size_t lds = pgd_mfma_lds_bytes(AW, nw);
+    switch (nw) {
+        case 1: pgd_mfma_kernel<AW, 1><<<grid, dim3(64), lds, s>>>(d); break;
+        case 2: pgd_mfma_kernel<AW, 2><<<grid, dim3(128), lds, s>>>(d); break;
+        case 3: pgd_mfma_kernel<AW, 3><<<grid, dim3(192), lds, s>>>(d); break;
+        default: pgd_mfma_kernel<AW, 4><<<grid, dim3(256), lds, s>>>(d); break;
+    }
+}
+
 dmimo_status run_pgd(const PgdDev& d, int64_t B, hipStream_t s) {
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pgd: B too large");
     const dim3 grid((unsigned)B);
     if (d.K <= 8) {
-        const int nw = (d.M + 63) / 64;
-        const size_t lds = pgd_mfma_lds_bytes(nw);
-        switch (nw) {
-            case 1: pgd_mfma_kernel<1><<<grid, dim3(64), lds, s>>>(d); break;
-            case 2: pgd_mfma_kernel<2><<<grid, dim3(128), lds, s>>>(d); break;
-            case 3: pgd_mfma_kernel<3><<<grid, dim3(192), lds, s>>>(d); break;
-            default: pgd_mfma_kernel<4><<<grid, dim3(256), lds, s>>>(d); break;
-        }
+        const int aw = pgd_antennas_per_wave(B, d.M);
+        const int nw = (d.M + aw - 1) / aw;
+        if (aw == 16) launch_mfma<16>(d, grid, nw, s);
+        else if (aw == 32) launch_mfma<32>(d, grid, nw, s);
+        else launch_mfma<64>(d, grid, nw, s);
         return check_launch("pgd_mfma_kernel");
     }
     pgd_kernel<16><<<grid, dim3(kPgdThreads), 0, s>>>(d);

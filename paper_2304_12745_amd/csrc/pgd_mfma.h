@@ -10,12 +10,14 @@
 //        E H16 = [Re(B H^*); Im(B H^*)]   (16 x M).
 // Both are exact 16 x 16 MFMA tiles at K = 8.
 //
-// One wave owns 64 antennas c0 .. c0+63.  Lane (hi, lo) = (lane >> 4, lane & 15).
-//   operand layout  "A":  16 floats, row lo at antennas c0 + 16 hi + c, c = 0..15;
+// One wave owns AW antennas c0 .. c0+AW-1 (AW = 16, 32 or 64; fewer antennas
+// per wave give shorter MFMA chains and more waves when channels are few).
+// Lane (hi, lo) = (lane >> 4, lane & 15).
+//   operand layout  "A":  AW/4 floats, row lo at antennas c0 + (AW/4) hi + c;
 //                         serves as both operands of D1 (the antenna order
 //                         inside a sum is free).
 //   operand layout  "B2": [q][s], row 4 s + hi at antenna c0 + 16 q + lo
-//                         (B operand of E H16, block q of 16 antennas, k-step s).
+//                         (B operand of E H16, block q < AW/16 of 16 antennas, k-step s).
 //   output layout   "D":  [q][r], row 4 hi + r at antenna c0 + 16 q + lo
 //                         (the MFMA result layout of E H16).
 //   E operand:            [s], E[lo][4 s + hi].
@@ -29,13 +31,15 @@ namespace dmimo {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kPgdMfmaMaxWaves = 4;     // 256 antennas
+constexpr int kPgdMfmaMaxWaves = 4;     // waves per channel
 constexpr int kPartFloats = 16 * 17;    // one wave's D1 partial, padded rows
 
 // Planar LDS image: row p * 8 + k holds part p (0 re, 1 im) of row k.  Row
-// stride 64 nw + 4 floats puts the four 16-lane groups of a wave on distinct banks.
-__device__ __forceinline__ int pl_stride(int nw) { return 64 * nw + 4; }
+// stride AW nw + 4 floats (AW nw is a multiple of 16) puts the four 16-lane
+// groups of a wave on distinct banks and keeps rows 16-byte aligned.
+__host__ __device__ __forceinline__ int pl_stride(int ncol) { return ncol + 4; }
 
+template <int AW>
 struct PgdLane {
     int tid, wave, lane, lo, hi, c0;
     __device__ PgdLane() {
@@ -44,15 +48,14 @@ struct PgdLane {
         lane = tid & 63;
         lo = lane & 15;
         hi = lane >> 4;
-        c0 = 64 * wave;
+        c0 = AW * wave;
     }
 };
 
 // scale * X (K x M, complex64, row-major) into the planar image, zero padded
-// to 8 x 64 nw, optionally conjugated.  All threads of the block take part.
-__device__ __forceinline__ void load_planar(float* sX, int stride, int nw, const float2* X, int K,
+// to 8 x ncol, optionally conjugated.  All threads of the block take part.
+__device__ __forceinline__ void load_planar(float* sX, int stride, int ncol, const float2* X, int K,
                                             int M, bool conj, float scale = 1.0f) {
-    const int ncol = 64 * nw;
     for (int e = threadIdx.x; e < 8 * ncol; e += blockDim.x) {
         const int k = e / ncol, m = e - k * ncol;
         float2 x = make_float2(0.f, 0.f);
@@ -62,11 +65,13 @@ __device__ __forceinline__ void load_planar(float* sX, int stride, int nw, const
     }
 }
 
-__device__ __forceinline__ void read_op_a(const float* sX, int stride, const PgdLane& L, float (&XA)[16]) {
-    // 16-byte aligned: stride and c0 + 16 hi are multiples of 4 floats
-    const float4* src = reinterpret_cast<const float4*>(sX + L.lo * stride + L.c0 + 16 * L.hi);
+template <int AW>
+__device__ __forceinline__ void read_op_a(const float* sX, int stride, const PgdLane<AW>& L,
+                                          float (&XA)[AW / 4]) {
+    // 16-byte aligned: stride and c0 + (AW/4) hi are multiples of 4 floats
+    const float4* src = reinterpret_cast<const float4*>(sX + L.lo * stride + L.c0 + (AW / 4) * L.hi);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < AW / 16; ++t) {
         const float4 v = src[t];
         XA[4 * t] = v.x;
         XA[4 * t + 1] = v.y;
@@ -75,23 +80,29 @@ __device__ __forceinline__ void read_op_a(const float* sX, int stride, const Pgd
     }
 }
 
-__device__ __forceinline__ void read_op_b2(const float* sX, int stride, const PgdLane& L, float (&XB)[4][4]) {
+template <int AW>
+__device__ __forceinline__ void read_op_b2(const float* sX, int stride, const PgdLane<AW>& L,
+                                           float (&XB)[AW / 16][4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < AW / 16; ++q)
 #pragma unroll
         for (int s = 0; s < 4; ++s) XB[q][s] = sX[(4 * s + L.hi) * stride + L.c0 + 16 * q + L.lo];
 }
 
-__device__ __forceinline__ void read_out_d(const float* sX, int stride, const PgdLane& L, float (&XD)[4][4]) {
+template <int AW>
+__device__ __forceinline__ void read_out_d(const float* sX, int stride, const PgdLane<AW>& L,
+                                           float (&XD)[AW / 16][4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < AW / 16; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) XD[q][r] = sX[(4 * L.hi + r) * stride + L.c0 + 16 * q + L.lo];
 }
 
-__device__ __forceinline__ void write_out_d(float* sX, int stride, const PgdLane& L, const float (&XD)[4][4]) {
+template <int AW>
+__device__ __forceinline__ void write_out_d(float* sX, int stride, const PgdLane<AW>& L,
+                                            const float (&XD)[AW / 16][4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < AW / 16; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) sX[(4 * L.hi + r) * stride + L.c0 + 16 * q + L.lo] = XD[q][r];
 }
@@ -103,15 +114,17 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// This wave's share of D1 = X16 H16^T over its 64 antennas.
-__device__ __forceinline__ f32x4 d1_partial(const float (&XA)[16], const float (&HA)[16]) {
+// This wave's share of D1 = X16 H16^T over its AW antennas.
+template <int AW>
+__device__ __forceinline__ f32x4 d1_partial(const float (&XA)[AW / 4], const float (&HA)[AW / 4]) {
     f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < 16; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(XA[c], HA[c], d, 0, 0, 0);
+    for (int c = 0; c < AW / 4; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(XA[c], HA[c], d, 0, 0, 0);
     return d;
 }
 
-__device__ __forceinline__ void put_partial(float* part, const PgdLane& L, f32x4 d) {
+template <int AW>
+__device__ __forceinline__ void put_partial(float* part, const PgdLane<AW>& L, f32x4 d) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) part[(4 * L.hi + r) * 17 + L.lo] = d[r];
 }
@@ -120,8 +133,8 @@ __device__ __forceinline__ void put_partial(float* part, const PgdLane& L, f32x4
 // entry summed over the partials in wave order); dg is this lane's diagonal
 // entry d[lo & 7], zero for no shift.  Column l = 4 s + hi lies in the top
 // half exactly for s < 2, so the block of every entry is known per s.
-template <int NW>
-__device__ __forceinline__ void embed_operand(const float* parts, const PgdLane& L, float dg,
+template <int NW, int AW>
+__device__ __forceinline__ void embed_operand(const float* parts, const PgdLane<AW>& L, float dg,
                                               float (&E)[4]) {
     const int ia = L.lo & 7;
     const bool itop = L.lo < 8;
@@ -157,7 +170,8 @@ __device__ __forceinline__ float gain_sq(const float* parts, int j, int k) {
 }
 
 // Block q of E H16 = [Re(B H^*); Im(B H^*)] in the output layout.
-__device__ __forceinline__ f32x4 apply_block(const float (&E)[4], const float (&HB)[4][4], int q) {
+template <int NQ>
+__device__ __forceinline__ f32x4 apply_block(const float (&E)[4], const float (&HB)[NQ][4], int q) {
     f32x4 g = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 4; ++s) g = __builtin_amdgcn_mfma_f32_16x16x4f32(E[s], HB[q][s], g, 0, 0, 0);
@@ -186,8 +200,19 @@ __device__ __forceinline__ float prox_scale(float nrm, float thr) {
     return nrm > thr ? 1.0f - thr * __builtin_amdgcn_rcpf(nrm) : 0.0f;
 }
 
-inline size_t pgd_mfma_lds_bytes(int nw) {
-    return sizeof(float) * (16 * (size_t)(64 * nw + 4) + 2 * (size_t)nw * kPartFloats);
+inline size_t pgd_mfma_lds_bytes(int aw, int nw) {
+    return sizeof(float) * (16 * (size_t)pl_stride(aw * nw) + 2 * (size_t)nw * kPartFloats);
+}
+
+// Antennas per wave: 64, unless the launch would leave most SIMDs idle
+// (fewer than 1024 waves at 64), then the smallest of 16 / 32 / 64 that still
+// covers M with at most 4 waves.
+inline int pgd_antennas_per_wave(int64_t channels, int M) {
+    const int64_t waves64 = channels * ((M + 63) / 64);
+    if (waves64 >= 1024) return 64;
+    if (M <= 64) return 16;
+    if (M <= 128) return 32;
+    return 64;
 }
 
 }  // namespace dmimo

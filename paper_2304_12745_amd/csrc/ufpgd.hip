@@ -52,16 +52,18 @@ __device__ __forceinline__ double wave_sum_d(double x) {
     return x;
 }
 
-template <int NW>
+template <int AW, int NW>
 __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     constexpr int nw = NW;
+    constexpr int NQ = AW / 16;                // 16-antenna blocks per wave
+    constexpr int TV = AW / 4;                 // tape floats per lane and layer
     extern __shared__ float smem[];
-    const int stride = pl_stride(nw);
+    const int stride = pl_stride(AW * NW);
     float* sX = smem;                                   // [16][stride]
     float* sD = smem + 16 * stride;                     // [2][nw][16][17]
     double* sT = reinterpret_cast<double*>(sD + 2 * nw * kPartFloats);   // [2][nw]
 
-    const PgdLane L;
+    const PgdLane<AW> L;
     const int64_t b = blockIdx.x;
     const int K = a.K, M = a.M, I = a.layers;
     const int64_t ch = a.idx ? (int64_t)a.idx[b] : b;
@@ -74,15 +76,15 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     const float2* Hb = a.H + ch * K * M;
     const bool grad = a.tapeV != nullptr;
 
-    load_planar(sX, stride, nw, Hb, K, M, false);
+    load_planar(sX, stride, AW * nw, Hb, K, M, false);
     __syncthreads();
-    float HA[16], HB[4][4];
+    float HA[AW / 4], HB[NQ][4];
     read_op_a(sX, stride, L, HA);
     read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    load_planar(sX, stride, nw, Hb, K, M, true);       // W(0) = H^*
+    load_planar(sX, stride, AW * nw, Hb, K, M, true);  // W(0) = H^*
     __syncthreads();
-    float WD[4][4], WA[16];
+    float WD[NQ][4], WA[AW / 4];
     read_out_d(sX, stride, L, WD);
     read_op_a(sX, stride, L, WA);
     const float dg = a.d[L.lo & 7];
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     for (int i = 0; i < I; ++i) {
         const float eta = (float)a.etas[i];
         const float thr = (float)(a.lambdas[i] * a.etas[i]);
-        put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial(WA, HA));
+        put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial<AW>(WA, HA));
         __syncthreads();
         float E[4];
         embed_operand<NW>(sD + ph * nw * kPartFloats, L, dg, E);
@@ -100,9 +102,9 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
         if (grad && L.wave == 0)
             *reinterpret_cast<float4*>(a.tapeE + ((b * I + i) * 64 + L.lane) * 4) =
                 make_float4(E[0], E[1], E[2], E[3]);
-        float* tv = grad ? a.tapeV + (((b * I + i) * nw + L.wave) * 64 + L.lane) * 16 : nullptr;
+        float* tv = grad ? a.tapeV + (((b * I + i) * nw + L.wave) * 64 + L.lane) * TV : nullptr;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const f32x4 g = apply_block(E, HB, q);
             float v[4];
             float n2 = 0.0f;
@@ -122,10 +124,10 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     }
 
     // cost and its cotangent
-    float nrm[4];
+    float nrm[NQ];
     double l21 = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         float n2 = 0.0f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) n2 = fmaf(WD[q][r], WD[q][r], n2);
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     }
     l21 = wave_sum_d(l21);
     if (L.lane == 0) sT[ph * nw + L.wave] = l21;
-    put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial(WA, HA));
+    put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial<AW>(WA, HA));
     __syncthreads();
     float E[4];
     embed_operand<NW>(sD + ph * nw * kPartFloats, L, dg, E);
@@ -150,9 +152,9 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     ph ^= 1;
     if (!grad) return;
 
-    float Gb[4][4];
+    float Gb[NQ][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const f32x4 g = apply_block(E, HB, q);
         const float inv = nrm[q] > 0.0f ? a.lam_c * __builtin_amdgcn_rcpf(nrm[q]) : 0.0f;
 #pragma unroll
@@ -164,11 +166,11 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
         const double lam_d = a.lambdas[i], eta_d = a.etas[i];
         const float eta = (float)eta_d;
         const float t = (float)(lam_d * eta_d);
-        const float* tv = a.tapeV + (((b * I + i) * nw + L.wave) * 64 + L.lane) * 16;
-        float Gv[4][4];
+        const float* tv = a.tapeV + (((b * I + i) * nw + L.wave) * 64 + L.lane) * TV;
+        float Gv[NQ][4];
         double dtp = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const float4 vv = *reinterpret_cast<const float4*>(tv + 4 * q);
             const float v[4] = {vv.x, vv.y, vv.z, vv.w};
             float n2 = 0.0f, rho = 0.0f;
@@ -195,9 +197,9 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
         dtp = wave_sum_d(dtp);
         write_out_d(sX, stride, L, Gv);
         wave_lds_sync();
-        float GA[16];
+        float GA[AW / 4];
         read_op_a(sX, stride, L, GA);
-        put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial(GA, HA));
+        put_partial(sD + (ph * nw + L.wave) * kPartFloats, L, d1_partial<AW>(GA, HA));
         if (L.lane == 0) sT[ph * nw + L.wave] = dtp;
         __syncthreads();
         float E2[4];                                     // A' = Gv H^T, embedded, no shift
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
         }
         ph ^= 1;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const f32x4 g = apply_block(E2, HB, q);
 #pragma unroll
             for (int r = 0; r < 4; ++r) Gb[q][r] = fmaf(-eta, g[r], Gv[q][r]);
@@ -281,11 +283,14 @@ struct UfpgdWs {
 };
 
 UfpgdWs ufpgd_ws_layout(int64_t B, int M, int layers) {
-    const int nw = (M + 63) / 64;
+    // the tape of V has M rounded up to the antennas of the waves (any AW)
+    // times 16 floats per 4 antennas (64 lanes x AW/4 floats per AW antennas)
+    const int aw = pgd_antennas_per_wave(B, M);
+    const int nw = (M + aw - 1) / aw;
     UfpgdWs w;
     size_t off = 0;
     w.tapeV = off;
-    off = align_up(off + sizeof(float) * (size_t)B * layers * nw * 64 * 16);
+    off = align_up(off + sizeof(float) * (size_t)B * layers * nw * 64 * (aw / 4));
     w.tapeE = off;
     off = align_up(off + sizeof(float) * (size_t)B * layers * 64 * 4);
     w.dlam = off;
@@ -298,17 +303,28 @@ UfpgdWs ufpgd_ws_layout(int64_t B, int M, int layers) {
     return w;
 }
 
-size_t ufpgd_lds_bytes(int nw) { return pgd_mfma_lds_bytes(nw) + sizeof(double) * 2 * nw; }
+size_t ufpgd_lds_bytes(int aw, int nw) { return pgd_mfma_lds_bytes(aw, nw) + sizeof(double) * 2 * nw; }
 
-void launch_grad(const UfpgdDev& d, int64_t B, int nw, hipStream_t s) {
-    const dim3 grid((unsigned)B);
-    const size_t lds = ufpgd_lds_bytes(nw);
+template <int AW>
+void launch_grad_aw(const UfpgdDev& d, dim3 grid, int nw, hipStream_t s) {
+    const size_t lds = ufpgd_lds_bytes(AW, nw);
     switch (nw) {
-        case 1: ufpgd_grad_kernel<1><<<grid, dim3(64), lds, s>>>(d); break;
-        case 2: ufpgd_grad_kernel<2><<<grid, dim3(128), lds, s>>>(d); break;
-        case 3: ufpgd_grad_kernel<3><<<grid, dim3(192), lds, s>>>(d); break;
-        default: ufpgd_grad_kernel<4><<<grid, dim3(256), lds, s>>>(d); break;
+        case 1: ufpgd_grad_kernel<AW, 1><<<grid, dim3(64), lds, s>>>(d); break;
+        case 2: ufpgd_grad_kernel<AW, 2><<<grid, dim3(128), lds, s>>>(d); break;
+        case 3: ufpgd_grad_kernel<AW, 3><<<grid, dim3(192), lds, s>>>(d); break;
+        default: ufpgd_grad_kernel<AW, 4><<<grid, dim3(256), lds, s>>>(d); break;
     }
+}
+
+// The antennas per wave follow pgd_antennas_per_wave(B, M), the same choice
+// the workspace layout makes.
+void launch_grad(const UfpgdDev& d, int64_t B, hipStream_t s) {
+    const dim3 grid((unsigned)B);
+    const int aw = pgd_antennas_per_wave(B, d.M);
+    const int nw = (d.M + aw - 1) / aw;
+    if (aw == 16) launch_grad_aw<16>(d, grid, nw, s);
+    else if (aw == 32) launch_grad_aw<32>(d, grid, nw, s);
+    else launch_grad_aw<64>(d, grid, nw, s);
 }
 
 UfpgdDev make_dev(const UfpgdArgs& g) {
@@ -340,7 +356,6 @@ size_t ufpgd_workspace_bytes(int64_t B, int M, int layers) {
 dmimo_status launch_ufpgd_grad(const UfpgdArgs& g, double* cost, double* dlam, double* deta,
                                void* ws, hipStream_t s) {
     UfpgdDev d = make_dev(g);
-    const int nw = (g.M + 63) / 64;
     d.cost = cost;
     if (dlam) {
         const UfpgdWs w = ufpgd_ws_layout(g.B, g.M, g.layers);
@@ -350,13 +365,12 @@ dmimo_status launch_ufpgd_grad(const UfpgdArgs& g, double* cost, double* dlam, d
         d.dlam = dlam;
         d.deta = deta;
     }
-    launch_grad(d, g.B, nw, s);
+    launch_grad(d, g.B, s);
     return check_launch("ufpgd_grad_kernel");
 }
 
 dmimo_status launch_ufpgd_train(const UfpgdArgs& g, const UfpgdTrainArgs& t, void* ws,
                                 hipStream_t s) {
-    const int nw = (g.M + 63) / 64;
     const UfpgdWs w = ufpgd_ws_layout(g.B, g.M, g.layers);
     char* base = static_cast<char*>(ws);
     UfpgdDev d = make_dev(g);
@@ -386,7 +400,7 @@ dmimo_status launch_ufpgd_train(const UfpgdArgs& g, const UfpgdTrainArgs& t, voi
     const int adam_threads = 64 * std::min(16, 2 * g.layers);
     for (int64_t step = 0; step < t.steps; ++step) {
         d.idx = t.idx + step * g.B;
-        launch_grad(d, g.B, nw, s);
+        launch_grad(d, g.B, s);
         ufpgd_adam_kernel<<<dim3(1), dim3(adam_threads), 0, s>>>(a, t.t0 + step + 1,
                                                         t.batch_cost ? t.batch_cost + step : nullptr);
     }
