@@ -91,7 +91,8 @@ def parse_args():
     p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=500)
-    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=2000,
+                   help="untimed steps first (enough to bring the GPU clocks up)")
     p.add_argument("--nx", type=int, default=512)
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="budget of the oracle CPU baseline (0 disables it)")
@@ -190,7 +191,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "powermap_mfma_kernel<1,2,8>",
+            "kernel": "powermap_mfma_kernel<1,4,8>",
             "achieved": round(achieved, 3),
             "peak": round(peak, 3),
             "unit": "T VALU lane-slots/s",
@@ -225,8 +226,9 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     """Warm up, then time exactly args.steps steps of the room workload.
 
     One step, in order on torch's current stream: the user channel, MR and
-    ZF precoders (Gram + FP64 Cholesky inside), the MR map, the ZF map.  HIP
-    events bracket every map launch on that stream.  (A variant with the MR
+    ZF precoders (Gram + FP64 Cholesky inside), the MR map, the ZF map.  One
+    pair of HIP events on that stream brackets the two map launches of a step
+    (a pair around each launch would add its own dispatch gap to each).  (A variant with the MR
     branch on a second stream was measured slower: 0.114 vs 0.094 ms/step,
     because the cross-queue event waits cost more than the overlap saves.)
     Returns (ms per step, mean map launch ms, maps, precoders).
@@ -243,23 +245,24 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
         D.channel(params, ap, upts, prec="f32", out=H)
         D.beamform(H, "mr", None, w.sigma2, w.p_total, prec, out=bf["mr"])
         D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=bf["zf"])
-        for i, p in enumerate(("mr", "zf")):
-            if e is not None:
-                e[2 * i].record()
+        if e is not None:
+            e[0].record()
+        for p in ("mr", "zf"):
             D.powermap(params, ap0, bf[p].W[0], gpts, w.sigma2, prec, out=maps[p])
-            if e is not None:
-                e[2 * i + 1].record()
+        if e is not None:
+            e[1].record()
 
     for _ in range(args.warmup):
         step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(events[i])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    launch = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in events) / (2 * args.steps)
+    # one event pair brackets the two back-to-back map launches of a step
+    launch = sum(e[0].elapsed_time(e[1]) for e in events) / (2 * args.steps)
     return ms, launch, maps, bf
 
 

@@ -117,6 +117,49 @@ constexpr int f32_lds_bytes() {
 
 // One workgroup of the FP32 map: points wg_first .. wg_first + 16 PT WAVES - 1.
 // smem: at least f32_lds_bytes<NT, PT, WAVES>() bytes, 16-byte aligned.
+// The antenna steps of one LDS chunk: each step synthesises PT terms per lane
+// (antenna 4 s + grp) and feeds them to the MFMAs.  ROW: slot 1 of s_ap holds
+// fma(dy, dy, dz * dz) of the workgroup's grid row.
+template <int NT, int PT, bool ROW>
+__device__ __forceinline__ void f32_steps(const PmMapDev& a, int steps, int grp, int col,
+                                          const double* s_ap, const float* s_b, const double (&px)[PT],
+                                          const double (&py)[PT], const double (&pz)[PT],
+                                          f32x4 (&acc)[PT][NT]) {
+    constexpr int BS = NT * 32 + 16;
+    for (int s = 0; s < steps; ++s) {
+        const int mm = 4 * s + grp;
+        float hr[PT], hi[PT];
+        if constexpr (ROW) {
+            const double ax = s_ap[mm * 3 + 0];
+            const double c = s_ap[mm * 3 + 1];
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
+                const double dx = px[t] - ax;
+                wave_term_rev_d2(fma(dx, dx, c), a.amp_rev, a.inv_dmin_rev, hr[t], hi[t]);
+            }
+        } else {
+            const double ax = s_ap[mm * 3 + 0];
+            const double ay = s_ap[mm * 3 + 1];
+            const double az = s_ap[mm * 3 + 2];
+#pragma unroll
+            for (int t = 0; t < PT; ++t)
+                wave_term_rev(px[t] - ax, py[t] - ay, pz[t] - az, a.amp_rev, a.inv_dmin_rev, hr[t],
+                              hi[t]);
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const float b1 = s_b[mm * BS + q * 32 + col];
+            const float b2 = s_b[mm * BS + q * 32 + 16 + col];
+#pragma unroll
+            for (int t = 0; t < PT; ++t)
+                acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(hr[t], b1, acc[t][q], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < PT; ++t)
+                acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(hi[t], b2, acc[t][q], 0, 0, 0);
+        }
+    }
+}
+
 template <int NT, int PT, int WAVES>
 __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, char* smem) {
     constexpr int NTH = 64 * WAVES;
@@ -148,12 +191,39 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // When every point of the workgroup lies on one grid row, y and z are the
+    // same for all of them, so fma(dy, dy, dz * dz) is formed once per antenna
+    // (slot 1 of s_ap) and a term needs only dx: d2 = fma(dx, dx, C), the
+    // same bits as the general path.
+    bool row = false;
+    double ry = 0.0, rz = 0.0;
+    if (a.P.kind == DMIMO_PTS_GRID) {
+        const int64_t last = min(wg_first + (int64_t)16 * PT * WAVES, N) - 1;
+        row = wg_first / a.P.nx == last / a.P.nx;
+        double rx;
+        point_rev(a, wg_first < N ? wg_first : N - 1, rx, ry, rz);
+    }
+
     for (int m0 = 0; m0 < M; m0 += kChunk) {
         const int mc = min(kChunk, M - m0);
         __syncthreads();
-        for (int e = tid; e < kChunk * 3; e += NTH) {
-            const int mm = e / 3;
-            s_ap[e] = mm < mc ? a.ap[(int64_t)(m0 + mm) * 3 + (e - 3 * mm)] * a.inv_lam : 0.0;
+        if (row) {
+            for (int mm = tid; mm < kChunk; mm += NTH) {
+                double ax = 0.0, c = 0.0;
+                if (mm < mc) {
+                    const double* q = a.ap + (int64_t)(m0 + mm) * 3;
+                    ax = q[0] * a.inv_lam;
+                    const double dy = ry - q[1] * a.inv_lam, dz = rz - q[2] * a.inv_lam;
+                    c = fma(dy, dy, dz * dz);
+                }
+                s_ap[mm * 3 + 0] = ax;
+                s_ap[mm * 3 + 1] = c;
+            }
+        } else {
+            for (int e = tid; e < kChunk * 3; e += NTH) {
+                const int mm = e / 3;
+                s_ap[e] = mm < mc ? a.ap[(int64_t)(m0 + mm) * 3 + (e - 3 * mm)] * a.inv_lam : 0.0;
+            }
         }
         for (int e = tid; e < kChunk * NT * 16; e += NTH) {
             const int mm = e / (NT * 16);
@@ -169,28 +239,10 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
         }
         __syncthreads();
         const int steps = (mc + 3) >> 2;
-        for (int s = 0; s < steps; ++s) {
-            const int mm = 4 * s + grp;
-            const double ax = s_ap[mm * 3 + 0];
-            const double ay = s_ap[mm * 3 + 1];
-            const double az = s_ap[mm * 3 + 2];
-            float hr[PT], hi[PT];
-#pragma unroll
-            for (int t = 0; t < PT; ++t)
-                wave_term_rev(px[t] - ax, py[t] - ay, pz[t] - az, a.amp_rev, a.inv_dmin_rev, hr[t],
-                              hi[t]);
-#pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                const float b1 = s_b[mm * BS + q * 32 + col];
-                const float b2 = s_b[mm * BS + q * 32 + 16 + col];
-#pragma unroll
-                for (int t = 0; t < PT; ++t)
-                    acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(hr[t], b1, acc[t][q], 0, 0, 0);
-#pragma unroll
-                for (int t = 0; t < PT; ++t)
-                    acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(hi[t], b2, acc[t][q], 0, 0, 0);
-            }
-        }
+        if (row)
+            f32_steps<NT, PT, true>(a, steps, grp, col, s_ap, s_b, px, py, pz, acc);
+        else
+            f32_steps<NT, PT, false>(a, steps, grp, col, s_ap, s_b, px, py, pz, acc);
     }
     __syncthreads();
     map_epilogue<NT, PT>(a, acc, base, lane,

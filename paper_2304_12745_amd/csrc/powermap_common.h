@@ -60,9 +60,8 @@ __device__ __forceinline__ void point_rev(const PmMapDev& a, int64_t n, double& 
 //   h  = amp * (cos 2 pi fr - j sin 2 pi fr), with amp = 1 / (4 pi max(d, d_min)).
 // The hardware sin / cos take revolutions directly.  `scale` multiplies the
 // amplitude (the FP16 split path uses it to place h in the FP16 range).
-__device__ __forceinline__ void wave_term_rev(double dx, double dy, double dz, float amp_scaled,
-                                              float inv_dmin_rev, float& hr, float& hi) {
-    const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+__device__ __forceinline__ void wave_term_rev_d2(double d2, float amp_scaled, float inv_dmin_rev,
+                                                 float& hr, float& hi) {
     const float rs = __builtin_amdgcn_rsqf(fmaxf((float)d2, 1e-30f));
     const double y = (double)rs;
     const double s0 = d2 * y;
@@ -72,6 +71,11 @@ __device__ __forceinline__ void wave_term_rev(double dx, double dy, double dz, f
     const float amp = amp_scaled * fminf(rs, inv_dmin_rev);
     hr = amp * __builtin_amdgcn_cosf(fr);
     hi = -amp * __builtin_amdgcn_sinf(fr);
+}
+
+__device__ __forceinline__ void wave_term_rev(double dx, double dy, double dz, float amp_scaled,
+                                              float inv_dmin_rev, float& hr, float& hi) {
+    wave_term_rev_d2(fma(dx, dx, fma(dy, dy, dz * dz)), amp_scaled, inv_dmin_rev, hr, hi);
 }
 
 // Column layouts of the output tiles (see the kernels):
@@ -98,7 +102,7 @@ __device__ __forceinline__ float b_value(float2 w, int part, bool second) {
 // im^2 separately for NT = 1, stream powers for NT >= 2), padded by one.
 template <int NT>
 constexpr int ep_stride() {
-    return NT == 1 ? 17 : (NT == 2 ? 17 : 33);
+    return NT == 1 ? 20 : (NT == 2 ? 17 : 33);
 }
 
 // LDS bytes of the epilogue buffer of a workgroup of WAVES wavefronts.
@@ -146,10 +150,48 @@ __device__ __forceinline__ void map_epilogue(const PmMapDev& a, const f32x4 (&ac
     if (n >= a.P.n) return;
     const float* row = ep + lane * KS;
     const int K = a.K;
+    if constexpr (NT == 1) {
+        // all 16 columns at once (rows are 16-byte aligned), streams unrolled
+        float v[16];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float4 q = reinterpret_cast<const float4*>(row)[c];
+            v[4 * c] = q.x;
+            v[4 * c + 1] = q.y;
+            v[4 * c + 2] = q.z;
+            v[4 * c + 3] = q.w;
+        }
+        float p[8];
+        float y = 0.0f, pb = -1.0f;
+        int kb = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            p[k] = k < K ? v[k] + v[8 + k] : 0.0f;
+            y += p[k];
+            if (k < K && p[k] > pb) {
+                pb = p[k];
+                kb = k;
+            }
+        }
+        a.power[n] = y;
+        if (a.sinr) {
+            float intf = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k != kb) intf += p[k];
+            a.sinr[n] = pb * __builtin_amdgcn_rcpf(intf + a.sigma2);
+        }
+        if (a.best_k) a.best_k[n] = kb;
+        if (a.per_stream) {
+            float* ps = a.per_stream + n * K;
+            for (int k = 0; k < K; ++k) ps[k] = v[k] + v[8 + k];
+        }
+        return;
+    }
     float y = 0.0f, pb = -1.0f;
     int kb = 0;
     for (int k = 0; k < K; ++k) {
-        const float p = NT == 1 ? row[k] + row[8 + k] : row[k];
+        const float p = row[k];
         y += p;
         if (p > pb) {
             pb = p;
@@ -160,13 +202,13 @@ __device__ __forceinline__ void map_epilogue(const PmMapDev& a, const f32x4 (&ac
     if (a.sinr) {
         float intf = 0.0f;
         for (int k = 0; k < K; ++k)
-            if (k != kb) intf += NT == 1 ? row[k] + row[8 + k] : row[k];
+            if (k != kb) intf += row[k];
         a.sinr[n] = pb / (intf + a.sigma2);
     }
     if (a.best_k) a.best_k[n] = kb;
     if (a.per_stream) {
         float* ps = a.per_stream + n * K;
-        for (int k = 0; k < K; ++k) ps[k] = NT == 1 ? row[k] + row[8 + k] : row[k];
+        for (int k = 0; k < K; ++k) ps[k] = row[k];
     }
 }
 
