@@ -328,7 +328,59 @@ constexpr int x3_lds_bytes() {
 
 // One workgroup of the split-precision map: points wg_first .. + 16 PT WAVES - 1.
 // smem: at least x3_lds_bytes<NT, PT, WAVES>() bytes; s_red: WAVES floats.
-template <int NT, int PT, bool BF16, int WAVES>
+// The antenna steps of one chunk in the split-precision body: each lane
+// synthesises 8 consecutive antennas of each of its PT points, splits them
+// into hi / lo halves and runs the three products per tile.  ROW: table y
+// holds fma(dy, dy, dz * dz) of the workgroup's grid row.
+template <int NT, int PT, bool BF16, bool ROW>
+__device__ __forceinline__ void x3_steps(const PmMapDev& a, const X3Tables<NT>& T, int steps, int grp,
+                                         int lane, float amp_s, const double (&px)[PT],
+                                         const double (&py)[PT], const double (&pz)[PT],
+                                         f32x4 (&acc)[PT][NT]) {
+    for (int s = 0; s < steps; ++s) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            u32x4 arh, arl, aih, ail;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                const int mm = 32 * s + 8 * grp + i;
+                float hr0, hi0, hr1, hi1;
+                if constexpr (ROW) {
+                    const double dx0 = px[t] - T.x[mm], dx1 = px[t] - T.x[mm + 1];
+                    wave_term_rev_d2(fma(dx0, dx0, T.y[mm]), amp_s, a.inv_dmin_rev, hr0, hi0);
+                    wave_term_rev_d2(fma(dx1, dx1, T.y[mm + 1]), amp_s, a.inv_dmin_rev, hr1, hi1);
+                } else {
+                    wave_term_rev(px[t] - T.x[mm], py[t] - T.y[mm], pz[t] - T.z[mm], amp_s,
+                                  a.inv_dmin_rev, hr0, hi0);
+                    wave_term_rev(px[t] - T.x[mm + 1], py[t] - T.y[mm + 1], pz[t] - T.z[mm + 1],
+                                  amp_s, a.inv_dmin_rev, hr1, hi1);
+                }
+                float rr0, rr1, ri0, ri1;
+                arh[i >> 1] = pack_hi<BF16>(hr0, hr1, rr0, rr1);
+                aih[i >> 1] = pack_hi<BF16>(hi0, hi1, ri0, ri1);
+                arl[i >> 1] = pack_lo<BF16>(rr0, rr1);
+                ail[i >> 1] = pack_lo<BF16>(ri0, ri1);
+            }
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const u32x4 b1h = T.b[s][q][0][lane], b1l = T.b[s][q][1][lane];
+                const u32x4 b2h = T.b[s][q][2][lane], b2l = T.b[s][q][3][lane];
+                f32x4 c = acc[t][q];
+                c = mfma16<BF16>(arh, b1h, c);
+                c = mfma16<BF16>(arl, b1h, c);
+                c = mfma16<BF16>(arh, b1l, c);
+                c = mfma16<BF16>(aih, b2h, c);
+                c = mfma16<BF16>(ail, b2h, c);
+                c = mfma16<BF16>(aih, b2l, c);
+                acc[t][q] = c;
+            }
+        }
+    }
+}
+
+// ROWS: allow the grid-row step loop (a second copy of the loop; the serving
+// kernels, which hold more state, keep one copy and stay within 128 VGPRs).
+template <int NT, int PT, bool BF16, int WAVES, bool ROWS = true>
 __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, char* smem,
                                           float* s_red) {
     constexpr int NTH = 64 * WAVES;
@@ -363,6 +415,21 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
         for (int q = 0; q < NT; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     int wexp = 0;   // current chunk weight scale 2^wexp (FP16)
 
+    // grid-row workgroups form (y - a_y)^2 + (z - a_z)^2 once per antenna, as
+    // the FP32 body does (the same d2 bits).  Only for FP16 and NT >= 2: at
+    // NT = 1 the second copy of the step loop would push the body past 128
+    // VGPRs, and the BF16 body measured slower with it (hall map 7.50 vs
+    // 7.03 ms, against 7.18 vs 7.65 ms for FP16).
+    constexpr bool kRows = ROWS && NT >= 2 && !BF16;
+    bool row = false;
+    double ry = 0.0, rz = 0.0;
+    if (kRows && a.P.kind == DMIMO_PTS_GRID) {
+        const int64_t last = min(wg_first + (int64_t)16 * PT * WAVES, N) - 1;
+        row = wg_first / a.P.nx == last / a.P.nx;
+        double rx;
+        point_rev(a, wg_first < N ? wg_first : N - 1, rx, ry, rz);
+    }
+
     // table item of this thread: (step, tile, lane) = 8 antennas
     // 32 step + 8 (lane / 16) + i of column lane % 16 of the tile
     constexpr int kItems = 2 * NT * 64;
@@ -392,8 +459,18 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
         for (int e = tid; e < kChunk; e += NTH) {
             const bool live = e < mc;
             T.x[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 0] * a.inv_lam : 0.0;
-            T.y[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 1] * a.inv_lam : 0.0;
-            T.z[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 2] * a.inv_lam : 0.0;
+            if (row) {         // slot y holds fma(dy, dy, dz * dz) of the workgroup's row
+                double c = 0.0;
+                if (live) {
+                    const double dy = ry - a.ap[(int64_t)(m0 + e) * 3 + 1] * a.inv_lam;
+                    const double dz = rz - a.ap[(int64_t)(m0 + e) * 3 + 2] * a.inv_lam;
+                    c = fma(dy, dy, dz * dz);
+                }
+                T.y[e] = c;
+            } else {
+                T.y[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 1] * a.inv_lam : 0.0;
+                T.z[e] = live ? a.ap[(int64_t)(m0 + e) * 3 + 2] * a.inv_lam : 0.0;
+            }
         }
         float wscale = 1.0f;
         if constexpr (!BF16) {
@@ -443,39 +520,10 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
         }
         __syncthreads();
         const int steps = (mc + 31) >> 5;
-        for (int s = 0; s < steps; ++s) {
-#pragma unroll
-            for (int t = 0; t < PT; ++t) {
-                u32x4 arh, arl, aih, ail;
-#pragma unroll
-                for (int i = 0; i < 8; i += 2) {
-                    const int mm = 32 * s + 8 * grp + i;
-                    float hr0, hi0, hr1, hi1;
-                    wave_term_rev(px[t] - T.x[mm], py[t] - T.y[mm], pz[t] - T.z[mm], amp_s,
-                                  a.inv_dmin_rev, hr0, hi0);
-                    wave_term_rev(px[t] - T.x[mm + 1], py[t] - T.y[mm + 1], pz[t] - T.z[mm + 1],
-                                  amp_s, a.inv_dmin_rev, hr1, hi1);
-                    float rr0, rr1, ri0, ri1;
-                    arh[i >> 1] = pack_hi<BF16>(hr0, hr1, rr0, rr1);
-                    aih[i >> 1] = pack_hi<BF16>(hi0, hi1, ri0, ri1);
-                    arl[i >> 1] = pack_lo<BF16>(rr0, rr1);
-                    ail[i >> 1] = pack_lo<BF16>(ri0, ri1);
-                }
-#pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    const u32x4 b1h = T.b[s][q][0][lane], b1l = T.b[s][q][1][lane];
-                    const u32x4 b2h = T.b[s][q][2][lane], b2l = T.b[s][q][3][lane];
-                    f32x4 c = acc[t][q];
-                    c = mfma16<BF16>(arh, b1h, c);
-                    c = mfma16<BF16>(arl, b1h, c);
-                    c = mfma16<BF16>(arh, b1l, c);
-                    c = mfma16<BF16>(aih, b2h, c);
-                    c = mfma16<BF16>(ail, b2h, c);
-                    c = mfma16<BF16>(aih, b2l, c);
-                    acc[t][q] = c;
-                }
-            }
-        }
+        if (kRows && row)
+            x3_steps<NT, PT, BF16, kRows>(a, T, steps, grp, lane, amp_s, px, py, pz, acc);
+        else
+            x3_steps<NT, PT, BF16, false>(a, T, steps, grp, lane, amp_s, px, py, pz, acc);
     }
     // undo the scales (exact powers of two)
     const float inv = BF16 ? 1.0f : ldexpf(1.0f, -wexp) / kHScale;

@@ -87,7 +87,7 @@ void serve_kernel(const PmMapDev* __restrict__ slots, const ServeItem* __restric
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const ServeItem w = items[it];
         const PmMapDev a = slots[w.slot];
-        if constexpr (X3) map_x3_wg<NT, PT, BF16, kServeWaves>(a, w.first, smem, s_red);
+        if constexpr (X3) map_x3_wg<NT, PT, BF16, kServeWaves, false>(a, w.first, smem, s_red);
         else map_f32_wg<NT, PT, kServeWaves>(a, w.first, smem);
         __syncthreads();   // LDS is reused by the next item
     }
