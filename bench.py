@@ -496,6 +496,7 @@ def pa_phase(w, D, WL, torch, params, ap0, gpts):
     pcg_b = (zfb.l21 / rb.l21)
     off_b = (rb.p_ant == 0).sum(dim=1).double()
     flops = 16 * K * K * M * it
+    hall = pa_hall(D, WL, torch, lam, er, timed)
     return {
         "workload": f"room deployment: M={M} jittered ceiling APs, the step's K={K} users, "
                     "SINR targets 10 dB, noise -90 dBm; lambda 1/15, eta = 1/lambda_max, "
@@ -515,7 +516,40 @@ def pa_phase(w, D, WL, torch, params, ap0, gpts):
                     "mean_pcg": round(pcg_b.mean().item(), 4),
                     "min_pcg": round(pcg_b.min().item(), 4),
                     "mean_aps_off": round(off_b.mean().item(), 2)},
+        "hall": hall,
     }
+
+
+def pa_hall(D, WL, torch, lam, er, timed):
+    """The PA-aware precoder on the hall (32 users, 32 x 32 ceiling APs, 5.8
+    GHz, targets 10 dB, -90 dBm) on the slab path, and the full 2048 x 2048
+    power + SINR map of its sparse W."""
+    import numpy as np
+
+    w = WL.hall_workload()
+    K, M, N = w.K, w.M, w.grid.n
+    gamma = np.full(K, 10.0)
+    params = D.channel_params(w.freq_hz)
+    ap = torch.from_numpy(w.ap_xyz).cuda()
+    H = D.channel(params, ap, D.list_points(torch.from_numpy(w.user_xyz).cuda(), K), prec="f32")
+    r = D.pa_precoder(H, lam, er, gamma, w.sigma2)
+    ms = timed(lambda: D.pa_precoder(H, lam, er, gamma, w.sigma2, out=r), 2)
+    zf = D.beamform(H, "zf", gamma, w.sigma2, 0.0, "f32")
+    gpts = D.grid_points(w.grid)
+    ap0 = ap[0].contiguous()
+    mp = D.powermap(params, ap0, r.W[0].contiguous(), gpts, w.sigma2, "f32", want_best=False)
+    ms_map = timed(lambda: D.powermap(params, ap0, r.W[0].contiguous(), gpts, w.sigma2, "f32",
+                                      out=mp), 2)
+    sinr_db = 10 * torch.log10(r.sinr[0])
+    return {"workload": f"hall: M={M} regular ceiling APs (50 x 50 m, z = 5 m), K={K} users, "
+                        f"5.8 GHz, targets 10 dB, noise -90 dBm; {lam.numel()} iterations",
+            "precoder_ms": round(ms, 3),
+            "pcg_vs_zf": round((zf.l21[0] / r.l21[0]).item(), 4),
+            "aps_off": int((r.p_ant[0] == 0).sum().item()),
+            "sinr_db_min": round(sinr_db.min().item(), 3),
+            "sinr_db_max": round(sinr_db.max().item(), 3),
+            "map_2048x2048_ms": round(ms_map, 3),
+            "map_terms": N * M}
 
 
 def cpu_baseline(w, bf, maps, budget_s):

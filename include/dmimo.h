@@ -203,7 +203,11 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
  * The back-mapping is exact for the constraint: H W^T = sqrt(sigma2) Hn Wn^T.
  * lambdas keep the meaning they have for unit-variance channels (1/15 in
  * Sec. VI-C); eta_rel = 1 is the largest step of Sec. IV.
- *   H          device complex64 [B][K][M]; 1 <= K <= 16, 1 <= M <= 256.
+ *   H          device complex64 [B][K][M]; 1 <= K <= 32, 1 <= M <= 4096.
+ *              K <= 16 and M <= 256: one workgroup per deployment for all
+ *              layers.  Larger deployments (e.g. 32 users on 1024 APs): slabs
+ *              of 64 antennas, one workgroup each, two launches per layer,
+ *              at most 65535 deployments per call.
  *   gamma_lin  host [K] SINR targets (linear) or NULL (ones); sigma2 > 0.
  *   lambdas, eta_rel  device FP64 [layers].
  *   W          device complex64 [B][K][M] output.

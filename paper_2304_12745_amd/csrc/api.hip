@@ -158,8 +158,11 @@ size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32
             const size_t elem = prec == DMIMO_F64 ? 16 : 8;
             return align256((size_t)B * K * K * elem);
         }
-        case DMIMO_CALL_PA_PRECODER:
-            return align256((size_t)B * 2 * sizeof(double));
+        case DMIMO_CALL_PA_PRECODER: {
+            if (K > 32 || M < 1 || M > 4096) return 0;
+            const size_t f = align256((size_t)B * 2 * sizeof(double));
+            return (K > 16 || M > 256) ? f + align256(pa_large_workspace_bytes(B, K, M)) : f;
+        }
         default:
             return 0;
     }
@@ -320,7 +323,7 @@ dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
     clear_error();
     if (B < 0 || layers < 0) return fail(DMIMO_E_SHAPE, "pa_precoder: B and layers must be >= 0");
     if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "pa_precoder: K and M must be >= 1");
-    if (K > 16 || M > 256) return fail(DMIMO_E_SHAPE, "pa_precoder: K <= 16 and M <= 256");
+    if (K > 32 || M > 4096) return fail(DMIMO_E_SHAPE, "pa_precoder: K <= 32 and M <= 4096");
     if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "pa_precoder: unknown precision");
     if (prec != DMIMO_F32) return fail(DMIMO_E_UNSUPPORTED, "pa_precoder: FP32 only");
     if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(DMIMO_E_ARG, "pa_precoder: sigma2 must be > 0");
@@ -332,6 +335,10 @@ dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
     if (layers > 0 && (!lambdas || !eta_rel)) return fail(DMIMO_E_ARG, "pa_precoder: NULL lambdas or eta_rel");
     if (!ws || ws_bytes < dmimo_workspace_size(DMIMO_CALL_PA_PRECODER, B, K, M, 0, prec))
         return fail(DMIMO_E_WORKSPACE, "pa_precoder: workspace smaller than dmimo_workspace_size()");
+    if (K > 16 || M > 256)
+        return launch_pa_large(B, K, M, H, gamma_lin, sigma2, layers, lambdas, eta_rel, W, p_ant,
+                               l21, sinr, rsum, ws, align256((size_t)B * 2 * sizeof(double)),
+                               as_stream(stream));
     return launch_pa_precoder(B, K, M, H, gamma_lin, sigma2, layers, lambdas, eta_rel, W, p_ant,
                               l21, sinr, rsum, ws, as_stream(stream));
 }

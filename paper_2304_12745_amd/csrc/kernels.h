@@ -54,6 +54,20 @@ dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* ga
                         int layers, const double* lambdas, const double* etas, const void* W0,
                         void* W, double* l21, double* rsum, hipStream_t s);
 
+// {1/s, 1/lambda_max(Hn Hn^H)} per channel into pa [B][2] (K <= 32)
+dmimo_status launch_pa_prepare(int64_t B, int K, int M, const void* H, double* pa, hipStream_t s);
+
+// workspace of the slab path of the PA precoder (K > 16 or M > 256), after
+// the [B][2] normalisation factors
+size_t pa_large_workspace_bytes(int64_t B, int K, int M);
+
+// the slab path (K <= 32, M <= 4096): ws holds the [B][2] factors, then at
+// byte pa_bytes the partials and E
+dmimo_status launch_pa_large(int64_t B, int K, int M, const void* H, const double* gamma,
+                             double sigma2, int layers, const double* lambdas, const double* eta_rel,
+                             void* W, double* p_ant, double* l21, double* sinr, double* rsum,
+                             void* ws, size_t pa_bytes, hipStream_t s);
+
 // ws: [B][2] FP64 normalisation factors, written here
 dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const double* gamma,
                                 double sigma2, int layers, const double* lambdas,

@@ -82,11 +82,12 @@ __device__ __forceinline__ PgdScale pgd_scale(const PgdDev& a, int64_t b) {
 // quotient of G at the largest-norm column of S.  Writes {1/s, s^2 /
 // lambda_max(G)} = {1/s, 1/lambda_max(Hn Hn^H)}; an all-zero channel gets
 // {0, 0}, which makes its output W = 0.
+template <int KM>
 __global__ __launch_bounds__(64) void pa_prepare_kernel(const float2* H, int K, int M, double* pa) {
-    __shared__ double Gr[16][17], Gi[16][17];     // G
-    __shared__ double Sr[16][17], Si[16][17];     // S
-    __shared__ double Tr[16][17], Ti[16][17];     // S^2
-    __shared__ double colnorm[16];
+    __shared__ double Gr[KM][KM + 1], Gi[KM][KM + 1];     // G
+    __shared__ double Sr[KM][KM + 1], Si[KM][KM + 1];     // S
+    __shared__ double Tr[KM][KM + 1], Ti[KM][KM + 1];     // S^2
+    __shared__ double colnorm[KM];
     const int64_t b = blockIdx.x;
     const int lane = threadIdx.x;
     const float2* Hb = H + b * K * M;
@@ -494,10 +495,17 @@ dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const do
     d.p_ant = p_ant;
     d.sinr = sinr;
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pa_precoder: B too large");
-    pa_prepare_kernel<<<dim3((unsigned)B), dim3(64), 0, s>>>(d.H, K, M, static_cast<double*>(ws));
-    dmimo_status st = check_launch("pa_prepare_kernel");
+    dmimo_status st = launch_pa_prepare(B, K, M, H, static_cast<double*>(ws), s);
     if (st) return st;
     return run_pgd(d, B, s);
+}
+
+dmimo_status launch_pa_prepare(int64_t B, int K, int M, const void* H, double* pa, hipStream_t s) {
+    if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pa_precoder: B too large");
+    const float2* h = reinterpret_cast<const float2*>(H);
+    if (K <= 16) pa_prepare_kernel<16><<<dim3((unsigned)B), dim3(64), 0, s>>>(h, K, M, pa);
+    else pa_prepare_kernel<32><<<dim3((unsigned)B), dim3(64), 0, s>>>(h, K, M, pa);
+    return check_launch("pa_prepare_kernel");
 }
 
 }  // namespace dmimo

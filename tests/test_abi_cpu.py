@@ -230,8 +230,14 @@ def test_pa_precoder_validation(lib):
                                      None, None, None, ws, nbytes, None)
 
     assert pa(K=0) == 2
-    assert pa(K=17) == 2
-    assert pa(M=257) == 2
+    assert pa(K=33) == 2
+    assert pa(M=4097) == 2
+    # K > 16 or M > 256 take the slab path, which needs the larger workspace
+    assert pa(K=17) == 4 and pa(M=257) == 4
+    big = lib.dmimo_workspace_size(D.CALL_PA_PRECODER, 4, 32, 1024, 0, D.F32)
+    assert big >= 256 + (2 * 4 * 16 + 4) * 64 * 64 * 4
+    assert pa(K=32, M=1024, nbytes=big - 1) == 4
+    assert lib.dmimo_workspace_size(D.CALL_PA_PRECODER, 4, 33, 64, 0, D.F32) == 0
     assert pa(B=-1) == 2
     assert pa(prec=D.F64) == 6
     assert pa(prec=11) == 3

@@ -130,3 +130,52 @@ def test_zero_channel_and_scale_covariance(D):
     r2 = D.pa_precoder(torch.from_numpy((H * 1e3).astype(np.complex64)).cuda(), lams, er, gamma, 1e-12)
     e = _rel(r2.W.cpu().numpy()[[0, 2]] * 1e3, W[[0, 2]])
     assert e.max() < 1e-5
+
+
+def _hall_like(n, K, M, seed):
+    """n user draws on a regular ceiling grid of M APs (the hall workload's
+    geometry, 5.8 GHz), a square grid of side sqrt(M)."""
+    rng = np.random.default_rng(seed)
+    side = int(round(np.sqrt(M)))
+    pitch = 50.0 / side
+    aps = WL.ceiling_grid(side, side, pitch, 5.0)[:M]
+    room = side * pitch
+    return np.stack([O.los_channel(WL.uniform_positions(rng, K, room, room, 1.0), aps, 5.8e9)
+                     for _ in range(n)])
+
+
+def test_slab_path_hall_deployment(D):
+    say("pa_precoder slab path: hall K=32, M=1024, 120 layers")
+    H = _hall_like(1, 32, 1024, seed=31)
+    _compare(D, H, np.full(32, 10.0), 1e-12, [1 / 15] * 120, [1.0] * 120)
+
+
+@pytest.mark.parametrize("B,K,M", [(3, 20, 64), (2, 12, 300), (2, 32, 130), (1, 17, 4096)])
+def test_slab_path_shapes(D, B, K, M):
+    say(f"pa_precoder slab path: B={B} K={K} M={M}")
+    rng = np.random.default_rng(B * 1000 + K * 10 + M)
+    if M == 4096:
+        H = _hall_like(B, K, M, seed=K)
+        lams, er = [0.1] * 8, [1.0] * 8
+    else:
+        side = int(np.ceil(np.sqrt(M)))
+        aps = WL.ceiling_grid(side, side, 20.0 / side, 4.0, jitter_frac=0.25, rng=rng)[:M]
+        H = np.stack([O.los_channel(WL.uniform_positions(rng, K, 20.0, 20.0, 1.2), aps, 3.5e9)
+                      for _ in range(B)])
+        lams = rng.uniform(0.0, 0.4, 30)
+        er = rng.uniform(0.5, 1.0, 30)
+    _compare(D, H, rng.uniform(3.0, 20.0, K), 1e-12, lams, er)
+
+
+def test_slab_path_zero_lambda_gives_zf(D):
+    say("pa_precoder slab path lambda = 0, 1500 iterations -> ZF, K=24 M=512")
+    H = _hall_like(1, 24, 512, seed=33)
+    gamma = np.full(24, 10.0)
+    r = D.pa_precoder(torch.from_numpy(H.astype(np.complex64)).cuda(), [0.0] * 1500, [1.0] * 1500,
+                      gamma, 1e-12)
+    Hc = H.astype(np.complex64).astype(np.complex128)
+    Wo, _, _ = PA.pa_precoder(Hc, gamma, 1e-12, [0.0] * 1500, [1.0] * 1500)
+    Wzf, _ = O.zf_precoder(Hc, gamma, 1e-12, 0.0)
+    e = _rel(r.W.cpu().numpy(), Wo)
+    say(f"    W rel err vs oracle {e.max():.2e}, oracle vs ZF {_rel(Wo, Wzf).max():.2e}")
+    assert e.max() < 2e-4
