@@ -8,13 +8,16 @@
 //   D1 = X64 H64^T (64 x 64):  Ar = D1[a][b] - D1[32+a][32+b],
 //                              Ai = D1[a][32+b] + D1[32+a][b];
 //   E  = [[Ar - D, Ai], [Ai, -(Ar - D)]];   E H64 = [Re((A - D) H^*); Im(...)].
-// The antennas are cut into slabs of 64; one single-wave workgroup owns a
-// slab of one deployment.  Each layer is two launches:
+// The antennas are cut into slabs of 64; one four-wave workgroup owns a slab
+// of one deployment, wave w the 16-row tile w of both products.  Each layer
+// is two launches:
 //   lg_reduce_kernel  sums the slabs' D1 partials (fixed slab order) into E,
-//                     once per deployment;
-//   lg_layer_kernel   per slab: G = E H64 (256 MFMA 16x16x4), V = W - eta G,
-//                     the column prox, W back to memory, and the slab's D1
-//                     partial of the new W (256 MFMA) for the next layer.
+//                     one entry per thread;
+//   lg_layer_kernel   per slab: G = E H64 (64 MFMA 16x16x4 per wave),
+//                     V = W - eta G, the column prox (column norms combined
+//                     across the waves in LDS), W back to memory, and the
+//                     slab's D1 partial of the new W (64 MFMA per wave) for
+//                     the next layer.
 // lg_init_kernel writes W(0) = Hn^* and its partials; lg_final_kernel maps W
 // back and forms p_m, ||W||_{2,1}, SINR_k and the sum rate.
 #include <cmath>
@@ -59,7 +62,7 @@ __device__ __forceinline__ float* part_ptr(const LgDev& a, int parity, int64_t b
 // and optionally conjugated: sX[R][c], R < 32 real parts, R >= 32 imaginary.
 __device__ __forceinline__ void lg_load_slab(float* sX, const float2* X, int K, int M, int c0,
                                              float scale, bool conj) {
-    for (int e = threadIdx.x; e < kLgMaxK * kLgSlab; e += 64) {
+    for (int e = threadIdx.x; e < kLgMaxK * kLgSlab; e += blockDim.x) {
         const int k = e / kLgSlab, c = e - k * kLgSlab;
         float2 x = make_float2(0.f, 0.f);
         if (k < K && c0 + c < M) x = X[(int64_t)k * M + c0 + c];
@@ -68,96 +71,85 @@ __device__ __forceinline__ void lg_load_slab(float* sX, const float2* X, int K, 
     }
 }
 
-// D1 partial of the slab: X64 (planar sX) times H64^T (planar sH), 16 tiles;
-// lane (hi, lo) ends with D1[16 r + 4 hi + v][16 r' + lo] in acc[r][r'][v].
-__device__ __forceinline__ void lg_partial(const float* sX, const float* sH, int lo, int hi,
-                                           f32x4 (&acc)[4][4]) {
+// Row tile r of the slab's D1 partial: X64 (planar sX) times H64^T (planar
+// sH); lane (hi, lo) ends with D1[16 r + 4 hi + v][16 r' + lo] in acc[r'][v].
+__device__ __forceinline__ void lg_partial(const float* sX, const float* sH, int r, int lo, int hi,
+                                           f32x4 (&acc)[4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
     for (int c = 0; c < 16; ++c) {
-        float xa[4], ha[4];
+        const float xa = sX[(16 * r + lo) * kLgStride + 16 * hi + c];
+        float ha[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            xa[r] = sX[(16 * r + lo) * kLgStride + 16 * hi + c];
-            ha[r] = sH[(16 * r + lo) * kLgStride + 16 * hi + c];
-        }
+        for (int q = 0; q < 4; ++q) ha[q] = sH[(16 * q + lo) * kLgStride + 16 * hi + c];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[r], ha[q], acc[r][q], 0, 0, 0);
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, ha[q], acc[q], 0, 0, 0);
     }
 }
 
-__device__ __forceinline__ void lg_store_partial(float* dst, int lo, int hi, const f32x4 (&acc)[4][4]) {
+__device__ __forceinline__ void lg_store_partial(float* dst, int r, int lo, int hi, const f32x4 (&acc)[4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dst[(16 * r + 4 * hi + v) * kLgRows + 16 * q + lo] = acc[r][q][v];
+        for (int v = 0; v < 4; ++v) dst[(16 * r + 4 * hi + v) * kLgRows + 16 * q + lo] = acc[q][v];
 }
 
 // W(0) = Hn^* and its D1 partials (parity 0).
-__global__ __launch_bounds__(64) void lg_init_kernel(LgDev a) {
+__global__ __launch_bounds__(256) void lg_init_kernel(LgDev a) {
     __shared__ __attribute__((aligned(16))) float sH[kLgRows * kLgStride];
     __shared__ __attribute__((aligned(16))) float sW[kLgRows * kLgStride];
     const int64_t b = blockIdx.y;
     const int slab = blockIdx.x, c0 = kLgSlab * slab;
-    const int lane = threadIdx.x, lo = lane & 15, hi = lane >> 4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lo = lane & 15, hi = lane >> 4;
     const float hs = (float)a.pa[2 * b];
     const float2* Hb = a.H + b * a.K * a.M;
     lg_load_slab(sH, Hb, a.K, a.M, c0, hs, false);
     lg_load_slab(sW, Hb, a.K, a.M, c0, hs, true);
     __syncthreads();
     float2* Wb = a.W + b * a.K * a.M;
-    for (int e = lane; e < a.K * kLgSlab; e += 64) {
+    for (int e = tid; e < a.K * kLgSlab; e += 256) {
         const int k = e / kLgSlab, c = e - k * kLgSlab;
         if (c0 + c < a.M)
             Wb[(int64_t)k * a.M + c0 + c] = make_float2(sW[k * kLgStride + c], sW[(kLgMaxK + k) * kLgStride + c]);
     }
-    f32x4 acc[4][4];
-    lg_partial(sW, sH, lo, hi, acc);
-    lg_store_partial(part_ptr(a, 0, b, slab), lo, hi, acc);
+    f32x4 acc[4];
+    lg_partial(sW, sH, wave, lo, hi, acc);
+    lg_store_partial(part_ptr(a, 0, b, slab), wave, lo, hi, acc);
 }
 
-// E of one deployment from the S partials of parity `par`: workgroup
-// (row tile i, deployment b), 16 rows x 64 columns, 16 entries per lane.
+// E of one deployment from the S partials of parity `par`: one entry per
+// thread, workgroup (64 entries, deployment b).
 __global__ __launch_bounds__(64) void lg_reduce_kernel(LgDev a, int par) {
     const int64_t b = blockIdx.y;
-    const int i = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int e = blockIdx.x * 64 + threadIdx.x;           // < 4096
+    const int R = e / kLgRows, C = e % kLgRows;
     const float* p0 = part_ptr(a, par, b, 0);
-    float* Eb = a.E + b * kLgPart;
-    for (int e = lane; e < 16 * kLgRows; e += 64) {
-        const int R = 16 * i + e / kLgRows, C = e % kLgRows;
-        const int ra = R & 31, cb = C & 31;
-        const bool top = R < 32, same = top == (C < 32);
-        // Ar[ra][cb] = D1[ra][cb] - D1[32+ra][32+cb];  Ai = D1[ra][32+cb] + D1[32+ra][cb]
-        const int i1 = ra * kLgRows + (same ? cb : 32 + cb);
-        const int i2 = (32 + ra) * kLgRows + (same ? 32 + cb : cb);
-        float x = 0.f, y = 0.f;
-        for (int sl = 0; sl < a.S; ++sl) {
-            x += p0[(int64_t)sl * kLgPart + i1];
-            y += p0[(int64_t)sl * kLgPart + i2];
-        }
-        float v = same ? x - y : x + y;
-        if (same && ra == cb && ra < a.K) v -= a.d[ra];
-        Eb[R * kLgRows + C] = (same && !top) ? -v : v;
+    const int ra = R & 31, cb = C & 31;
+    const bool top = R < 32, same = top == (C < 32);
+    // Ar[ra][cb] = D1[ra][cb] - D1[32+ra][32+cb];  Ai = D1[ra][32+cb] + D1[32+ra][cb]
+    const int i1 = ra * kLgRows + (same ? cb : 32 + cb);
+    const int i2 = (32 + ra) * kLgRows + (same ? 32 + cb : cb);
+    float x = 0.f, y = 0.f;
+    for (int sl = 0; sl < a.S; ++sl) {
+        x += p0[(int64_t)sl * kLgPart + i1];
+        y += p0[(int64_t)sl * kLgPart + i2];
     }
+    float v = same ? x - y : x + y;
+    if (same && ra == cb && ra < a.K) v -= a.d[ra];
+    a.E[b * kLgPart + e] = (same && !top) ? -v : v;
 }
 
 // One layer on one slab, then the slab's D1 partial of the new W (parity
-// `par ^ 1`).
-__global__ __launch_bounds__(64) void lg_layer_kernel(LgDev a, int layer, int par) {
+// `par ^ 1`).  Wave w: rows 16 w .. 16 w + 15 of G, V, W and of the partial.
+__global__ __launch_bounds__(256) void lg_layer_kernel(LgDev a, int layer, int par) {
     __shared__ __attribute__((aligned(16))) float sH[kLgRows * kLgStride];
     __shared__ __attribute__((aligned(16))) float sW[kLgRows * kLgStride];
+    __shared__ __attribute__((aligned(16))) float sE[kLgRows * kLgStride];
+    __shared__ float sN[4][kLgSlab];                   // per-wave column sums of |v|^2
     const int64_t b = blockIdx.y;
     const int slab = blockIdx.x, c0 = kLgSlab * slab;
-    const int lane = threadIdx.x, lo = lane & 15, hi = lane >> 4;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lo = lane & 15, hi = lane >> 4;
     const float hs = (float)a.pa[2 * b];
     const double es = a.pa[2 * b + 1];
     const float eta = (float)(a.eta_rel[layer] * es);
@@ -166,63 +158,59 @@ __global__ __launch_bounds__(64) void lg_layer_kernel(LgDev a, int layer, int pa
     float2* Wb = a.W + b * a.K * a.M;
     lg_load_slab(sH, Hb, a.K, a.M, c0, hs, false);
     lg_load_slab(sW, Wb, a.K, a.M, c0, 1.0f, false);
+    {
+        const float4* Eb = reinterpret_cast<const float4*>(a.E + b * kLgPart);
+        for (int e = tid; e < kLgPart / 4; e += 256) {
+            const int row = e >> 4, c4 = e & 15;
+            *reinterpret_cast<float4*>(sE + row * kLgStride + 4 * c4) = Eb[e];
+        }
+    }
     __syncthreads();
 
-    // G = E H64 on this slab: tile (row tile i, antenna block q), 16 k-steps
-    const float* Eb = a.E + b * kLgPart;
-    f32x4 g[4][4];
+    // G row tile w = E[16 w .. 16 w + 15][:] H64, antenna blocks q, 16 k-steps
+    f32x4 g[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g[i][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+    for (int q = 0; q < 4; ++q) g[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
     for (int s = 0; s < 16; ++s) {
-        float ev[4], hb[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ev[i] = Eb[(16 * i + lo) * kLgRows + 4 * s + hi];
+        const float ev = sE[(16 * w + lo) * kLgStride + 4 * s + hi];
+        float hb[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) hb[q] = sH[(4 * s + hi) * kLgStride + 16 * q + lo];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                g[i][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev[i], hb[q], g[i][q], 0, 0, 0);
+        for (int q = 0; q < 4; ++q) g[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev, hb[q], g[q], 0, 0, 0);
     }
-    // V = W - eta G and the prox, per antenna column (q, lo): rows 16 i + 4 hi + v
+    // V = W - eta G on rows 16 w + 4 hi + v; this wave's share of each column's |v|^2
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         float n2 = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float w = sW[(16 * i + 4 * hi + v) * kLgStride + 16 * q + lo];
-                const float x = fmaf(-eta, g[i][q][v], w);
-                g[i][q][v] = x;
-                n2 = fmaf(x, x, n2);
-            }
-        const float sc = prox_scale(col_norm(column_sum(n2)), thr);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) g[i][q][v] *= sc;
+        for (int v = 0; v < 4; ++v) {
+            const float x = fmaf(-eta, g[q][v], sW[(16 * w + 4 * hi + v) * kLgStride + 16 * q + lo]);
+            g[q][v] = x;
+            n2 = fmaf(x, x, n2);
+        }
+        n2 = column_sum(n2);
+        if (hi == 0) sN[w][16 * q + lo] = n2;
     }
-    __syncthreads();                       // every lane has read its W before any is overwritten
+    __syncthreads();                       // all V formed and all W read; column sums in sN
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int q = 0; q < 4; ++q) {
+        const int c = 16 * q + lo;
+        const float n2 = (sN[0][c] + sN[1][c]) + (sN[2][c] + sN[3][c]);
+        const float sc = prox_scale(col_norm(n2), thr);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sW[(16 * i + 4 * hi + v) * kLgStride + 16 * q + lo] = g[i][q][v];
+        for (int v = 0; v < 4; ++v) sW[(16 * w + 4 * hi + v) * kLgStride + c] = sc * g[q][v];
+    }
     __syncthreads();
-    for (int e = lane; e < a.K * kLgSlab; e += 64) {
+    for (int e = tid; e < a.K * kLgSlab; e += 256) {
         const int k = e / kLgSlab, c = e - k * kLgSlab;
         if (c0 + c < a.M)
             Wb[(int64_t)k * a.M + c0 + c] = make_float2(sW[k * kLgStride + c], sW[(kLgMaxK + k) * kLgStride + c]);
     }
-    f32x4 acc[4][4];
-    lg_partial(sW, sH, lo, hi, acc);
-    lg_store_partial(part_ptr(a, par ^ 1, b, slab), lo, hi, acc);
+    f32x4 acc[4];
+    lg_partial(sW, sH, w, lo, hi, acc);
+    lg_store_partial(part_ptr(a, par ^ 1, b, slab), w, lo, hi, acc);
 }
 
 // Per deployment: SINR_k and the sum rate from the last partials (gains of
@@ -315,12 +303,12 @@ dmimo_status launch_pa_large(int64_t B, int K, int M, const void* H, const doubl
     a.B = B;
     dmimo_status st = launch_pa_prepare(B, K, M, H, static_cast<double*>(ws), s);
     if (st) return st;
-    const dim3 slabs((unsigned)a.S, (unsigned)B), tiles(4, (unsigned)B);
-    lg_init_kernel<<<slabs, 64, 0, s>>>(a);
+    const dim3 slabs((unsigned)a.S, (unsigned)B), entries(kLgPart / 64, (unsigned)B);
+    lg_init_kernel<<<slabs, 256, 0, s>>>(a);
     int par = 0;
     for (int i = 0; i < layers; ++i) {
-        lg_reduce_kernel<<<tiles, 64, 0, s>>>(a, par);
-        lg_layer_kernel<<<slabs, 64, 0, s>>>(a, i, par);
+        lg_reduce_kernel<<<entries, 64, 0, s>>>(a, par);
+        lg_layer_kernel<<<slabs, 256, 0, s>>>(a, i, par);
         par ^= 1;
     }
     lg_final_kernel<<<dim3((unsigned)B), 256, 0, s>>>(a, par);
