@@ -517,7 +517,69 @@ def pa_phase(w, D, WL, torch, params, ap0, gpts):
                     "min_pcg": round(pcg_b.min().item(), 4),
                     "mean_aps_off": round(off_b.mean().item(), 2)},
         "hall": hall,
+        "serving": pa_serving(w, D, WL, torch),
     }
+
+
+def pa_serving(w, D, WL, torch, rate=500.0, seconds=2.0):
+    """Precoder-design queries in the serving runtime: a Poisson stream (rate
+    1/s, `seconds` long) into one server holding the benchmark room; half the
+    queries are DMIMO_PA (20-layer PGD schedule, lambda 1/15, targets 10 dB),
+    half ZF; each brings 8 fresh users and asks for a 256 x 256 power + SINR
+    map at 1.2 m.  Latency = completion - arrival, per kind."""
+    import numpy as np
+
+    rng = np.random.default_rng(12)
+    n = int(rate * seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    kinds = np.where(rng.random(n) < 0.5, "pa", "zf")
+    users = [WL.uniform_positions(rng, w.K, 20.0, 20.0, 1.2) for _ in range(n)]
+    side = 256
+    grid = WL.Grid(0.0, 0.0, 20.0 / side, 20.0 / side, 1.2, side, side)
+    pts = D.grid_points(grid)
+    bufs = [(torch.empty(side * side, device="cuda"), torch.empty(side * side, device="cuda"))
+            for _ in range(128)]
+    free = list(range(len(bufs)))
+    srv = D.Server(4 << 30, 64)
+    dep = srv.add_deployment(D.channel_params(w.freq_hz), w.ap_xyz[0])
+    srv.set_pa_schedule([1.0 / 15.0] * 20, [1.0] * 20, 10.0)
+    torch.cuda.synchronize()
+    outstanding, lat = [], {"pa": [], "zf": []}
+    t0 = time.monotonic() + 0.05
+
+    def reap():
+        keep = []
+        for tk, kind, bi, ta in outstanding:
+            st, _, td = srv.poll(tk)
+            if st >= D.Q_DONE:
+                lat[kind].append(td - ta)
+                srv.release(tk)
+                free.append(bi)
+            else:
+                keep.append((tk, kind, bi, ta))
+        outstanding[:] = keep
+
+    for i in range(n):
+        ta = t0 + arrivals[i]
+        while time.monotonic() < ta or not free:
+            if outstanding:
+                reap()
+        bi = free.pop()
+        tk = srv.submit(dep, users[i], kinds[i], pts, w.sigma2, w.p_total, "f32", bufs[bi][0],
+                        bufs[bi][1])
+        outstanding.append((tk, kinds[i], bi, ta))
+    while outstanding:
+        srv.wait(outstanding[0][0], 30.0)
+        reap()
+    srv.close()
+    out = {"workload": f"Poisson {rate:.0f} q/s for {seconds:.0f} s into one server holding the "
+                       f"room: half PA-aware precoder queries (20 PGD layers), half ZF; 8 users "
+                       f"and a {side} x {side} power + SINR map each"}
+    for kind, v in lat.items():
+        a = np.array(v) * 1e3
+        out[kind] = {"queries": len(a), "p50_ms": round(float(np.percentile(a, 50)), 3),
+                     "p99_ms": round(float(np.percentile(a, 99)), 3)}
+    return out
 
 
 def pa_hall(D, WL, torch, lam, er, timed):
