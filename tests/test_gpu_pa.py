@@ -179,3 +179,21 @@ def test_slab_path_zero_lambda_gives_zf(D):
     e = _rel(r.W.cpu().numpy(), Wo)
     say(f"    W rel err vs oracle {e.max():.2e}, oracle vs ZF {_rel(Wo, Wzf).max():.2e}")
     assert e.max() < 2e-4
+
+
+def test_bench_launch_configuration_1024_rooms_sampled(D):
+    """The benchmark's batched launch (1024 deployments: 64 antennas per wave),
+    checked on 12 sampled deployments."""
+    say("pa_precoder: 1024 room draws in one launch, 300 iterations, sampled")
+    H = _rooms(1024, 8, seed=27)
+    gamma = np.full(8, 10.0)
+    r = D.pa_precoder(torch.from_numpy(H.astype(np.complex64)).cuda(), [1 / 15] * 300,
+                      [1.0] * 300, gamma, 1e-12)
+    torch.cuda.synchronize()
+    s = np.sort(np.random.default_rng(1).choice(1024, 12, replace=False))
+    Hc = H[s].astype(np.complex64).astype(np.complex128)
+    W, _, _ = PA.pa_precoder(Hc, gamma, 1e-12, [1 / 15] * 300, [1.0] * 300)
+    e = _rel(r.W.cpu().numpy()[s], W)
+    say(f"    W rel err max {e.max():.2e}")
+    assert e.max() < 1e-4
+    np.testing.assert_allclose(r.l21.cpu().numpy()[s], O.l21_norm(W), rtol=1e-4)

@@ -123,3 +123,30 @@ def test_pgd_5000_iterations_reaches_the_paper_optimum(D):
     off_o = np.all(Wo == 0, axis=1)
     say(f"    zero columns gpu {off_g.sum()} oracle {off_o.sum()} disagree {np.sum(off_g != off_o)}")
     assert off_o.sum() > 100 and np.sum(off_g != off_o) <= off_o.size // 1000
+
+
+def test_bench_launch_configuration_sampled(D):
+    """The benchmark's launches (5000 channels: 64 antennas per wave), checked
+    on sampled channels: 20 layers on 64 of them and 5000 iterations on 12."""
+    say("PGD at the benchmark size: 5000 channels, sampled against the oracle")
+    K, M = 8, 64
+    w = WL.paper_workload(seed=0, B=5000)
+    H = c64(w.H)
+    L = P.mp_edge(K, M)
+    rng = np.random.default_rng(0)
+    Hd = torch.from_numpy(H).cuda()
+    r20 = D.pgd(Hd, [1 / 15] * 20, [1 / L] * 20, w.gamma_lin, 1.0)
+    r5k = D.pgd(Hd, [1 / 15] * 5000, [1 / L] * 5000, w.gamma_lin, 1.0)
+    torch.cuda.synchronize()
+    s20 = np.sort(rng.choice(5000, 64, replace=False))
+    Wo = P.unfolded(H[s20].astype(np.complex128), w.gamma_lin, 1.0, [1 / 15] * 20, [1 / L] * 20)
+    e = _rel(r20.W.cpu().numpy()[s20], Wo)
+    say(f"    20 layers: W rel err max {e.max():.2e}")
+    assert e.max() < 1e-4
+    s5k = np.sort(rng.choice(5000, 12, replace=False))
+    Wo = P.pgd(H[s5k].astype(np.complex128), w.gamma_lin, 1.0, 1 / 15, 1 / L, 5000)
+    Wzf, _ = O.zf_precoder(H[s5k].astype(np.complex128), w.gamma_lin, 1.0, 0.0)
+    pcg_g = O.l21_norm(Wzf) / r5k.l21.cpu().numpy()[s5k]
+    say(f"    5000 iterations: PCG max |diff| {np.abs(pcg_g - P.pcg(Wzf, Wo)).max():.2e}")
+    assert np.abs(pcg_g - P.pcg(Wzf, Wo)).max() < 1e-5
+    assert np.median(_rel(r5k.W.cpu().numpy()[s5k], Wo)) < 1e-3
