@@ -38,6 +38,29 @@ class FitResult:
     steps: int = 0
 
 
+class EarlyStopping:
+    """Early stopping on the validation cost (Sec. VI-A): remember the epoch
+    with the lowest cost; stop after `patience` epochs in a row without a new
+    lowest.  update() returns True when the epoch is the new best."""
+
+    def __init__(self, patience: int):
+        self.patience = patience
+        self.best_cost = math.inf
+        self.best_epoch = -1
+        self.bad = 0
+
+    def update(self, epoch: int, cost: float) -> bool:
+        if cost < self.best_cost:
+            self.best_cost, self.best_epoch, self.bad = cost, epoch, 0
+            return True
+        self.bad += 1
+        return False
+
+    @property
+    def stop(self) -> bool:
+        return self.bad >= self.patience
+
+
 def fit(Htrain, Hval, gamma_lin, sigma2=1.0, lam_c=1.0 / 15.0, layers=20, epochs=200, batch=64,
         lr=1e-3, patience=10, seed=0, log=None) -> FitResult:
     """Train lambda_i, eta_i.  Htrain, Hval: device complex64 [n][K][M].
@@ -56,7 +79,8 @@ def fit(Htrain, Hval, gamma_lin, sigma2=1.0, lam_c=1.0 / 15.0, layers=20, epochs
     full = n // batch * batch
     ws = torch.empty((D.ufpgd_workspace_size(batch, K, M, layers),), dtype=torch.uint8, device=dev)
     res = FitResult([], [], -1, 0)
-    best_cost, best, bad = math.inf, None, 0
+    es = EarlyStopping(patience)
+    best = None
     t0 = time.perf_counter()
     for ep in range(epochs):
         perm = rng.permutation(n).astype(np.int32)
@@ -73,14 +97,12 @@ def fit(Htrain, Hval, gamma_lin, sigma2=1.0, lam_c=1.0 / 15.0, layers=20, epochs
         res.train_cost.append(tc.item() / nb)
         res.val_cost.append(val)
         res.epochs_run = ep + 1
-        if val < best_cost:
-            best_cost, best, bad, res.best_epoch = val, state.clone(), 0, ep
-        else:
-            bad += 1
+        if es.update(ep, val):
+            best, res.best_epoch = state.clone(), ep
         if log:
             log(f"epoch {ep + 1}: train cost {res.train_cost[-1]:.6f} val cost {val:.6f} "
                 f"({time.perf_counter() - t0:.1f} s)")
-        if bad >= patience:
+        if es.stop:
             break
     torch.cuda.synchronize()
     res.seconds = time.perf_counter() - t0
