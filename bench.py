@@ -396,6 +396,12 @@ def pgd_phase(args, D, WL, torch):
     zf = D.beamform(H, "zf", g, 1.0, 0.0, "f32")
     mszf = timed(lambda: D.beamform(H, "zf", g, 1.0, 0.0, "f32", out=zf), 20)
     pcg5k = (zf.l21 / out5k.l21).mean().item()
+    # the same two launches with BF16x3 layers (split products on BF16 MFMA)
+    x20 = D.pgd(H, lam20, eta20, g, 1.0, prec="bf16x3")
+    ms20_x3 = timed(lambda: D.pgd(H, lam20, eta20, g, 1.0, prec="bf16x3", out=x20), 50)
+    x5k = D.pgd(H, lam5k, eta5k, g, 1.0, prec="bf16x3")
+    ms5k_x3 = timed(lambda: D.pgd(H, lam5k, eta5k, g, 1.0, prec="bf16x3", out=x5k), 3, warm=1)
+    pcg5k_x3 = (zf.l21 / x5k.l21).mean().item()
 
     Htr = torch.from_numpy(WL.complex_normal(np.random.default_rng(9), (20000, K, M),
                                              np.complex64)).cuda()
@@ -417,6 +423,10 @@ def pgd_phase(args, D, WL, torch):
         "pgd5000_mean_pcg": round(pcg5k, 4),
         "pgd5000_mean_rsum": round(out5k.rsum.mean().item(), 4),
         "zf_ms": round(mszf, 4),
+        "bf16x3": {"ufpgd20_ms": round(ms20_x3, 4), "pgd5000_ms": round(ms5k_x3, 3),
+                   "pgd5000_mean_pcg": round(pcg5k_x3, 4),
+                   "note": "both products of every layer on BF16 MFMA, operands split hi + lo, "
+                           "three products accumulated in FP32"},
         "train_step_ms": round(ms_train, 4),
         "train_step": "batch 64, 20 layers: forward + reverse pass + Adam + projections",
         "roofline": {"bound": "mfma", "kernel": "pgd_mfma_kernel", "unit": "TFLOP/s",

@@ -183,7 +183,10 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M,
  *             plain PGD; projections onto lambda >= 0 and the eta interval
  *             are the caller's).
  *   W0        device complex64 [B][K][M] or NULL.
- *   prec      DMIMO_F32 (FP32 arithmetic; others: DMIMO_E_UNSUPPORTED).
+ *   prec      DMIMO_F32 (FP32 arithmetic), or DMIMO_MIX_BF16X3 for K <= 8: both
+ *             products of the layer on BF16 matrix cores, every operand split
+ *             as hi + lo and three products accumulated in FP32 (relative
+ *             error near 2^-17 per product); others: DMIMO_E_UNSUPPORTED.
  *   W         device complex64 [B][K][M] output.
  *   l21       device FP64 [B] or NULL: ||W||_{2,1} of the output (PA consumed
  *             power / alpha, eq. effmodel).
@@ -217,7 +220,8 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
  *   sinr       device FP64 [B][K] or NULL; rsum device FP64 [B] or NULL.
  *   ws         device workspace of dmimo_workspace_size(DMIMO_CALL_PA_PRECODER,
  *              B, K, M, 0, DMIMO_F32) bytes.
- * An all-zero channel gives W = 0.  FP32 only. */
+ * An all-zero channel gives W = 0.  prec: DMIMO_F32, or DMIMO_MIX_BF16X3 for
+ * K <= 8 and M <= 256 (as in dmimo_pgd). */
 dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
                                const double* gamma_lin, double sigma2, int32_t layers,
                                const double* lambdas, const double* eta_rel, int32_t prec,

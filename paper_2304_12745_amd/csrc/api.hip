@@ -302,7 +302,8 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
     if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "pgd: K and M must be >= 1");
     if (K > 16 || M > 256) return fail(DMIMO_E_SHAPE, "pgd: K <= 16 and M <= 256");
     if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "pgd: unknown precision");
-    if (prec != DMIMO_F32) return fail(DMIMO_E_UNSUPPORTED, "pgd: FP32 only");
+    if (prec != DMIMO_F32 && !(prec == DMIMO_MIX_BF16X3 && K <= 8))
+        return fail(DMIMO_E_UNSUPPORTED, "pgd: FP32, or BF16x3 for K <= 8");
     if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return fail(DMIMO_E_ARG, "pgd: sigma2 must be >= 0");
     if (rsum && !(sigma2 > 0.0)) return fail(DMIMO_E_ARG, "pgd: the sum rate needs sigma2 > 0");
     for (int k = 0; gamma_lin && k < K; ++k)
@@ -311,7 +312,7 @@ dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const dou
     if (B == 0) return DMIMO_OK;
     if (!H || !W) return fail(DMIMO_E_ARG, "pgd: NULL H or W");
     if (layers > 0 && (!lambdas || !etas)) return fail(DMIMO_E_ARG, "pgd: NULL lambdas or etas");
-    return launch_pgd(B, K, M, H, gamma_lin, sigma2, layers, lambdas, etas, W0, W, l21, rsum,
+    return launch_pgd(B, K, M, H, gamma_lin, sigma2, layers, lambdas, etas, W0, W, l21, rsum, prec,
                       as_stream(stream));
 }
 
@@ -325,7 +326,8 @@ dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
     if (K < 1 || M < 1) return fail(DMIMO_E_SHAPE, "pa_precoder: K and M must be >= 1");
     if (K > 32 || M > 4096) return fail(DMIMO_E_SHAPE, "pa_precoder: K <= 32 and M <= 4096");
     if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "pa_precoder: unknown precision");
-    if (prec != DMIMO_F32) return fail(DMIMO_E_UNSUPPORTED, "pa_precoder: FP32 only");
+    if (prec != DMIMO_F32 && !(prec == DMIMO_MIX_BF16X3 && K <= 8 && M <= 256))
+        return fail(DMIMO_E_UNSUPPORTED, "pa_precoder: FP32, or BF16x3 for K <= 8 and M <= 256");
     if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(DMIMO_E_ARG, "pa_precoder: sigma2 must be > 0");
     for (int k = 0; gamma_lin && k < K; ++k)
         if (!(gamma_lin[k] >= 0.0) || !std::isfinite(gamma_lin[k]))
@@ -340,7 +342,7 @@ dmimo_status dmimo_pa_precoder(int32_t B, int32_t K, int32_t M, const void* H,
                                l21, sinr, rsum, ws, align256((size_t)B * 2 * sizeof(double)),
                                as_stream(stream));
     return launch_pa_precoder(B, K, M, H, gamma_lin, sigma2, layers, lambdas, eta_rel, W, p_ant,
-                              l21, sinr, rsum, ws, as_stream(stream));
+                              l21, sinr, rsum, ws, prec, as_stream(stream));
 }
 
 size_t dmimo_ufpgd_workspace_size(int32_t B, int32_t K, int32_t M, int32_t layers) {

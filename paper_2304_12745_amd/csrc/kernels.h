@@ -52,7 +52,7 @@ dmimo_status launch_powermap(const PowermapArgs& a, hipStream_t s);
 
 dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* gamma, double sigma2,
                         int layers, const double* lambdas, const double* etas, const void* W0,
-                        void* W, double* l21, double* rsum, hipStream_t s);
+                        void* W, double* l21, double* rsum, int prec, hipStream_t s);
 
 // {1/s, 1/lambda_max(Hn Hn^H)} per channel into pa [B][2] (K <= 32)
 dmimo_status launch_pa_prepare(int64_t B, int K, int M, const void* H, double* pa, hipStream_t s);
@@ -72,7 +72,7 @@ dmimo_status launch_pa_large(int64_t B, int K, int M, const void* H, const doubl
 dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const double* gamma,
                                 double sigma2, int layers, const double* lambdas,
                                 const double* eta_rel, void* W, double* p_ant, double* l21,
-                                double* sinr, double* rsum, void* ws, hipStream_t s);
+                                double* sinr, double* rsum, void* ws, int prec, hipStream_t s);
 
 struct UfpgdArgs {
     int64_t B;              // channels per launch (the batch)

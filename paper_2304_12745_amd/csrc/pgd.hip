@@ -27,6 +27,7 @@
 
 #include "kernels.h"
 #include "pgd_mfma.h"
+#include "split16.h"
 
 namespace dmimo {
 
@@ -311,6 +312,66 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdDev a) {
 }
 
 
+// Outputs of a PGD workgroup from the planar W in sX (normalised mode:
+// scaled back): W, p_m, ||W||_{2,1}, and from the last D1 partials (parity
+// ph) the SINR_k and the sum rate.  Every thread of the block calls it after
+// a barrier that follows the last partials.
+template <int NW>
+__device__ __forceinline__ void pgd_outputs(const PgdDev& a, int64_t b, int tid, int lane, int wave,
+                                            const float* sX, int stride, float* sD, int ph,
+                                            const PgdScale& cs) {
+    const int K = a.K, M = a.M;
+    const bool gains = a.rsum || a.sinr;
+    // outputs from the planar W (scaled back in the normalised mode)
+    float2* Wb = a.W + b * K * M;
+    const float wsf = (float)cs.ws;
+    for (int e = tid; e < K * M; e += blockDim.x) {
+        const int k = e / M, m = e - k * M;
+        Wb[e] = make_float2(wsf * sX[k * stride + m], wsf * sX[(8 + k) * stride + m]);
+    }
+    // scratch for the reductions: the partial buffer of the other parity
+    double* red = reinterpret_cast<double*>(sD + (ph ^ 1) * NW * kPartFloats);
+    if (a.l21 || a.p_ant) {
+        double s = 0.0;
+        for (int m = tid; m < M; m += blockDim.x) {
+            double p = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const double x = sX[k * stride + m], y = sX[(8 + k) * stride + m];
+                p += x * x + y * y;
+            }
+            if (a.p_ant) a.p_ant[b * M + m] = cs.ws * cs.ws * p;
+            s += sqrt(p);
+        }
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) red[64 + wave] = s;
+    }
+    if (gains && wave == 0) {
+        // gains G = H W^T = A^T with A = W H^T from the last MFMA pass:
+        // lane 8 k + j holds |G_kj|^2 = |A_jk|^2
+        const int k = lane >> 3, j = lane & 7;
+        red[lane] = (k < K && j < K) ? (double)gain_sq<NW>(sD + ph * NW * kPartFloats, j, k) : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0 && a.l21) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += red[64 + w];
+        a.l21[b] = cs.ws * t;
+    }
+    if (gains && wave == 0) {
+        // user k = lane < K: SINR_k and log2(1 + SINR_k), then a sum over the 8 lanes
+        double r = 0.0;
+        if (lane < K) {
+            double sig = 0.0, intf = 0.0;
+            for (int jj = 0; jj < K; ++jj) (jj == lane ? sig : intf) += red[lane * 8 + jj];
+            const double sn = sig / (intf + a.sigma2);
+            if (a.sinr) a.sinr[b * K + lane] = sn;
+            r = log2(1.0 + sn);
+        }
+        for (int off = 4; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+        if (lane == 0 && a.rsum) a.rsum[b] = r;
+    }
+}
+
 template <int AW, int NW>
 __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     constexpr int NQ = AW / 16;                // 16-antenna blocks per wave
@@ -369,56 +430,162 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     const bool gains = a.rsum || a.sinr;
     if (gains) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial<AW>(WA, HA));
     __syncthreads();
+    pgd_outputs<NW>(a, b, L.tid, L.lane, L.wave, sX, stride, sD, ph, cs);
+}
 
-    // outputs from the planar W (scaled back in the normalised mode)
-    const int tid = L.tid;
-    float2* Wb = a.W + b * K * M;
-    const float wsf = (float)cs.ws;
-    for (int e = tid; e < K * M; e += blockDim.x) {
-        const int k = e / M, m = e - k * M;
-        Wb[e] = make_float2(wsf * sX[k * stride + m], wsf * sX[(8 + k) * stride + m]);
+// ---------------------------------------------------------------------------
+// BF16x3: the same layer with both products on the BF16 matrix cores, each
+// FP32 operand split as hi + lo (BF16) and the three products hi*hi + lo*hi +
+// hi*lo accumulated in FP32 (relative error near 2^-17 per product).  Unlike
+// the FP32 MFMA, the BF16 MFMA overlaps the VALU work of the other waves.
+//   step 1  v_mfma_f32_16x16x32_bf16: 32 antennas per product; lane (hi, lo)
+//           holds row lo at antennas c0 + 32 t + 8 hi + j (t < 2, j < 8);
+//   step 2  v_mfma_f32_16x16x16_bf16: lane (hi, lo) holds E[lo][4 hi + j]
+//           and H16[4 hi + j][c0 + 16 q + lo] (j < 4).
+// 64 antennas per wave.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void read_op_a32(const float* sX, int stride, const PgdLane<64>& L,
+                                            float (&XA)[16]) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        // 32-byte aligned: stride and c0 + 32 t + 8 hi are multiples of 4 floats
+        const float4* src = reinterpret_cast<const float4*>(sX + L.lo * stride + L.c0 + 32 * t + 8 * L.hi);
+        const float4 u = src[0], v = src[1];
+        XA[8 * t + 0] = u.x; XA[8 * t + 1] = u.y; XA[8 * t + 2] = u.z; XA[8 * t + 3] = u.w;
+        XA[8 * t + 4] = v.x; XA[8 * t + 5] = v.y; XA[8 * t + 6] = v.z; XA[8 * t + 7] = v.w;
     }
-    // scratch for the reductions: the partial buffer of the other parity
-    double* red = reinterpret_cast<double*>(sD + (ph ^ 1) * NW * kPartFloats);
-    if (a.l21 || a.p_ant) {
-        double s = 0.0;
-        for (int m = tid; m < M; m += blockDim.x) {
-            double p = 0.0;
-            for (int k = 0; k < K; ++k) {
-                const double x = sX[k * stride + m], y = sX[(8 + k) * stride + m];
-                p += x * x + y * y;
-            }
-            if (a.p_ant) a.p_ant[b * M + m] = cs.ws * cs.ws * p;
-            s += sqrt(p);
-        }
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (L.lane == 0) red[64 + L.wave] = s;
+}
+
+__device__ __forceinline__ void split_x8(const float* x, u32x4& hi, u32x4& lo) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float r0, r1;
+        hi[i] = pack_hi<true>(x[2 * i], x[2 * i + 1], r0, r1);
+        lo[i] = pack_lo<true>(r0, r1);
     }
-    if (gains && L.wave == 0) {
-        // gains G = H W^T = A^T with A = W H^T from the last MFMA pass:
-        // lane 8 k + j holds |G_kj|^2 = |A_jk|^2
-        const int k = L.lane >> 3, j = L.lane & 7;
-        red[L.lane] = (k < K && j < K) ? (double)gain_sq<NW>(sD + ph * NW * kPartFloats, j, k) : 0.0;
+}
+
+__device__ __forceinline__ void split_x4(const float* x, u32x2& hi, u32x2& lo) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        float r0, r1;
+        hi[i] = pack_hi<true>(x[2 * i], x[2 * i + 1], r0, r1);
+        lo[i] = pack_lo<true>(r0, r1);
+    }
+}
+
+// This wave's share of D1 = X16 H16^T over its 64 antennas, x3.
+__device__ __forceinline__ f32x4 d1_partial_x3(const float (&XA)[16], const u32x4 (&Hh)[2],
+                                               const u32x4 (&Hl)[2]) {
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        u32x4 xh, xl;
+        split_x8(XA + 8 * t, xh, xl);
+        d = mfma16<true>(xh, Hh[t], d);
+        d = mfma16<true>(xl, Hh[t], d);
+        d = mfma16<true>(xh, Hl[t], d);
+    }
+    return d;
+}
+
+// Entry E[i][l] of [[Br, Bi], [Bi, -Br]], B = (X H^T) - diag(dg), from the NW
+// partials of D1 (summed in wave order).
+template <int NW>
+__device__ __forceinline__ float embed_entry(const float* parts, int i, int l, float dg) {
+    const int ia = i & 7, lb = l & 7;
+    const bool itop = i < 8;
+    const bool same = itop == (l < 8);
+    const int a1 = ia * 17 + (same ? lb : 8 + lb);
+    const int a2 = (8 + ia) * 17 + (same ? 8 + lb : lb);
+    float x = 0.0f, y = 0.0f;
+#pragma unroll
+    for (int p = 0; p < NW; ++p) {
+        x += parts[p * kPartFloats + a1];
+        y += parts[p * kPartFloats + a2];
+    }
+    float v = same ? x - y : x + y;
+    if (same && ia == lb) v -= dg;
+    return (same && !itop) ? -v : v;
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void pgd_x3_kernel(PgdDev a) {
+    extern __shared__ float smem[];
+    const int stride = pl_stride(64 * NW);
+    float* sX = smem;                          // [16][stride]   H, then W
+    float* sD = smem + 16 * stride;            // [2][NW][16][17] D1 partials
+
+    const PgdLane<64> L;
+    const int64_t b = blockIdx.x;
+    const int K = a.K, M = a.M;
+    const float2* Hb = a.H + b * K * M;
+    const PgdScale cs = pgd_scale(a, b);
+
+    load_planar(sX, stride, 64 * NW, Hb, K, M, false, cs.hs);
+    __syncthreads();
+    u32x4 HAh[2], HAl[2];
+    {
+        float h[16];
+        read_op_a32(sX, stride, L, h);
+        split_x8(h, HAh[0], HAl[0]);
+        split_x8(h + 8, HAh[1], HAl[1]);
+    }
+    u32x2 HBh[4], HBl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h[j] = sX[(4 * L.hi + j) * stride + L.c0 + 16 * q + L.lo];
+        split_x4(h, HBh[q], HBl[q]);
     }
     __syncthreads();
-    if (tid == 0 && a.l21) {
-        double t = 0.0;
-        for (int w = 0; w < NW; ++w) t += red[64 + w];
-        a.l21[b] = cs.ws * t;
-    }
-    if (gains && L.wave == 0) {
-        // user k = lane < K: SINR_k and log2(1 + SINR_k), then a sum over the 8 lanes
-        double r = 0.0;
-        if (L.lane < K) {
-            double sig = 0.0, intf = 0.0;
-            for (int jj = 0; jj < K; ++jj) (jj == L.lane ? sig : intf) += red[L.lane * 8 + jj];
-            const double sn = sig / (intf + a.sigma2);
-            if (a.sinr) a.sinr[b * K + L.lane] = sn;
-            r = log2(1.0 + sn);
+    if (a.W0) load_planar(sX, stride, 64 * NW, a.W0 + b * K * M, K, M, false, 1.0f);
+    else load_planar(sX, stride, 64 * NW, Hb, K, M, true, cs.hs);         // W(0) = H^*
+    __syncthreads();
+    float WD[4][4], WA[16];
+    read_out_d<64>(sX, stride, L, WD);
+    read_op_a32(sX, stride, L, WA);
+    const float dg = a.d[L.lo & 7];
+
+    int ph = 0;
+    for (int layer = 0; layer < a.layers; ++layer) {
+        const float eta = (float)(a.etas[layer] * cs.es);
+        const float thr = (float)(a.lambdas[layer] * a.etas[layer] * cs.es);
+        put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial_x3(WA, HAh, HAl));
+        __syncthreads();
+        float e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] = embed_entry<NW>(sD + ph * NW * kPartFloats, L.lo, 4 * L.hi + j, dg);
+        ph ^= 1;
+        u32x2 Eh, El;
+        split_x4(e, Eh, El);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f32x4 g = {0.f, 0.f, 0.f, 0.f};
+            g = mfma16k16_bf16(Eh, HBh[q], g);
+            g = mfma16k16_bf16(El, HBh[q], g);
+            g = mfma16k16_bf16(Eh, HBl[q], g);
+            float v[4];
+            float n2 = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                v[r] = fmaf(-eta, g[r], WD[q][r]);
+                n2 = fmaf(v[r], v[r], n2);
+            }
+            const float sc = prox_scale(col_norm(column_sum(n2)), thr);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) WD[q][r] = sc * v[r];
         }
-        for (int off = 4; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
-        if (L.lane == 0 && a.rsum) a.rsum[b] = r;
+        write_out_d(sX, stride, L, WD);
+        wave_lds_sync();
+        read_op_a32(sX, stride, L, WA);
     }
+    const bool gains = a.rsum || a.sinr;
+    if (gains) put_partial(sD + (ph * NW + L.wave) * kPartFloats, L, d1_partial_x3(WA, HAh, HAl));
+    __syncthreads();
+    pgd_outputs<NW>(a, b, L.tid, L.lane, L.wave, sX, stride, sD, ph, cs);
 }
 
 }  // namespace
@@ -460,9 +627,20 @@ void launch_mfma(const PgdDev& d, dim3 grid, int nw, hipStream_t s) {
     }
 }
 
-dmimo_status run_pgd(const PgdDev& d, int64_t B, hipStream_t s) {
+dmimo_status run_pgd(const PgdDev& d, int64_t B, int prec, hipStream_t s) {
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pgd: B too large");
     const dim3 grid((unsigned)B);
+    if (prec == DMIMO_MIX_BF16X3) {            // K <= 8 (validated by the caller)
+        const int nw = (d.M + 63) / 64;
+        const size_t lds = pgd_mfma_lds_bytes(64, nw);
+        switch (nw) {
+            case 1: pgd_x3_kernel<1><<<grid, dim3(64), lds, s>>>(d); break;
+            case 2: pgd_x3_kernel<2><<<grid, dim3(128), lds, s>>>(d); break;
+            case 3: pgd_x3_kernel<3><<<grid, dim3(192), lds, s>>>(d); break;
+            default: pgd_x3_kernel<4><<<grid, dim3(256), lds, s>>>(d); break;
+        }
+        return check_launch("pgd_x3_kernel");
+    }
     if (d.K <= 8) {
         const int aw = pgd_antennas_per_wave(B, d.M);
         const int nw = (d.M + aw - 1) / aw;
@@ -479,15 +657,15 @@ dmimo_status run_pgd(const PgdDev& d, int64_t B, hipStream_t s) {
 
 dmimo_status launch_pgd(int64_t B, int K, int M, const void* H, const double* gamma, double sigma2,
                         int layers, const double* lambdas, const double* etas, const void* W0,
-                        void* W, double* l21, double* rsum, hipStream_t s) {
+                        void* W, double* l21, double* rsum, int prec, hipStream_t s) {
     const PgdDev d = make_pgd_dev(K, M, H, gamma, sigma2, layers, lambdas, etas, W0, W, l21, rsum);
-    return run_pgd(d, B, s);
+    return run_pgd(d, B, prec, s);
 }
 
 dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const double* gamma,
                                 double sigma2, int layers, const double* lambdas,
                                 const double* eta_rel, void* W, double* p_ant, double* l21,
-                                double* sinr, double* rsum, void* ws, hipStream_t s) {
+                                double* sinr, double* rsum, void* ws, int prec, hipStream_t s) {
     // the normalised problem has unit noise: d_k = sqrt(gamma_k), SINR with noise 1
     PgdDev d = make_pgd_dev(K, M, H, gamma, 1.0, layers, lambdas, eta_rel, nullptr, W, l21, rsum);
     d.pa = static_cast<const double*>(ws);
@@ -497,7 +675,7 @@ dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const do
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pa_precoder: B too large");
     dmimo_status st = launch_pa_prepare(B, K, M, H, static_cast<double*>(ws), s);
     if (st) return st;
-    return run_pgd(d, B, s);
+    return run_pgd(d, B, prec, s);
 }
 
 dmimo_status launch_pa_prepare(int64_t B, int K, int M, const void* H, double* pa, hipStream_t s) {

@@ -36,6 +36,7 @@
 #pragma once
 
 #include "powermap_common.h"
+#include "split16.h"
 
 namespace dmimo {
 
@@ -252,62 +253,6 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
 // ---------------------------------------------------------------------------
 // split-precision x3 (FP16 / BF16)
 // ---------------------------------------------------------------------------
-
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <bool BF16>
-__device__ __forceinline__ uint32_t pack_hi(float x0, float x1, float& r0, float& r1) {
-    // hi parts of x0, x1 packed in one register; r0, r1 = the FP32 remainders
-    if constexpr (BF16) {
-        const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-        const uint32_t b0 = __builtin_bit_cast(uint16_t, h0), b1 = __builtin_bit_cast(uint16_t, h1);
-        r0 = x0 - __uint_as_float(b0 << 16);
-        r1 = x1 - __uint_as_float(b1 << 16);
-        return b0 | (b1 << 16);
-    } else {
-        const auto h = __builtin_amdgcn_cvt_pkrtz(x0, x1);
-        r0 = x0 - (float)h[0];
-        r1 = x1 - (float)h[1];
-        return __builtin_bit_cast(uint32_t, h);
-    }
-}
-
-template <bool BF16>
-__device__ __forceinline__ uint32_t pack_lo(float r0, float r1) {
-    if constexpr (BF16) {
-        const __bf16 h0 = (__bf16)r0, h1 = (__bf16)r1;
-        return (uint32_t)__builtin_bit_cast(uint16_t, h0) |
-               ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-    } else {
-        return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r0, r1));
-    }
-}
-
-// round-to-nearest 16-bit value of x (table entries)
-template <bool BF16>
-__device__ __forceinline__ uint16_t to16(float x, float& back) {
-    if constexpr (BF16) {
-        const __bf16 h = (__bf16)x;
-        back = (float)h;
-        return __builtin_bit_cast(uint16_t, h);
-    } else {
-        const _Float16 h = (_Float16)x;
-        back = (float)h;
-        return __builtin_bit_cast(uint16_t, h);
-    }
-}
-
-template <bool BF16>
-__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
-    if constexpr (BF16)
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-    else
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
-                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
-}
 
 constexpr float kHScale = 16384.0f;   // 2^14: FP16 range placement of h (|h| <= 1)
 

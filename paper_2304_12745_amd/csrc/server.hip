@@ -272,7 +272,7 @@ bool ServerImpl::admit_one(Query* q) {
     if (q->precoder == DMIMO_PA) {
         void* pa_ws = base + users_b + h_b + w_b + g_b;
         ok = ok && launch_pa_precoder(1, K, d.M, H, pa_gamma, q->sigma2, pa_layers, pa_lam, pa_eta,
-                                      W, nullptr, nullptr, nullptr, nullptr, pa_ws,
+                                      W, nullptr, nullptr, nullptr, nullptr, pa_ws, DMIMO_F32,
                                       stream) == DMIMO_OK;
     } else {
         BeamformArgs ba;

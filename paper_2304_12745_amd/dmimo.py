@@ -338,7 +338,7 @@ class PaResult:
 
 
 def pa_precoder(H, lambdas, eta_rel, gamma_lin=None, sigma2=1.0, out=None, ws=None,
-                stream=None) -> PaResult:
+                stream=None, prec="f32") -> PaResult:
     """PA-aware precoder of deployments with channels of any scale
     (dmimo_pa_precoder).  H complex64 [B][K][M] on the GPU; lambdas, eta_rel
     per layer (steps relative to 1 / lambda_max of the normalised Gram)."""
@@ -359,7 +359,7 @@ def pa_precoder(H, lambdas, eta_rel, gamma_lin=None, sigma2=1.0, out=None, ws=No
         ws = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=dev)
     out._keep = (lam, er, ws)
     _check(lib().dmimo_pa_precoder(B, K, M, _ptr(H), _gamma(gamma_lin, K), float(sigma2),
-                                   lam.numel(), _ptr(lam), _ptr(er), F32, _ptr(out.W),
+                                   lam.numel(), _ptr(lam), _ptr(er), _prec(prec), _ptr(out.W),
                                    _ptr(out.p_ant), _ptr(out.l21), _ptr(out.sinr),
                                    _ptr(out.rsum), _ptr(ws), nbytes, _stream(stream)),
            "dmimo_pa_precoder")

@@ -157,6 +157,8 @@ def test_pgd_validation(lib):
     assert pgd(layers=-1) == 2
     assert pgd(prec=9) == 3
     assert pgd(prec=D.F64) == 6
+    assert pgd(prec=D.MIX_F16X3) == 6
+    assert pgd(prec=D.MIX_BF16X3, K=12, M=64) == 6          # BF16x3 is for K <= 8
     assert pgd(sigma2=-1.0) == 1
     assert pgd(sigma2=0.0, rsum=FAKE) == 1
     bad = (ctypes.c_double * 2)(1.0, float("nan"))
@@ -240,6 +242,7 @@ def test_pa_precoder_validation(lib):
     assert lib.dmimo_workspace_size(D.CALL_PA_PRECODER, 4, 33, 64, 0, D.F32) == 0
     assert pa(B=-1) == 2
     assert pa(prec=D.F64) == 6
+    assert pa(prec=D.MIX_BF16X3, K=12) == 6
     assert pa(prec=11) == 3
     assert pa(sigma2=0.0) == 1
     assert pa(sigma2=float("nan")) == 1

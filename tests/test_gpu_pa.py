@@ -197,3 +197,16 @@ def test_bench_launch_configuration_1024_rooms_sampled(D):
     say(f"    W rel err max {e.max():.2e}")
     assert e.max() < 1e-4
     np.testing.assert_allclose(r.l21.cpu().numpy()[s], O.l21_norm(W), rtol=1e-4)
+
+
+def test_bf16x3_room_deployments(D):
+    say("pa_precoder BF16x3: 12 room draws, K=8, M=64, 300 layers")
+    H = _rooms(12, 8, seed=21)
+    r = D.pa_precoder(torch.from_numpy(H.astype(np.complex64)).cuda(), [1 / 15] * 300, [1.0] * 300,
+                      np.full(8, 10.0), 1e-12, prec="bf16x3")
+    Hc = H.astype(np.complex64).astype(np.complex128)
+    W, _, _ = PA.pa_precoder(Hc, np.full(8, 10.0), 1e-12, [1 / 15] * 300, [1.0] * 300)
+    e = _rel(r.W.cpu().numpy(), W)
+    db = np.abs(10 * np.log10(r.sinr.cpu().numpy() / O.user_sinr(Hc, W, 1e-12))).max()
+    say(f"    W rel err max {e.max():.2e}, SINR max dB err {db:.2e}")
+    assert e.max() < 2e-3 and db < 0.01

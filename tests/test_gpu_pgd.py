@@ -150,3 +150,40 @@ def test_bench_launch_configuration_sampled(D):
     say(f"    5000 iterations: PCG max |diff| {np.abs(pcg_g - P.pcg(Wzf, Wo)).max():.2e}")
     assert np.abs(pcg_g - P.pcg(Wzf, Wo)).max() < 1e-5
     assert np.median(_rel(r5k.W.cpu().numpy()[s5k], Wo)) < 1e-3
+
+
+@pytest.mark.parametrize("K,M", [(8, 64), (5, 37), (8, 200)])
+def test_bf16x3_layers_match_oracle(D, K, M):
+    """BF16x3 layers (both products split hi + lo on the BF16 matrix cores):
+    W within 1e-3 of the FP64 oracle after 20 layers of a varying schedule."""
+    say(f"PGD BF16x3 K={K} M={M}, 20 layers")
+    rng = np.random.default_rng(K * 77 + M)
+    H = c64(WL.complex_normal(rng, (64, K, M)))
+    gamma = rng.uniform(2.0, 15.0, K)
+    Lt = P.mp_edge(K, M)
+    lams = P.project_lambda(rng.uniform(-0.02, 0.3, 20))
+    etas = P.project_eta(rng.uniform(0.3 / Lt, 1.2 / Lt, 20), K, M)
+    r = D.pgd(torch.from_numpy(H).cuda(), lams, etas, gamma, 1.0, prec="bf16x3")
+    Wo = P.unfolded(H.astype(np.complex128), gamma, 1.0, lams, etas)
+    e = _rel(r.W.cpu().numpy(), Wo)
+    say(f"    W rel err max {e.max():.2e} median {np.median(e):.2e}")
+    assert e.max() < 1e-3
+    np.testing.assert_allclose(r.l21.cpu().numpy(), O.l21_norm(Wo), rtol=1e-3)
+    np.testing.assert_allclose(r.rsum.cpu().numpy(), P.sum_rate(H.astype(np.complex128), Wo, 1.0),
+                               atol=5e-3)
+
+
+def test_bf16x3_pgd_5000_reaches_the_same_optimum(D):
+    say("PGD BF16x3, 5000 iterations, 100 channels: PCG vs the FP64 oracle")
+    K, M = 8, 64
+    w = WL.paper_workload(seed=123, B=100)
+    H = c64(w.H)
+    Hc = H.astype(np.complex128)
+    Wzf, _ = O.zf_precoder(Hc, w.gamma_lin, 1.0, 0.0)
+    eta = 1.0 / P.mp_edge(K, M)
+    r = D.pgd(torch.from_numpy(H).cuda(), [1 / 15] * 5000, [eta] * 5000, w.gamma_lin, 1.0,
+              prec="bf16x3")
+    Wo = P.pgd(Hc, w.gamma_lin, 1.0, 1 / 15, eta, 5000)
+    d = np.abs(O.l21_norm(Wzf) / r.l21.cpu().numpy() - P.pcg(Wzf, Wo))
+    say(f"    PCG max |diff| {d.max():.2e}; W rel err median {np.median(_rel(r.W.cpu().numpy(), Wo)):.2e}")
+    assert d.max() < 2e-3
