@@ -66,8 +66,13 @@ def _src_hash(files):
     return h.hexdigest()[:16]
 
 
+# every file the map kernels are compiled from (the traffic summary is only
+# valid for these exact sources)
 POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
                     "paper_2304_12745_amd/csrc/powermap_mfma.hip",
+                    "paper_2304_12745_amd/csrc/powermap_body.h",
+                    "paper_2304_12745_amd/csrc/powermap_common.h",
+                    "paper_2304_12745_amd/csrc/split16.h",
                     "paper_2304_12745_amd/csrc/dmimo_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
 
