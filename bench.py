@@ -70,9 +70,11 @@ def _src_hash(files):
 # valid for these exact sources)
 POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
                     "paper_2304_12745_amd/csrc/powermap_mfma.hip",
+                    "paper_2304_12745_amd/csrc/powermap_mfma.h",
                     "paper_2304_12745_amd/csrc/powermap_body.h",
                     "paper_2304_12745_amd/csrc/powermap_common.h",
                     "paper_2304_12745_amd/csrc/split16.h",
+                    "paper_2304_12745_amd/csrc/kernels.h",
                     "paper_2304_12745_amd/csrc/dmimo_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
 
