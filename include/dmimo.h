@@ -22,7 +22,7 @@
  *    (DMIMO_E_HIP, detail in dmimo_last_error()).  Argument errors are
  *    detected before any HIP runtime call is made.
  *  - Numeric failures found on the device go to a per-deployment `info[b]`
- *    (0 = ok, j > 0 = Cholesky pivot j not positive).  A failed deployment
+ *    (0 = ok, j > 0 = ZF pivot j not positive).  A failed deployment
  *    does not affect the others.
  *  - B = 0 or N = 0 (an empty batch) is valid and launches nothing.
  *  - K and M must be >= 1.  K is at most DMIMO_K_MAX.
@@ -132,15 +132,22 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *             every user then has the same SINR.
  *             <= 0: MR uses W = H^*; ZF uses the constraint of eq. (optim1),
  *             H W^T = sqrt(sigma2) D_gamma^{1/2}; equal-gain MR uses |w| = 1.
- *   prec      precision of the Gram (ZF); the Cholesky factorisation, G^-1 and
- *             G^-1 H are FP64 in every mode.
+ *   prec      precision of the Gram (ZF) for K > 8 or M > 256 (M > 128 for
+ *             DMIMO_F64); G^-1 (Cholesky) and G^-1 H are FP64 in every mode.
+ *             Smaller deployments run in one kernel that forms G in FP64 from
+ *             the stored H and inverts it by FP64 Gauss-Jordan elimination, in
+ *             every mode (the MIX modes then equal DMIMO_F32 bit for bit).
  * Outputs (device; any may be NULL except W):
  *   W      [B][K][M] precoder, same complex type as H.
  *   p_ant  FP64 [B][M]  per-antenna power p_m = sum_k |w_km|^2.
  *   l21    FP64 [B]     ||W||_{2,1} = sum_m sqrt(p_m); consumed PA power is alpha * l21.
  *   sinr   FP64 [B][K]  SINR_k = |A_kk|^2 / (sum_{j!=k} |A_kj|^2 + sigma2), A = H W^T.
  *   rsum   FP64 [B]     sum rate, sum_k log2(1 + SINR_k).
- *   info   int32 [B]    0 ok; j > 0 Cholesky pivot j not positive (ZF); W,
+ *   info   int32 [B]    0 ok; j > 0 (ZF): pivot j, the diagonal entry of the
+ *                       Schur complement after j - 1 elimination steps (L_jj^2
+ *                       of the Cholesky factor), is not above tol * G_jj, tol =
+ *                       1e-12 for FP64 input, else 1e-6 (1e-4 with the BF16x3
+ *                       Gram); W,
  *                       p_ant, l21, sinr and rsum are zero for that deployment.
  *   ws, ws_bytes  device workspace of at least
  *                 dmimo_workspace_size(DMIMO_CALL_BEAMFORM_ZF, B, K, M, 0, prec) bytes

@@ -253,14 +253,21 @@ def test_beamform_batched_rician_zf(D, prec):
 
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 def test_beamform_paper_zf_mixed(D, prec):
-    say(f"beamform ZF, paper setting, Gram {prec}")
+    # K <= 8 and M <= 256: G is formed in FP64 inside the one-pass kernel in
+    # every mode, so the mixed modes give the FP32 result bit for bit
+    say(f"beamform ZF, paper setting, prec {prec}")
     w = WL.paper_workload(seed=0, B=256)
     r = _check_beamform(D, c64(w.H), "zf", w.gamma_lin, 1.0, 0.0, prec, MAP_TOL[prec],
                         1e-4 if prec != "bf16x3" else 1e-2)
     assert np.all(np.abs(host(r.rsum) - 27.68) < 0.005)
+    r32 = D.beamform(dev(c64(w.H)), "zf", w.gamma_lin, 1.0, 0.0, "f32")
+    np.testing.assert_array_equal(host(r.W), host(r32.W))
 
 
-@pytest.mark.parametrize("K,M", [(1, 1), (3, 3), (5, 37), (32, 64), (17, 300)])
+# one-pass kernel: K <= 8 with M <= 256 (M <= 128 in FP64), ragged tiles and
+# the limits; (8, 129) and (8, 257) fall just outside it (FP64 / every mode)
+@pytest.mark.parametrize("K,M", [(1, 1), (3, 3), (5, 37), (8, 128), (8, 129), (7, 193), (8, 256),
+                                 (8, 257), (32, 64), (17, 300)])
 def test_beamform_shapes(D, K, M):
     say(f"beamform ZF/MR shapes K={K} M={M}")
     rng = np.random.default_rng(K + 7 * M)
