@@ -7,7 +7,7 @@ One step is one pass of the whole path, with inputs already resident in HBM:
 
   1. dmimo_channel   user channels H (K x M, complex64)
   2. dmimo_beamform  MR at 1 W                      (+ p_m, L2,1, SINR_k, R_sum)
-  3. dmimo_beamform  ZF at 1 W: Gram, FP64 Cholesky (+ the same epilogues)
+  3. dmimo_beamform  ZF at 1 W: FP64 Gram and inverse (+ the same epilogues)
   4. dmimo_powermap  MR power + SINR + best-stream maps, 512 x 512 grid at z = 1.2 m
   5. dmimo_powermap  ZF power + SINR + best-stream maps, same grid
 
@@ -100,6 +100,9 @@ def parse_args():
     p.add_argument("--steps", type=int, default=500)
     p.add_argument("--warmup", type=int, default=2000,
                    help="untimed steps first (enough to bring the GPU clocks up)")
+    p.add_argument("--event-every", type=int, default=10,
+                   help="record the map event pair on every n-th timed step (each pair "
+                        "puts two markers in the queue, about 7 us per step)")
     p.add_argument("--nx", type=int, default=512)
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="budget of the oracle CPU baseline (0 disables it)")
@@ -205,6 +208,7 @@ def main():
             "frac": round(achieved / peak, 4),
             "traffic": traffic,
             "launch_ms": round(map_launch_ms, 5),
+            "event_samples": 2 * len(range(0, args.steps, max(1, args.event_every))),
             "alg_slots_per_term": alg_slots_per_term(K),
             "mfma_f32": {"achieved": round(mfma_tflops, 3), "peak": MFMA_F32_PEAK / 1e12,
                          "unit": "TFLOP/s", "frac": round(mfma_tflops * 1e12 / MFMA_F32_PEAK, 4),
@@ -233,9 +237,10 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     """Warm up, then time exactly args.steps steps of the room workload.
 
     One step, in order on torch's current stream: the user channel, MR and
-    ZF precoders (Gram + FP64 Cholesky inside), the MR map, the ZF map.  One
-    pair of HIP events on that stream brackets the two map launches of a step
-    (a pair around each launch would add its own dispatch gap to each).  (A variant with the MR
+    ZF precoders (Gram and inverse inside), the MR map, the ZF map.  One
+    pair of HIP events on that stream brackets the two map launches of every
+    args.event_every-th timed step (a pair around each launch would add its
+    own dispatch gap to each; a pair on every step adds about 7 us per step).  (A variant with the MR
     branch on a second stream was measured slower: 0.114 vs 0.094 ms/step,
     because the cross-queue event waits cost more than the overlap saves.)
     Returns (ms per step, mean map launch ms, maps, precoders).
@@ -261,15 +266,17 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
 
     for _ in range(args.warmup):
         step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    every = max(1, args.event_every)
+    events = {i: [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+              for i in range(0, args.steps, every)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(events[i])
+        step(events.get(i))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    # one event pair brackets the two back-to-back map launches of a step
-    launch = sum(e[0].elapsed_time(e[1]) for e in events) / (2 * args.steps)
+    # one event pair brackets the two back-to-back map launches of a sampled step
+    launch = sum(e[0].elapsed_time(e[1]) for e in events.values()) / (2 * len(events))
     return ms, launch, maps, bf
 
 
