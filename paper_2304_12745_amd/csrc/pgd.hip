@@ -74,98 +74,147 @@ __device__ __forceinline__ PgdScale pgd_scale(const PgdDev& a, int64_t b) {
     return c;
 }
 
-// Normalisation of the PA-aware precoder, one wave per channel: s^2 = mean
-// |h|^2, G = H H^H in FP64, and the largest eigenvalue of G.  The eigenvalue
-// comes from repeated squaring, S <- S^2 / tr(S^2) from S = G / tr G, twelve
-// times (S ~ G^4096 / tr, a projector onto the top eigenspace unless the top
-// two eigenvalues agree to ~1e-3 relative, when any vector of their span
-// gives a Rayleigh quotient within that of lambda_max), then the Rayleigh
-// quotient of G at the largest-norm column of S.  Writes {1/s, s^2 /
-// lambda_max(G)} = {1/s, 1/lambda_max(Hn Hn^H)}; an all-zero channel gets
-// {0, 0}, which makes its output W = 0.
+// Normalisation of the PA-aware precoder, one workgroup of NT threads per
+// channel: s^2 = mean |h|^2, G = H H^H in FP64, and the largest eigenvalue of
+// G.  H passes through LDS in chunks of 64 antennas; each Gram entry sums its
+// antennas in order.  The eigenvalue comes from repeated squaring,
+// S <- S^2 / tr(S^2) from S = G / tr G, twelve times (S ~ G^4096 / tr, a
+// projector onto the top eigenspace unless the top two eigenvalues agree to
+// ~1e-3 relative, when any vector of their span gives a Rayleigh quotient
+// within that of lambda_max), then the Rayleigh quotient of G at the
+// largest-norm column of S.  Writes {1/s, s^2 / lambda_max(G)} =
+// {1/s, 1/lambda_max(Hn Hn^H)}; an all-zero channel gets {0, 0}, which makes
+// its output W = 0.
+constexpr int kPrepChunk = 64;
+
 template <int KM>
-__global__ __launch_bounds__(64) void pa_prepare_kernel(const float2* H, int K, int M, double* pa) {
-    __shared__ double Gr[KM][KM + 1], Gi[KM][KM + 1];     // G
-    __shared__ double Sr[KM][KM + 1], Si[KM][KM + 1];     // S
-    __shared__ double Tr[KM][KM + 1], Ti[KM][KM + 1];     // S^2
-    __shared__ double colnorm[KM];
+struct PrepShared {
+    double Gr[KM][KM + 1], Gi[KM][KM + 1];            // G
+    double Sr[KM][KM + 1], Si[KM][KM + 1];            // S
+    union {
+        struct {
+            double r[KM][KM + 1], i[KM][KM + 1];      // S^2
+        } t;
+        float2 h[KM][kPrepChunk + 1];                 // chunk of H
+    } u;
+    double colnorm[KM];
+    double red[16];
+};
+
+template <int NT>
+__device__ __forceinline__ double prep_block_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (NT == 64) return v;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    return t;
+}
+
+template <int KM, int NT>
+__global__ __launch_bounds__(NT) void pa_prepare_kernel(const float2* H, int K, int M, double* pa) {
+    constexpr int QE = (KM * KM + NT - 1) / NT;   // Gram entries per thread
+    __shared__ PrepShared<KM> S;
     const int64_t b = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const float2* Hb = H + b * K * M;
     double p = 0.0;
-    for (int e = lane; e < K * M; e += 64) {
-        const float2 h = Hb[e];
-        p += (double)h.x * h.x + (double)h.y * h.y;
-    }
-    for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
-    for (int e = lane; e < K * K; e += 64) {
-        const int k = e / K, j = e - k * K;
-        double gr = 0.0, gi = 0.0;
-        for (int m = 0; m < M; ++m) {
-            const float2 hk = Hb[k * M + m], hj = Hb[j * M + m];
-            gr += (double)hk.x * hj.x + (double)hk.y * hj.y;
-            gi += (double)hk.y * hj.x - (double)hk.x * hj.y;
+    double2 acc[QE];
+#pragma unroll
+    for (int q = 0; q < QE; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int m0 = 0; m0 < M; m0 += kPrepChunk) {
+        const int mc = M - m0 < kPrepChunk ? M - m0 : kPrepChunk;
+        __syncthreads();
+        for (int e = tid; e < K * kPrepChunk; e += NT) {
+            const int k = e / kPrepChunk, c = e - k * kPrepChunk;
+            if (c < mc) {
+                const float2 h = Hb[(int64_t)k * M + m0 + c];
+                S.u.h[k][c] = h;
+                p += (double)h.x * h.x + (double)h.y * h.y;
+            }
         }
-        Gr[k][j] = gr;
-        Gi[k][j] = gi;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QE; ++q) {
+            const int e = tid + NT * q;
+            if (e < K * K) {
+                const int k = e / K, j = e - k * K;
+                double gr = acc[q].x, gi = acc[q].y;
+                for (int c = 0; c < mc; ++c) {
+                    const float2 hk = S.u.h[k][c], hj = S.u.h[j][c];
+                    gr += (double)hk.x * hj.x + (double)hk.y * hj.y;
+                    gi += (double)hk.y * hj.x - (double)hk.x * hj.y;
+                }
+                acc[q] = make_double2(gr, gi);
+            }
+        }
     }
-    __syncthreads();
+    p = prep_block_sum<NT>(p, S.red);
     // S = G / tr G  (tr G = sum |h|^2 = p)
     const double inv_tr = p > 0.0 ? 1.0 / p : 0.0;
-    for (int e = lane; e < K * K; e += 64) {
-        const int k = e / K, j = e - k * K;
-        Sr[k][j] = Gr[k][j] * inv_tr;
-        Si[k][j] = Gi[k][j] * inv_tr;
+#pragma unroll
+    for (int q = 0; q < QE; ++q) {
+        const int e = tid + NT * q;
+        if (e < K * K) {
+            const int k = e / K, j = e - k * K;
+            S.Gr[k][j] = acc[q].x;
+            S.Gi[k][j] = acc[q].y;
+            S.Sr[k][j] = acc[q].x * inv_tr;
+            S.Si[k][j] = acc[q].y * inv_tr;
+        }
     }
     __syncthreads();
     for (int it = 0; it < 12; ++it) {
-        double dpart = 0.0;                        // this lane's share of tr(S^2)
-        for (int e = lane; e < K * K; e += 64) {
+        double dpart = 0.0;                        // this thread's share of tr(S^2)
+        for (int e = tid; e < K * K; e += NT) {
             const int k = e / K, j = e - k * K;
             double tr = 0.0, ti = 0.0;
             for (int l = 0; l < K; ++l) {
-                tr += Sr[k][l] * Sr[l][j] - Si[k][l] * Si[l][j];
-                ti += Sr[k][l] * Si[l][j] + Si[k][l] * Sr[l][j];
+                tr += S.Sr[k][l] * S.Sr[l][j] - S.Si[k][l] * S.Si[l][j];
+                ti += S.Sr[k][l] * S.Si[l][j] + S.Si[k][l] * S.Sr[l][j];
             }
-            Tr[k][j] = tr;
-            Ti[k][j] = ti;
+            S.u.t.r[k][j] = tr;
+            S.u.t.i[k][j] = ti;
             if (k == j) dpart += tr;
         }
-        for (int off = 32; off > 0; off >>= 1) dpart += __shfl_xor(dpart, off, 64);
+        dpart = prep_block_sum<NT>(dpart, S.red);
         const double inv = dpart > 0.0 ? 1.0 / dpart : 0.0;
         __syncthreads();
-        for (int e = lane; e < K * K; e += 64) {
+        for (int e = tid; e < K * K; e += NT) {
             const int k = e / K, j = e - k * K;
-            Sr[k][j] = Tr[k][j] * inv;
-            Si[k][j] = Ti[k][j] * inv;
+            S.Sr[k][j] = S.u.t.r[k][j] * inv;
+            S.Si[k][j] = S.u.t.i[k][j] * inv;
         }
         __syncthreads();
     }
-    if (lane < K) {
+    if (tid < K) {
         double c = 0.0;
-        for (int k = 0; k < K; ++k) c += Sr[k][lane] * Sr[k][lane] + Si[k][lane] * Si[k][lane];
-        colnorm[lane] = c;
+        for (int k = 0; k < K; ++k) c += S.Sr[k][tid] * S.Sr[k][tid] + S.Si[k][tid] * S.Si[k][tid];
+        S.colnorm[tid] = c;
     }
     __syncthreads();
+    if (tid >= 64) return;   // K <= 64: the rest runs in wave 0
     int jb = 0;
     for (int j = 1; j < K; ++j)
-        if (colnorm[j] > colnorm[jb]) jb = j;
+        if (S.colnorm[j] > S.colnorm[jb]) jb = j;
     // Rayleigh quotient of G at v = S[:, jb]: lane k holds v_k and (G v)_k
     double num = 0.0, den = 0.0;
-    if (lane < K) {
+    if (tid < K) {
         double yr = 0.0, yi = 0.0;
         for (int j = 0; j < K; ++j) {
-            yr += Gr[lane][j] * Sr[j][jb] - Gi[lane][j] * Si[j][jb];
-            yi += Gr[lane][j] * Si[j][jb] + Gi[lane][j] * Sr[j][jb];
+            yr += S.Gr[tid][j] * S.Sr[j][jb] - S.Gi[tid][j] * S.Si[j][jb];
+            yi += S.Gr[tid][j] * S.Si[j][jb] + S.Gi[tid][j] * S.Sr[j][jb];
         }
-        num = Sr[lane][jb] * yr + Si[lane][jb] * yi;
-        den = Sr[lane][jb] * Sr[lane][jb] + Si[lane][jb] * Si[lane][jb];
+        num = S.Sr[tid][jb] * yr + S.Si[tid][jb] * yi;
+        den = S.Sr[tid][jb] * S.Sr[tid][jb] + S.Si[tid][jb] * S.Si[tid][jb];
     }
     for (int off = 32; off > 0; off >>= 1) {
         num += __shfl_xor(num, off, 64);
         den += __shfl_xor(den, off, 64);
     }
-    if (lane == 0) {
+    if (tid == 0) {
         const double lam = den > 0.0 ? num / den : 0.0;
         const double s2 = p / ((double)K * M);
         const bool ok = s2 > 0.0 && lam > 0.0;
@@ -681,8 +730,8 @@ dmimo_status launch_pa_precoder(int64_t B, int K, int M, const void* H, const do
 dmimo_status launch_pa_prepare(int64_t B, int K, int M, const void* H, double* pa, hipStream_t s) {
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "pa_precoder: B too large");
     const float2* h = reinterpret_cast<const float2*>(H);
-    if (K <= 16) pa_prepare_kernel<16><<<dim3((unsigned)B), dim3(64), 0, s>>>(h, K, M, pa);
-    else pa_prepare_kernel<32><<<dim3((unsigned)B), dim3(64), 0, s>>>(h, K, M, pa);
+    if (K <= 16) pa_prepare_kernel<16, 64><<<dim3((unsigned)B), dim3(64), 0, s>>>(h, K, M, pa);
+    else pa_prepare_kernel<32, 256><<<dim3((unsigned)B), dim3(256), 0, s>>>(h, K, M, pa);
     return check_launch("pa_prepare_kernel");
 }
 
