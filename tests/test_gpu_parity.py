@@ -99,6 +99,35 @@ def test_channel_los_grid(D, prec, M):
     assert e <= tol
 
 
+# more rows than one grid-stride step covers (65536 rows for M >= 33, 524288
+# for M = 5), the step crossing deployments: sampled rows against the oracle
+@pytest.mark.parametrize("M,B,nx,ny,kind,prec", [(64, 3, 250, 160, "grid", "f32"),
+                                                 (64, 3, 250, 160, "grid", "f64"),
+                                                 (5, 2, 600, 500, "grid", "f32"),
+                                                 (64, 3, 40000, 1, "list", "f32"),
+                                                 (37, 2, 50000, 1, "list", "f32")])
+def test_channel_grid_stride_wrap(D, M, B, nx, ny, kind, prec):
+    say(f"channel {kind} B={B} N={nx * ny} M={M} prec={prec}")
+    rng = np.random.default_rng(M + 10 * B + nx)
+    aps = np.stack([WL.uniform_positions(rng, M, 20, 20, 4.0) for _ in range(B)])
+    f = 3.5e9
+    if kind == "grid":
+        g = WL.Grid(0.0, 0.0, 20 / nx, 20 / ny, 1.2, nx, ny)
+        pts = np.broadcast_to(grid_pts(g), (B, nx * ny, 3))
+        desc = D.grid_points(g)
+    else:
+        pts = np.stack([WL.uniform_positions(rng, nx, 20, 20, 1.2) for _ in range(B)])
+        desc = D.list_points(dev(pts), nx)
+    H = host(D.channel(D.channel_params(f), dev(aps), desc, prec=prec))
+    assert H.shape == (B, nx * ny, M)
+    tol = 2e-6 if prec == "f32" else 1e-11
+    for b in range(B):
+        rows = np.concatenate([[0, nx * ny - 1], rng.choice(nx * ny, 200, replace=False)])
+        ref = O.los_channel(pts[b][rows], aps[b], f)
+        e = np.max(np.abs(H[b][rows] - ref) / np.abs(ref))
+        assert e <= tol, (b, e)
+
+
 def test_channel_los_list_batched(D):
     say("channel LoS list, B=3")
     rng = np.random.default_rng(7)
