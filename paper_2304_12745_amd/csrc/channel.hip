@@ -30,7 +30,12 @@ struct ChannelArgs {
     int64_t stride;      // rows per grid-stride step
     int64_t sb, sn;      // stride = sb N + sn
     int32_t si, sj;      // sn = sj nx + si (grid points)
+    int lds_ap;          // rows wider than 64 antennas, B = 1: coordinates in LDS
 };
+
+// Antenna coordinates of a single deployment for the wide-row path, as
+// planes x[M], y[M], z[M].
+constexpr int kLdsApMax = 2048;
 
 // One term; the NLoS draw is read and the term stored only where `valid`.
 template <bool F64, bool RICIAN>
@@ -71,6 +76,15 @@ __global__ __launch_bounds__(256) void channel_kernel(ChannelArgs a) {
     const int l = lane & (lpr - 1);
     const int64_t rows = a.B * a.N;
     const bool grid = a.P.kind == DMIMO_PTS_GRID;
+    extern __shared__ double s_ap[];
+    if (APL == 0 && a.lds_ap) {
+        for (int i = threadIdx.x; i < a.M; i += blockDim.x) {
+            s_ap[i] = a.ap[3 * i + 0];
+            s_ap[a.M + i] = a.ap[3 * i + 1];
+            s_ap[2 * a.M + i] = a.ap[3 * i + 2];
+        }
+        __syncthreads();
+    }
 
     int64_t r = wave * rows_per_wave + sub;
     if (r >= rows) return;
@@ -126,6 +140,11 @@ __global__ __launch_bounds__(256) void channel_kernel(ChannelArgs a) {
                 const int64_t m = l + q * lpr;
                 emit_term<F64, RICIAN>(a, r * a.M + m, m < a.M, px - ax[q], py - ay[q], pz - az[q]);
             }
+        } else if (a.lds_ap) {
+#pragma unroll 4
+            for (int64_t m = l; m < a.M; m += lpr)
+                emit_term<F64, RICIAN>(a, r * a.M + m, true, px - s_ap[m], py - s_ap[a.M + m],
+                                       pz - s_ap[2 * a.M + m]);
         } else {
 #pragma unroll 4
             for (int64_t m = l; m < a.M; m += lpr)
@@ -178,7 +197,10 @@ dmimo_status launch_channel(const WaveConst& w, const PointsDev& P, bool rician,
     a.lpr_log2 = lpr_log2;
     const int64_t rows = B * P.n;
     const int64_t rows_per_block = 4 * (64 >> lpr_log2);
-    const int64_t blocks = std::min<int64_t>(ceil_div(rows, rows_per_block), 256 * 16);
+    // workgroups per CU at most: 12 for the packed rows, 64 for wide rows
+    const int64_t blocks = std::min<int64_t>(ceil_div(rows, rows_per_block), 256 * (apl ? 12 : 64));
+    a.lds_ap = apl == 0 && B == 1 && M <= kLdsApMax;
+    const size_t lds = a.lds_ap ? (size_t)(3 * M) * sizeof(double) : 0;
     a.stride = blocks * 4 * (64 >> lpr_log2);
     a.sb = a.stride / a.N;
     a.sn = a.stride - a.sb * a.N;
@@ -190,7 +212,7 @@ dmimo_status launch_channel(const WaveConst& w, const PointsDev& P, bool rician,
     dim3 grid((unsigned)blocks), block(256);
     auto go = [&](auto f64c, auto ricc) {
         constexpr bool F = decltype(f64c)::value, R = decltype(ricc)::value;
-        if (apl == 0) channel_kernel<F, R, 0><<<grid, block, 0, s>>>(a);
+        if (apl == 0) channel_kernel<F, R, 0><<<grid, block, lds, s>>>(a);
         else if (apl == 2) channel_kernel<F, R, 2><<<grid, block, 0, s>>>(a);
         else channel_kernel<F, R, 4><<<grid, block, 0, s>>>(a);
     };

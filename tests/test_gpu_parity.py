@@ -128,6 +128,30 @@ def test_channel_grid_stride_wrap(D, M, B, nx, ny, kind, prec):
         assert e <= tol, (b, e)
 
 
+# rows wider than 64 antennas: one deployment holds its antenna coordinates
+# in LDS (M <= 2048), several deployments or more antennas read them from HBM
+@pytest.mark.parametrize("M,B,kind", [(100, 1, "grid"), (2048, 1, "grid"), (2049, 1, "grid"),
+                                      (300, 2, "grid"), (1024, 1, "list")])
+def test_channel_wide_rows(D, M, B, kind):
+    say(f"channel wide rows {kind} B={B} M={M}")
+    rng = np.random.default_rng(M + B)
+    aps = np.stack([WL.uniform_positions(rng, M, 50, 50, 5.0) for _ in range(B)])
+    f = 5.8e9
+    if kind == "grid":
+        g = WL.Grid(0.0, 0.0, 50 / 41, 50 / 37, 1.0, 41, 37)
+        pts = np.broadcast_to(grid_pts(g), (B, g.nx * g.ny, 3))
+        desc = D.grid_points(g)
+    else:
+        pts = np.stack([WL.uniform_positions(rng, 1500, 50, 50, 1.0) for _ in range(B)])
+        desc = D.list_points(dev(pts), 1500)
+    for prec, tol in (("f32", 2e-6), ("f64", 1e-11)):
+        H = host(D.channel(D.channel_params(f), dev(aps), desc, prec=prec))
+        for b in range(B):
+            ref = O.los_channel(pts[b], aps[b], f)
+            e = np.max(np.abs(H[b] - ref) / np.abs(ref))
+            assert e <= tol, (prec, b, e)
+
+
 def test_channel_los_list_batched(D):
     say("channel LoS list, B=3")
     rng = np.random.default_rng(7)
