@@ -115,6 +115,8 @@ def parse_args():
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
     p.add_argument("--no-pgd", action="store_true", help="skip the PGD / unfolded-PGD phase")
     p.add_argument("--no-pa", action="store_true", help="skip the PA-aware precoder phase")
+    p.add_argument("--no-channel", action="store_true",
+                   help="skip the materialised-channel bandwidth phase")
     return p.parse_args()
 
 
@@ -221,6 +223,8 @@ def main():
     if mixed is not None:
         mixed["value"] = round(terms_per_step / (mixed["ms_per_step"] * 1e-3) / 1e9, 3)
         out["mixed"] = mixed
+    if not args.no_channel:
+        out["channel"] = channel_phase(D, WL, torch, params, ap, gpts, N)
     if args.serve_seconds > 0:
         out["serving"] = serving_phase(args, D, WL, torch)
     if not args.no_pgd:
@@ -278,6 +282,43 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     # one event pair brackets the two back-to-back map launches of a sampled step
     launch = sum(e[0].elapsed_time(e[1]) for e in events.values()) / (2 * len(events))
     return ms, launch, maps, bf
+
+
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
+
+
+def channel_phase(D, WL, torch, params, ap, gpts, N):
+    """dmimo_channel materialising H in HBM, an HBM-write-bound kernel: the
+    room grid (512 x 512 points x 64 APs) in complex64 and complex128, and the
+    hall grid (2048 x 2048 points x 1024 APs, 34.4 GB) in complex64.  Kernel
+    time from HIP events around back-to-back launches; bytes = the output."""
+    def run(prm, apd, pts, n, m, prec, reps):
+        H = D.channel(prm, apd, pts, prec=prec)
+        for _ in range(2):
+            D.channel(prm, apd, pts, prec=prec, out=H)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            D.channel(prm, apd, pts, prec=prec, out=H)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del H
+        torch.cuda.empty_cache()
+        nbytes = n * m * (16 if prec == "f64" else 8)
+        return {"ms": round(ms, 4), "G_h_per_s": round(n * m / ms / 1e6, 1),
+                "GB_per_s": round(nbytes / ms / 1e6, 1), "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 3)}
+    M = ap.shape[1]
+    out = {"room_f32": run(params, ap, gpts, N, M, "f32", 50),
+           "room_f64": run(params, ap, gpts, N, M, "f64", 50)}
+    hw = WL.hall_workload()
+    hap = torch.from_numpy(hw.ap_xyz).to(ap.device)
+    out["hall_f32"] = run(D.channel_params(hw.freq_hz), hap, D.grid_points(hw.grid), hw.grid.n,
+                          hw.M, "f32", 5)
+    out["workload"] = ("room: 512 x 512 grid x 64 APs (16.8 M terms); hall: 2048 x 2048 grid x "
+                       "1024 APs (4.29 G terms); LoS, output H [N][M] in HBM")
+    return out
 
 
 def serving_phase(args, D, WL, torch):
