@@ -215,6 +215,13 @@ def main():
             "mfma_f32": {"achieved": round(mfma_tflops, 3), "peak": MFMA_F32_PEAK / 1e12,
                          "unit": "TFLOP/s", "frac": round(mfma_tflops * 1e12 / MFMA_F32_PEAK, 4),
                          "flops_per_term": 8 * K},
+            # the matrix unit and the VALU do not co-issue on this kernel
+            # (SQ_VALU_MFMA_COEXEC_CYCLES = 0), so its floor is the sum of the
+            # synthesis at the VALU peak and the contraction at the MFMA peak
+            "serial_valu_mfma": {
+                "floor_ms": round((alg / VALU_PEAK_SLOTS + 8 * K * N * M / MFMA_F32_PEAK) * 1e3, 5),
+                "frac": round((alg / VALU_PEAK_SLOTS + 8 * K * N * M / MFMA_F32_PEAK) * 1e3
+                              / map_launch_ms, 4)},
             "terms_per_launch": N * M,
             "source_hash": khash,
         },
