@@ -219,11 +219,16 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
     // column pass: thread -> (column c = tid / 4, row group g = tid % 4, rows g, g+4, ...)
     const int cc = tid >> 2;
     const int rg = tid & 3;
-    // gains: entries e = tid / 4 + 64 q, antennas c = tid % 4 (mod 4)
-    constexpr int QE = (KT * KT + 63) / 64;
-    double2 acc[QE];
+    // gains: the K x K matrix in 8 x 8 blocks of BS x BS entries; block tid / 4,
+    // antennas c = tid % 4 (mod 4).  A block reuses each h and w value it reads
+    // BS times.
+    constexpr int BS = KT / 8;
+    const int k0 = BS * (cc >> 3), j0 = BS * (cc & 7);
+    double2 acc[BS][BS];
 #pragma unroll
-    for (int q = 0; q < QE; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) acc[u][v] = make_double2(0.0, 0.0);
     double l21 = 0.0;
     const bool want_gain = a.sinr || a.rsum;
 
@@ -238,16 +243,26 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
         if (cc < mc) {
             const int64_t m = m0 + cc;
             double pm = 0.0;
-            for (int k = rg; k < K; k += 4) {
+            // ZF: x_k = sum_j G^-1[k][j] h_j for this thread's users k = rg + 4 t,
+            // each h_j read once
+            constexpr int KU = KT / 4;
+            double2 x[KU];
+            if (a.precoder == DMIMO_ZF) {
+#pragma unroll
+                for (int t = 0; t < KU; ++t) x[t] = make_double2(0.0, 0.0);
+                for (int j = 0; j < K; ++j) {
+                    const double2 hj = to_d2(S.u.t.h[j][cc]);
+#pragma unroll
+                    for (int t = 0; t < KU; ++t) cfma(x[t], S.ginv[rg + 4 * t][j], hj);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < KU; ++t) {
+                const int k = rg + 4 * t;
+                if (k >= K) break;
                 double2 w;
                 if (a.precoder == DMIMO_ZF) {
-                    double2 x = make_double2(0.0, 0.0);
-#pragma unroll 8
-                    for (int j = 0; j < KT; ++j) {
-                        if (j >= K) break;
-                        cfma(x, S.ginv[k][j], to_d2(S.u.t.h[j][cc]));
-                    }
-                    w = make_double2(S.scale[k] * x.x, -S.scale[k] * x.y);
+                    w = make_double2(S.scale[k] * x[t].x, -S.scale[k] * x[t].y);
                 } else {
                     const double2 h = to_d2(S.u.t.h[k][cc]);
                     if (a.precoder == DMIMO_MR) {
@@ -275,15 +290,19 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
         }
         if (!want_gain) continue;
         __syncthreads();
+        if (k0 < K && j0 < K)
+            for (int c = rg; c < mc; c += 4) {
+                double2 hk[BS], wj[BS];
 #pragma unroll
-        for (int q = 0; q < QE; ++q) {
-            const int e = cc + 64 * q;
-            if (e >= K * K) break;
-            const int k = e / K, j = e - (e / K) * K;
-            double2 s = acc[q];
-            for (int c = rg; c < mc; c += 4) cfma(s, to_d2(S.u.t.h[k][c]), to_d2(S.u.t.w[j][c]));
-            acc[q] = s;
-        }
+                for (int u = 0; u < BS; ++u) {
+                    hk[u] = k0 + u < K ? to_d2(S.u.t.h[k0 + u][c]) : make_double2(0.0, 0.0);
+                    wj[u] = j0 + u < K ? to_d2(S.u.t.w[j0 + u][c]) : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < BS; ++u)
+#pragma unroll
+                    for (int v = 0; v < BS; ++v) cfma(acc[u][v], hk[u], wj[v]);
+            }
     }
     l21 = block_sum(l21, S.red);
     if (tid == 0) {
@@ -293,15 +312,16 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
     if (!want_gain) return;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < QE; ++q) {
-        const int e = cc + 64 * q;
-        double2 v = acc[q];
-        v.x += __shfl_xor(v.x, 1, 64);
-        v.y += __shfl_xor(v.y, 1, 64);
-        v.x += __shfl_xor(v.x, 2, 64);
-        v.y += __shfl_xor(v.y, 2, 64);
-        if (e < K * K && rg == 0) S.u.A[e / K][e % K] = v;
-    }
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) {
+            double2 t = acc[u][v];
+            t.x += __shfl_xor(t.x, 1, 64);
+            t.y += __shfl_xor(t.y, 1, 64);
+            t.x += __shfl_xor(t.x, 2, 64);
+            t.y += __shfl_xor(t.y, 2, 64);
+            if (rg == 0 && k0 + u < K && j0 + v < K) S.u.A[k0 + u][j0 + v] = t;
+        }
     __syncthreads();
     double rate = 0.0;
     if (tid < K) {
