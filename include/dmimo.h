@@ -133,7 +133,7 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *             <= 0: MR uses W = H^*; ZF uses the constraint of eq. (optim1),
  *             H W^T = sqrt(sigma2) D_gamma^{1/2}; equal-gain MR uses |w| = 1.
  *   prec      precision of the Gram (ZF) for K > 8 or M > 256 (M > 128 for
- *             DMIMO_F64); G^-1 (Cholesky) and G^-1 H are FP64 in every mode.
+ *             DMIMO_F64); G^-1 (Gauss-Jordan) and G^-1 H are FP64 in every mode.
  *             Smaller deployments run in one kernel that forms G in FP64 from
  *             the stored H and inverts it by FP64 Gauss-Jordan elimination, in
  *             every mode (the MIX modes then equal DMIMO_F32 bit for bit).

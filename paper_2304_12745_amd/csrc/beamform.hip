@@ -4,11 +4,12 @@
 //
 // ZF (eq. optim1 constraint H W^T = sigma D_gamma^{1/2}, or total-power
 // scaling) runs after the Gram kernel has written G = H H^H to the workspace:
-//   1. G -> FP64 in LDS, Cholesky G = L L^H (left-looking, one column per
-//      step).  A pivot below tol * G_jj sets info = j+1.
-//   2. L^-1 by forward substitution, one column per thread.
-//      tr(G^-1) = ||L^-1||_F^2.
-//   3. G^-1 = L^-H L^-1 (FP64, K x K in LDS).
+//   1. G -> FP64 in LDS, inverted in place by Gauss-Jordan elimination
+//      without pivoting (G is Hermitian positive definite), every thread
+//      updating its entries in each of the K steps.  The pivot of step j is
+//      the diagonal entry of the Schur complement, L_jj^2 of the Cholesky
+//      factor; one below tol * G_jj sets info = j+1.  tr(G^-1) is the sum of
+//      the inverse's diagonal.
 // MR / equal-gain MR: ||H||_F^2 by block reduction.
 // Then, for every tile of 64 antennas:
 //   4. H tile -> LDS.  Four threads per antenna form x = G^-1 h_m (ZF) or the
@@ -65,15 +66,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
-    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
 __device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
     acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
     acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
@@ -81,12 +73,8 @@ __device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
 
 template <typename T2, int KT>
 struct BfShared {
-    double2 ginv[KT][KT + 1];                 // G^-1 (ZF)
+    double2 ginv[KT][KT + 1];                 // G, then G^-1 (ZF)
     union {
-        struct {
-            double2 L[KT][KT + 1];            // Cholesky factor
-            double2 Li[KT][KT + 1];           // L^-1
-        } f;
         struct {
             T2 h[KT][kCols + 1];              // H tile
             T2 w[KT][kCols + 1];              // W tile (stored precision)
@@ -95,7 +83,7 @@ struct BfShared {
     } u;
     double red[kThreads / 64];
     double scale[KT];
-    int fail;
+    double d0[KT];                            // diagonal of G
 };
 
 template <typename T2, int KT>
@@ -109,44 +97,54 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
     T2* Wb = reinterpret_cast<T2*>(a.W) + b * K * M;
 
-    if (tid == 0) S.fail = 0;
-
     if (a.precoder == DMIMO_ZF) {
         const T2* Gb = reinterpret_cast<const T2*>(a.G) + b * K * K;
         for (int e = tid; e < K * K; e += kThreads) {
             const int i = e / K, j = e - (e / K) * K;
-            S.ginv[i][j] = to_d2(Gb[e]);   // G, kept intact for the pivot test
-            S.u.f.L[i][j] = make_double2(0.0, 0.0);
-            S.u.f.Li[i][j] = make_double2(0.0, 0.0);
+            const double2 g = to_d2(Gb[e]);
+            S.ginv[i][j] = g;
+            if (i == j) S.d0[i] = g.x;   // G_jj for the pivot test
         }
         __syncthreads();
-        // 1. Cholesky, left-looking
-        for (int j = 0; j < K; ++j) {
-            if (tid == 0) {
-                double d = S.ginv[j][j].x;
-                for (int p = 0; p < j; ++p) d -= S.u.f.L[j][p].x * S.u.f.L[j][p].x + S.u.f.L[j][p].y * S.u.f.L[j][p].y;
-                if (!(d > a.pivot_tol * S.ginv[j][j].x)) {
-                    S.fail = j + 1;
-                    d = 1.0;
+        // 1. G^-1 by Gauss-Jordan elimination without pivoting, in place; all
+        //    threads read step p's pivot row and column, then write their
+        //    entries.  The pivot of step p is the Schur complement's diagonal
+        //    entry (L_pp^2 of the Cholesky factor).
+        constexpr int QG = (KT * KT + kThreads - 1) / kThreads;
+        int fail = 0;
+        for (int p = 0; p < K; ++p) {
+            const double piv = S.ginv[p][p].x;
+            if (!(piv > a.pivot_tol * S.d0[p])) {
+                fail = p + 1;
+                break;
+            }
+            const double inv = 1.0 / piv;
+            double2 nv[QG];
+#pragma unroll
+            for (int q = 0; q < QG; ++q) {
+                const int e = tid + kThreads * q;
+                if (e < K * K) {
+                    const int i = e / K, j = e - (e / K) * K;
+                    const double2 gpj = S.ginv[p][j], gip = S.ginv[i][p];
+                    const double2 r = j == p ? make_double2(inv, 0.0) : make_double2(gpj.x * inv, gpj.y * inv);
+                    if (i == p) {
+                        nv[q] = r;
+                    } else {
+                        const double2 g = j == p ? make_double2(0.0, 0.0) : S.ginv[i][j];
+                        nv[q] = make_double2(fma(-gip.x, r.x, fma(gip.y, r.y, g.x)),
+                                             fma(-gip.x, r.y, fma(-gip.y, r.x, g.y)));
+                    }
                 }
-                S.u.f.L[j][j] = make_double2(sqrt(d), 0.0);
             }
             __syncthreads();
-            if (S.fail) break;
-            const int i = j + 1 + tid;
-            if (i < K) {
-                double2 s = S.ginv[i][j];
-                for (int p = 0; p < j; ++p) {
-                    const double2 t = cmulc(S.u.f.L[i][p], S.u.f.L[j][p]);
-                    s.x -= t.x;
-                    s.y -= t.y;
-                }
-                const double inv = 1.0 / S.u.f.L[j][j].x;
-                S.u.f.L[i][j] = make_double2(s.x * inv, s.y * inv);
+#pragma unroll
+            for (int q = 0; q < QG; ++q) {
+                const int e = tid + kThreads * q;
+                if (e < K * K) S.ginv[e / K][e - (e / K) * K] = nv[q];
             }
             __syncthreads();
         }
-        if (S.fail) {
+        if (fail) {
             for (int64_t e = tid; e < (int64_t)K * M; e += kThreads) {
                 T2 z;
                 z.x = 0;
@@ -160,42 +158,12 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
             if (tid == 0) {
                 if (a.l21) a.l21[b] = 0.0;
                 if (a.rsum) a.rsum[b] = 0.0;
-                if (a.info) a.info[b] = S.fail;
+                if (a.info) a.info[b] = fail;
             }
             return;
         }
-        // 2. L^-1: thread c solves L x = e_c
-        if (tid < K) {
-            const int c = tid;
-            for (int i = c; i < K; ++i) {
-                double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
-                for (int p = c; p < i; ++p) {
-                    const double2 t = cmul(S.u.f.L[i][p], S.u.f.Li[p][c]);
-                    s.x -= t.x;
-                    s.y -= t.y;
-                }
-                const double inv = 1.0 / S.u.f.L[i][i].x;
-                S.u.f.Li[i][c] = make_double2(s.x * inv, s.y * inv);
-            }
-        }
-        __syncthreads();
-        double tr = 0.0;
-        for (int e = tid; e < K * K; e += kThreads) {
-            const double2 v = S.u.f.Li[e / K][e % K];
-            tr += v.x * v.x + v.y * v.y;
-        }
-        tr = block_sum(tr, S.red);   // tr(G^-1) = ||L^-1||_F^2
-        // 3. G^-1 = L^-H L^-1
-        for (int e = tid; e < K * K; e += kThreads) {
-            const int i = e / K, j = e - (e / K) * K;
-            double2 s = make_double2(0.0, 0.0);
-            for (int p = (i > j ? i : j); p < K; ++p) {
-                const double2 t = cconjmul(S.u.f.Li[p][i], S.u.f.Li[p][j]);
-                s.x += t.x;
-                s.y += t.y;
-            }
-            S.ginv[i][j] = s;
-        }
+        double tr = 0.0;   // tr(G^-1)
+        for (int k = 0; k < K; ++k) tr += S.ginv[k][k].x;
         if (tid < K)
             S.scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total / tr) : sqrt(a.sigma2) * sqrt(a.gamma[tid]);
         __syncthreads();

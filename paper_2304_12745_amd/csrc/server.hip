@@ -8,8 +8,8 @@
 //     their HBM footprint (server scratch + output maps) fits the budget.
 //     The scratch comes from one arena allocated at creation; nothing is
 //     allocated afterwards.  An admitted query gets its user channel
-//     (channel kernel) and precoder (beamform kernel, Gram + FP64 Cholesky
-//     for ZF) on the server stream.
+//     (channel kernel) and precoder (beamform kernel; for ZF the Gram and an
+//     FP64 inverse) on the server stream.
 //   * ticks: each tick is one launch of serve_kernel, a fixed grid that
 //     loops over a list of (query, 128- or 256-point tile) work items.  The
 //     items come from every active query, smallest remaining work first,

@@ -295,7 +295,7 @@ def test_beamform_room_zf_total_power(D):
 
 @pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 def test_beamform_batched_rician_zf(D, prec):
-    # ZF via the mixed Gram: SINR within 0.01 dB (FP32) / 0.1 dB (mixed), FP64 Cholesky
+    # ZF via the mixed Gram: SINR within 0.01 dB (FP32) / 0.1 dB (mixed), FP64 inverse
     say(f"beamform ZF batched Rician (K=16, M=256), Gram {prec}")
     w = WL.batched_workload(B=16)
     Hc = np.stack([O.rician_channel(w.user_xyz[b], w.ap_xyz[b], w.freq_hz, w.kappa_lin,
