@@ -137,6 +137,9 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *             Smaller deployments run in one kernel that forms G in FP64 from
  *             the stored H and inverts it by FP64 Gauss-Jordan elimination, in
  *             every mode (the MIX modes then equal DMIMO_F32 bit for bit).
+ *             ZF calls of at most 64 deployments with at least 8 tiles of 64
+ *             antennas (M > 448) also form G in FP64, from per-tile sums
+ *             computed in parallel workgroups and added in tile order.
  * Outputs (device; any may be NULL except W):
  *   W      [B][K][M] precoder, same complex type as H.
  *   p_ant  FP64 [B][M]  per-antenna power p_m = sum_k |w_km|^2.

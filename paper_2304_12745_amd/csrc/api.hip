@@ -154,10 +154,8 @@ size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32
     (void)N;
     if (B <= 0 || K <= 0) return 0;
     switch (call) {
-        case DMIMO_CALL_BEAMFORM_ZF: {
-            const size_t elem = prec == DMIMO_F64 ? 16 : 8;
-            return align256((size_t)B * K * K * elem);
-        }
+        case DMIMO_CALL_BEAMFORM_ZF:
+            return beamform_zf_workspace_bytes(B, K, M, prec);
         case DMIMO_CALL_PA_PRECODER: {
             if (K > 32 || M < 1 || M > 4096) return 0;
             const size_t f = align256((size_t)B * 2 * sizeof(double));

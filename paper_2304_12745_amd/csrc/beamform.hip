@@ -86,86 +86,243 @@ struct BfShared {
     double d0[KT];                            // diagonal of G
 };
 
+// Gauss-Jordan elimination without pivoting of the K x K matrix in g (LDS),
+// in place, by all threads of the workgroup: each step reads its pivot row
+// and column, then every thread writes its entries.  The pivot of step p is
+// the diagonal entry of the Schur complement (L_pp^2 of the Cholesky factor);
+// one not above tol * d0[p] stops the elimination.  Returns 0, or p + 1 for
+// the failed step (the same value in every thread).
+template <int KT>
+__device__ int gj_invert(double2 (*g)[KT + 1], const double* d0, int K, double tol) {
+    constexpr int QG = (KT * KT + kThreads - 1) / kThreads;
+    const int tid = threadIdx.x;
+    for (int p = 0; p < K; ++p) {
+        const double piv = g[p][p].x;
+        if (!(piv > tol * d0[p])) return p + 1;
+        const double inv = 1.0 / piv;
+        double2 nv[QG];
+#pragma unroll
+        for (int q = 0; q < QG; ++q) {
+            const int e = tid + kThreads * q;
+            if (e < K * K) {
+                const int i = e / K, j = e - (e / K) * K;
+                const double2 gpj = g[p][j], gip = g[i][p];
+                const double2 r = j == p ? make_double2(inv, 0.0) : make_double2(gpj.x * inv, gpj.y * inv);
+                if (i == p) {
+                    nv[q] = r;
+                } else {
+                    const double2 x = j == p ? make_double2(0.0, 0.0) : g[i][j];
+                    nv[q] = make_double2(fma(-gip.x, r.x, fma(gip.y, r.y, x.x)),
+                                         fma(-gip.x, r.y, fma(-gip.y, r.x, x.y)));
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QG; ++q) {
+            const int e = tid + kThreads * q;
+            if (e < K * K) g[e / K][e - (e / K) * K] = nv[q];
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
+// Loads G[b] (as written by the Gram) into g and its diagonal into d0.
+template <typename T2, int KT>
+__device__ void load_gram(const BfDev& a, int64_t b, double2 (*g)[KT + 1], double* d0) {
+    const int K = a.K;
+    const T2* Gb = reinterpret_cast<const T2*>(a.G) + b * K * K;
+    for (int e = threadIdx.x; e < K * K; e += kThreads) {
+        const int i = e / K, j = e - (e / K) * K;
+        const double2 v = to_d2(Gb[e]);
+        g[i][j] = v;
+        if (i == j) d0[i] = v.x;
+    }
+}
+
+template <int KT>
+__device__ __forceinline__ double zf_scale(const BfDev& a, double tr, int k) {
+    return a.p_total > 0.0 ? sqrt(a.p_total / tr) : sqrt(a.sigma2) * sqrt(a.gamma[k]);
+}
+
+// Thread roles of one 64-antenna tile (256 threads):
+//   column pass: antenna cc = tid / 4, users rg, rg + 4, ... (rg = tid % 4);
+//   gains: the K x K matrix in 8 x 8 blocks of BS x BS entries, block tid / 4,
+//   antennas c = rg (mod 4); a block reuses each h and w value it reads BS times.
+template <int KT>
+struct TileRoles {
+    static constexpr int BS = KT / 8;
+    int cc, rg, k0, j0;
+    __device__ TileRoles() {
+        cc = threadIdx.x >> 2;
+        rg = threadIdx.x & 3;
+        k0 = BS * (cc >> 3);
+        j0 = BS * (cc & 7);
+    }
+};
+
+// One tile, with H[b][:, m0 .. m0 + mc) already in h (LDS): forms and stores
+// W and p_m (scale[k] per user; ZF: W = scale conj(G^-1 h)), adds sqrt(p_m) to
+// l21 and, if want_gain, the tile's share of A = H W^T to acc.
+template <typename T2, int KT>
+__device__ void bf_tile(const BfDev& a, int64_t b, int64_t m0, int mc, const TileRoles<KT>& R,
+                        const double2 (*ginv)[KT + 1], const double* scale, const T2 (*h)[kCols + 1],
+                        T2 (*w)[kCols + 1], bool want_gain,
+                        double2 (&acc)[TileRoles<KT>::BS][TileRoles<KT>::BS], double& l21) {
+    constexpr int BS = TileRoles<KT>::BS;
+    const int K = a.K;
+    const int64_t M = a.M;
+    T2* Wb = reinterpret_cast<T2*>(a.W) + b * K * M;
+    const int cc = R.cc, rg = R.rg;
+    if (cc < mc) {
+        const int64_t m = m0 + cc;
+        double pm = 0.0;
+        // ZF: x_k = sum_j G^-1[k][j] h_j for this thread's users k = rg + 4 t,
+        // each h_j read once
+        constexpr int KU = KT / 4;
+        double2 x[KU];
+        if (a.precoder == DMIMO_ZF) {
+#pragma unroll
+            for (int t = 0; t < KU; ++t) x[t] = make_double2(0.0, 0.0);
+            for (int j = 0; j < K; ++j) {
+                const double2 hj = to_d2(h[j][cc]);
+#pragma unroll
+                for (int t = 0; t < KU; ++t) cfma(x[t], ginv[rg + 4 * t][j], hj);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KU; ++t) {
+            const int k = rg + 4 * t;
+            if (k >= K) break;
+            double2 wv;
+            if (a.precoder == DMIMO_ZF) {
+                wv = make_double2(scale[k] * x[t].x, -scale[k] * x[t].y);
+            } else {
+                const double2 hk = to_d2(h[k][cc]);
+                if (a.precoder == DMIMO_MR) {
+                    wv = make_double2(scale[k] * hk.x, -scale[k] * hk.y);
+                } else {
+                    const double mag = sqrt(hk.x * hk.x + hk.y * hk.y);
+                    wv = mag > 0.0 ? make_double2(scale[k] * hk.x / mag, -scale[k] * hk.y / mag)
+                                   : make_double2(scale[k], 0.0);
+                }
+            }
+            T2 ws;
+            ws.x = wv.x;
+            ws.y = wv.y;
+            Wb[(int64_t)k * M + m] = ws;
+            w[k][cc] = ws;
+            pm += (double)ws.x * (double)ws.x + (double)ws.y * (double)ws.y;
+        }
+        // the four threads of a column are adjacent lanes
+        pm += __shfl_xor(pm, 1, 64);
+        pm += __shfl_xor(pm, 2, 64);
+        if (rg == 0) {
+            if (a.p_ant) a.p_ant[b * M + m] = pm;
+            l21 += sqrt(pm);
+        }
+    }
+    if (!want_gain) return;
+    __syncthreads();
+    const int k0 = R.k0, j0 = R.j0;
+    if (k0 < K && j0 < K)
+        for (int c = rg; c < mc; c += 4) {
+            double2 hk[BS], wj[BS];
+#pragma unroll
+            for (int u = 0; u < BS; ++u) {
+                hk[u] = k0 + u < K ? to_d2(h[k0 + u][c]) : make_double2(0.0, 0.0);
+                wj[u] = j0 + u < K ? to_d2(w[j0 + u][c]) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < BS; ++u)
+#pragma unroll
+                for (int v = 0; v < BS; ++v) cfma(acc[u][v], hk[u], wj[v]);
+        }
+}
+
+// Sum of a block's partial gains over its four antenna phases (adjacent lanes).
+template <int BS>
+__device__ __forceinline__ double2 phase_sum(double2 t) {
+    t.x += __shfl_xor(t.x, 1, 64);
+    t.y += __shfl_xor(t.y, 1, 64);
+    t.x += __shfl_xor(t.x, 2, 64);
+    t.y += __shfl_xor(t.y, 2, 64);
+    return t;
+}
+
+// SINR_k of the gains A (LDS) and the sum rate, by the first wave.
+template <int KT>
+__device__ void gains_epilogue(const BfDev& a, int64_t b, const double2 (*A)[KT + 1], double* red) {
+    const int K = a.K;
+    double rate = 0.0;
+    const int tid = threadIdx.x;
+    if (tid < K) {
+        double sig = 0.0, intf = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const double2 v = A[tid][j];
+            const double p = v.x * v.x + v.y * v.y;
+            if (j == tid) sig = p;
+            else intf += p;
+        }
+        const double snr = sig / (intf + a.sigma2);
+        if (a.sinr) a.sinr[b * K + tid] = snr;
+        rate = log2(1.0 + snr);
+    }
+    rate = block_sum(rate, red);
+    if (tid == 0 && a.rsum) a.rsum[b] = rate;
+}
+
+// Outputs of a deployment whose ZF pivot p failed: W, p_m, SINR, ||W||_{2,1}
+// and the sum rate zero, info = p.  The W and p_m zeros cover the antennas
+// [m_lo, m_hi); the rest is written by thread block `owner` only.
+template <typename T2>
+__device__ void zf_failed(const BfDev& a, int64_t b, int fail, int64_t m_lo, int64_t m_hi, bool owner) {
+    const int K = a.K, tid = threadIdx.x;
+    const int64_t M = a.M;
+    T2* Wb = reinterpret_cast<T2*>(a.W) + b * K * M;
+    for (int64_t e = tid; e < (int64_t)K * (m_hi - m_lo); e += kThreads) {
+        const int64_t k = e / (m_hi - m_lo), m = m_lo + (e - k * (m_hi - m_lo));
+        T2 z;
+        z.x = 0;
+        z.y = 0;
+        Wb[k * M + m] = z;
+    }
+    if (a.p_ant)
+        for (int64_t m = m_lo + tid; m < m_hi; m += kThreads) a.p_ant[b * M + m] = 0.0;
+    if (!owner) return;
+    if (a.sinr)
+        for (int k = tid; k < K; k += kThreads) a.sinr[b * K + k] = 0.0;
+    if (tid == 0) {
+        if (a.l21) a.l21[b] = 0.0;
+        if (a.rsum) a.rsum[b] = 0.0;
+        if (a.info) a.info[b] = fail;
+    }
+}
+
 template <typename T2, int KT>
 __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
     __shared__ BfShared<T2, KT> S;
+    constexpr int BS = TileRoles<KT>::BS;
 
     const int64_t b = blockIdx.x;
     const int K = a.K;
     const int64_t M = a.M;
     const int tid = threadIdx.x;
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
-    T2* Wb = reinterpret_cast<T2*>(a.W) + b * K * M;
 
     if (a.precoder == DMIMO_ZF) {
-        const T2* Gb = reinterpret_cast<const T2*>(a.G) + b * K * K;
-        for (int e = tid; e < K * K; e += kThreads) {
-            const int i = e / K, j = e - (e / K) * K;
-            const double2 g = to_d2(Gb[e]);
-            S.ginv[i][j] = g;
-            if (i == j) S.d0[i] = g.x;   // G_jj for the pivot test
-        }
+        load_gram<T2, KT>(a, b, S.ginv, S.d0);
         __syncthreads();
-        // 1. G^-1 by Gauss-Jordan elimination without pivoting, in place; all
-        //    threads read step p's pivot row and column, then write their
-        //    entries.  The pivot of step p is the Schur complement's diagonal
-        //    entry (L_pp^2 of the Cholesky factor).
-        constexpr int QG = (KT * KT + kThreads - 1) / kThreads;
-        int fail = 0;
-        for (int p = 0; p < K; ++p) {
-            const double piv = S.ginv[p][p].x;
-            if (!(piv > a.pivot_tol * S.d0[p])) {
-                fail = p + 1;
-                break;
-            }
-            const double inv = 1.0 / piv;
-            double2 nv[QG];
-#pragma unroll
-            for (int q = 0; q < QG; ++q) {
-                const int e = tid + kThreads * q;
-                if (e < K * K) {
-                    const int i = e / K, j = e - (e / K) * K;
-                    const double2 gpj = S.ginv[p][j], gip = S.ginv[i][p];
-                    const double2 r = j == p ? make_double2(inv, 0.0) : make_double2(gpj.x * inv, gpj.y * inv);
-                    if (i == p) {
-                        nv[q] = r;
-                    } else {
-                        const double2 g = j == p ? make_double2(0.0, 0.0) : S.ginv[i][j];
-                        nv[q] = make_double2(fma(-gip.x, r.x, fma(gip.y, r.y, g.x)),
-                                             fma(-gip.x, r.y, fma(-gip.y, r.x, g.y)));
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < QG; ++q) {
-                const int e = tid + kThreads * q;
-                if (e < K * K) S.ginv[e / K][e - (e / K) * K] = nv[q];
-            }
-            __syncthreads();
-        }
+        // 1. G^-1 in place
+        const int fail = gj_invert<KT>(S.ginv, S.d0, K, a.pivot_tol);
         if (fail) {
-            for (int64_t e = tid; e < (int64_t)K * M; e += kThreads) {
-                T2 z;
-                z.x = 0;
-                z.y = 0;
-                Wb[e] = z;
-            }
-            if (a.p_ant)
-                for (int64_t m = tid; m < M; m += kThreads) a.p_ant[b * M + m] = 0.0;
-            if (a.sinr)
-                for (int k = tid; k < K; k += kThreads) a.sinr[b * K + k] = 0.0;
-            if (tid == 0) {
-                if (a.l21) a.l21[b] = 0.0;
-                if (a.rsum) a.rsum[b] = 0.0;
-                if (a.info) a.info[b] = fail;
-            }
+            zf_failed<T2>(a, b, fail, 0, M, true);
             return;
         }
         double tr = 0.0;   // tr(G^-1)
         for (int k = 0; k < K; ++k) tr += S.ginv[k][k].x;
-        if (tid < K)
-            S.scale[tid] = a.p_total > 0.0 ? sqrt(a.p_total / tr) : sqrt(a.sigma2) * sqrt(a.gamma[tid]);
+        if (tid < K) S.scale[tid] = zf_scale<KT>(a, tr, tid);
         __syncthreads();
     } else {
         double f = 0.0;
@@ -183,15 +340,8 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
         __syncthreads();
     }
 
-    // 4-5. tiles of kCols antennas
-    // column pass: thread -> (column c = tid / 4, row group g = tid % 4, rows g, g+4, ...)
-    const int cc = tid >> 2;
-    const int rg = tid & 3;
-    // gains: the K x K matrix in 8 x 8 blocks of BS x BS entries; block tid / 4,
-    // antennas c = tid % 4 (mod 4).  A block reuses each h and w value it reads
-    // BS times.
-    constexpr int BS = KT / 8;
-    const int k0 = BS * (cc >> 3), j0 = BS * (cc & 7);
+    // 2-3. tiles of kCols antennas
+    const TileRoles<KT> R;
     double2 acc[BS][BS];
 #pragma unroll
     for (int u = 0; u < BS; ++u)
@@ -199,7 +349,6 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
         for (int v = 0; v < BS; ++v) acc[u][v] = make_double2(0.0, 0.0);
     double l21 = 0.0;
     const bool want_gain = a.sinr || a.rsum;
-
     for (int64_t m0 = 0; m0 < M; m0 += kCols) {
         const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
         __syncthreads();
@@ -208,69 +357,7 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
             if (c < mc) S.u.t.h[k][c] = Hb[(int64_t)k * M + m0 + c];
         }
         __syncthreads();
-        if (cc < mc) {
-            const int64_t m = m0 + cc;
-            double pm = 0.0;
-            // ZF: x_k = sum_j G^-1[k][j] h_j for this thread's users k = rg + 4 t,
-            // each h_j read once
-            constexpr int KU = KT / 4;
-            double2 x[KU];
-            if (a.precoder == DMIMO_ZF) {
-#pragma unroll
-                for (int t = 0; t < KU; ++t) x[t] = make_double2(0.0, 0.0);
-                for (int j = 0; j < K; ++j) {
-                    const double2 hj = to_d2(S.u.t.h[j][cc]);
-#pragma unroll
-                    for (int t = 0; t < KU; ++t) cfma(x[t], S.ginv[rg + 4 * t][j], hj);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < KU; ++t) {
-                const int k = rg + 4 * t;
-                if (k >= K) break;
-                double2 w;
-                if (a.precoder == DMIMO_ZF) {
-                    w = make_double2(S.scale[k] * x[t].x, -S.scale[k] * x[t].y);
-                } else {
-                    const double2 h = to_d2(S.u.t.h[k][cc]);
-                    if (a.precoder == DMIMO_MR) {
-                        w = make_double2(S.scale[k] * h.x, -S.scale[k] * h.y);
-                    } else {
-                        const double mag = sqrt(h.x * h.x + h.y * h.y);
-                        w = mag > 0.0 ? make_double2(S.scale[k] * h.x / mag, -S.scale[k] * h.y / mag)
-                                      : make_double2(S.scale[k], 0.0);
-                    }
-                }
-                T2 ws;
-                ws.x = w.x;
-                ws.y = w.y;
-                Wb[(int64_t)k * M + m] = ws;
-                S.u.t.w[k][cc] = ws;
-                pm += (double)ws.x * (double)ws.x + (double)ws.y * (double)ws.y;
-            }
-            // the four threads of a column are adjacent lanes
-            pm += __shfl_xor(pm, 1, 64);
-            pm += __shfl_xor(pm, 2, 64);
-            if (rg == 0) {
-                if (a.p_ant) a.p_ant[b * M + m] = pm;
-                l21 += sqrt(pm);
-            }
-        }
-        if (!want_gain) continue;
-        __syncthreads();
-        if (k0 < K && j0 < K)
-            for (int c = rg; c < mc; c += 4) {
-                double2 hk[BS], wj[BS];
-#pragma unroll
-                for (int u = 0; u < BS; ++u) {
-                    hk[u] = k0 + u < K ? to_d2(S.u.t.h[k0 + u][c]) : make_double2(0.0, 0.0);
-                    wj[u] = j0 + u < K ? to_d2(S.u.t.w[j0 + u][c]) : make_double2(0.0, 0.0);
-                }
-#pragma unroll
-                for (int u = 0; u < BS; ++u)
-#pragma unroll
-                    for (int v = 0; v < BS; ++v) cfma(acc[u][v], hk[u], wj[v]);
-            }
+        bf_tile<T2, KT>(a, b, m0, mc, R, S.ginv, S.scale, S.u.t.h, S.u.t.w, want_gain, acc, l21);
     }
     l21 = block_sum(l21, S.red);
     if (tid == 0) {
@@ -283,30 +370,203 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
     for (int u = 0; u < BS; ++u)
 #pragma unroll
         for (int v = 0; v < BS; ++v) {
-            double2 t = acc[u][v];
-            t.x += __shfl_xor(t.x, 1, 64);
-            t.y += __shfl_xor(t.y, 1, 64);
-            t.x += __shfl_xor(t.x, 2, 64);
-            t.y += __shfl_xor(t.y, 2, 64);
-            if (rg == 0 && k0 + u < K && j0 + v < K) S.u.A[k0 + u][j0 + v] = t;
+            const double2 t = phase_sum<BS>(acc[u][v]);
+            if (R.rg == 0 && R.k0 + u < K && R.j0 + v < K) S.u.A[R.k0 + u][R.j0 + v] = t;
         }
     __syncthreads();
-    double rate = 0.0;
-    if (tid < K) {
-        const int k = tid;
-        double sig = 0.0, intf = 0.0;
-        for (int j = 0; j < K; ++j) {
-            const double2 v = S.u.A[k][j];
-            const double p = v.x * v.x + v.y * v.y;
-            if (j == k) sig = p;
-            else intf += p;
-        }
-        const double snr = sig / (intf + a.sigma2);
-        if (a.sinr) a.sinr[b * K + k] = snr;
-        rate = log2(1.0 + snr);
+    gains_epilogue<KT>(a, b, S.u.A, S.red);
+}
+
+// ---------------------------------------------------------------------------
+// ZF of few deployments with many antennas (B <= kWideMaxB, at least
+// kWideMinTiles tiles of 64 antennas), every step spread over the tiles:
+//   bfw_gram_kernel   per (tile, deployment): the tile's share of G, FP64;
+//   bfw_prep_kernel   per deployment: G = the shares summed in tile order
+//                     (FP64 in every mode), inverted by Gauss-Jordan;
+//   bfw_tile_kernel   per (tile, deployment): W, p_m and the tile's share of
+//                     the gains A = H W^T;
+//   bfw_final_kernel  per deployment: the shares summed in tile order, SINR,
+//                     sum rate, ||W||_{2,1}.
+// Workspace after the Gram slot: G^-1 [B][K][K] and scale [B][K] (FP64), the
+// failed pivot [B], tile shares [B][T][K][K] (FP64: first of G, then of the
+// gains) and sqrt(p_m) sums [B][T].
+// ---------------------------------------------------------------------------
+constexpr int64_t kWideMaxB = 64;
+constexpr int64_t kWideMinTiles = 8;
+
+struct BfWide {
+    double2* ginv;
+    double* scale;
+    int32_t* fail;
+    double2* gpart;
+    double* lpart;
+    int64_t T;
+};
+
+// The tile's share of G = H H^H, FP64 sums, in the gain-share slot of the
+// workspace (consumed by bfw_prep_kernel before the tiles overwrite it).
+template <typename T2, int KT>
+__global__ __launch_bounds__(kThreads) void bfw_gram_kernel(BfDev a, BfWide wd) {
+    __shared__ T2 h[KT][kCols + 1];
+    constexpr int BS = TileRoles<KT>::BS;
+    const int64_t t = blockIdx.x, b = blockIdx.y;
+    const int K = a.K, tid = threadIdx.x;
+    const int64_t M = a.M, m0 = t * kCols;
+    const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
+    const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
+    for (int e = tid; e < K * kCols; e += kThreads) {
+        const int k = e / kCols, c = e - k * kCols;
+        if (c < mc) h[k][c] = Hb[(int64_t)k * M + m0 + c];
     }
-    rate = block_sum(rate, S.red);
-    if (tid == 0 && a.rsum) a.rsum[b] = rate;
+    __syncthreads();
+    const TileRoles<KT> R;
+    double2 acc[BS][BS];
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) acc[u][v] = make_double2(0.0, 0.0);
+    if (R.k0 < K && R.j0 < K)
+        for (int c = R.rg; c < mc; c += 4) {
+            double2 hk[BS], hj[BS];
+#pragma unroll
+            for (int u = 0; u < BS; ++u) {
+                hk[u] = R.k0 + u < K ? to_d2(h[R.k0 + u][c]) : make_double2(0.0, 0.0);
+                hj[u] = R.j0 + u < K ? to_d2(h[R.j0 + u][c]) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < BS; ++u)
+#pragma unroll
+                for (int v = 0; v < BS; ++v) {   // h_k conj(h_j)
+                    acc[u][v].x = fma(hk[u].x, hj[v].x, fma(hk[u].y, hj[v].y, acc[u][v].x));
+                    acc[u][v].y = fma(hk[u].y, hj[v].x, fma(-hk[u].x, hj[v].y, acc[u][v].y));
+                }
+        }
+    double2* gp = wd.gpart + (b * wd.T + t) * K * K;
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) {
+            const double2 sum = phase_sum<BS>(acc[u][v]);
+            if (R.rg == 0 && R.k0 + u < K && R.j0 + v < K) gp[(R.k0 + u) * K + R.j0 + v] = sum;
+        }
+}
+
+// G of deployment b from the tiles' shares (tile order; the diagonal's
+// imaginary part set to zero), inverted in place; G^-1, the scale and the
+// failed pivot to the workspace.
+template <int KT>
+__global__ __launch_bounds__(kThreads) void bfw_prep_kernel(BfDev a, BfWide wd) {
+    __shared__ double2 g[KT][KT + 1];
+    __shared__ double d0[KT];
+    const int64_t b = blockIdx.x;
+    const int K = a.K, tid = threadIdx.x;
+    for (int e = tid; e < K * K; e += kThreads) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int64_t t = 0; t < wd.T; ++t) {
+            const double2 v = wd.gpart[(b * wd.T + t) * K * K + e];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        const int i = e / K, j = e - (e / K) * K;
+        if (i == j) {
+            s.y = 0.0;
+            d0[i] = s.x;
+        }
+        g[i][j] = s;
+    }
+    __syncthreads();
+    const int fail = gj_invert<KT>(g, d0, K, a.pivot_tol);
+    for (int e = tid; e < K * K; e += kThreads) wd.ginv[b * K * K + e] = g[e / K][e - (e / K) * K];
+    double tr = 0.0;
+    for (int k = 0; k < K; ++k) tr += g[k][k].x;
+    if (tid < K) wd.scale[b * K + tid] = fail ? 0.0 : zf_scale<KT>(a, tr, tid);
+    if (tid == 0) wd.fail[b] = fail;
+}
+
+template <typename T2, int KT>
+__global__ __launch_bounds__(kThreads) void bfw_tile_kernel(BfDev a, BfWide wd) {
+    __shared__ double2 ginv[KT][KT + 1];
+    __shared__ T2 h[KT][kCols + 1];
+    __shared__ T2 w[KT][kCols + 1];
+    __shared__ double scale[KT];
+    __shared__ double red[kThreads / 64];
+    constexpr int BS = TileRoles<KT>::BS;
+    const int64_t t = blockIdx.x, b = blockIdx.y;
+    const int K = a.K, tid = threadIdx.x;
+    const int64_t M = a.M, m0 = t * kCols;
+    const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
+    const int fail = wd.fail[b];
+    if (fail) {
+        zf_failed<T2>(a, b, fail, m0, m0 + mc, false);
+        return;
+    }
+    const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
+    for (int e = tid; e < K * K; e += kThreads) ginv[e / K][e - (e / K) * K] = wd.ginv[b * K * K + e];
+    if (tid < K) scale[tid] = wd.scale[b * K + tid];
+    for (int e = tid; e < K * kCols; e += kThreads) {
+        const int k = e / kCols, c = e - k * kCols;
+        if (c < mc) h[k][c] = Hb[(int64_t)k * M + m0 + c];
+    }
+    __syncthreads();
+    const TileRoles<KT> R;
+    double2 acc[BS][BS];
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) acc[u][v] = make_double2(0.0, 0.0);
+    double l21 = 0.0;
+    const bool want_gain = a.sinr || a.rsum;
+    bf_tile<T2, KT>(a, b, m0, mc, R, ginv, scale, h, w, want_gain, acc, l21);
+    l21 = block_sum(l21, red);
+    if (tid == 0) wd.lpart[b * wd.T + t] = l21;
+    if (!want_gain) return;
+    double2* gp = wd.gpart + (b * wd.T + t) * K * K;
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int v = 0; v < BS; ++v) {
+            const double2 s = phase_sum<BS>(acc[u][v]);
+            if (R.rg == 0 && R.k0 + u < K && R.j0 + v < K) gp[(R.k0 + u) * K + R.j0 + v] = s;
+        }
+}
+
+template <int KT>
+__global__ __launch_bounds__(kThreads) void bfw_final_kernel(BfDev a, BfWide wd) {
+    __shared__ double2 A[KT][KT + 1];
+    __shared__ double red[kThreads / 64];
+    const int64_t b = blockIdx.x;
+    const int K = a.K, tid = threadIdx.x;
+    const int fail = wd.fail[b];
+    if (fail) {
+        if (a.sinr)
+            for (int k = tid; k < K; k += kThreads) a.sinr[b * K + k] = 0.0;
+        if (tid == 0) {
+            if (a.l21) a.l21[b] = 0.0;
+            if (a.rsum) a.rsum[b] = 0.0;
+            if (a.info) a.info[b] = fail;
+        }
+        return;
+    }
+    const bool want_gain = a.sinr || a.rsum;
+    if (want_gain) {
+        for (int e = tid; e < K * K; e += kThreads) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int64_t t = 0; t < wd.T; ++t) {
+                const double2 v = wd.gpart[(b * wd.T + t) * K * K + e];
+                s.x += v.x;
+                s.y += v.y;
+            }
+            A[e / K][e - (e / K) * K] = s;
+        }
+        __syncthreads();
+        gains_epilogue<KT>(a, b, A, red);
+    }
+    if (tid == 0) {
+        double l = 0.0;
+        for (int64_t t = 0; t < wd.T; ++t) l += wd.lpart[b * wd.T + t];
+        if (a.l21) a.l21[b] = l;
+        if (a.info) a.info[b] = 0;
+    }
 }
 
 // Deployments of at most 8 users and kSmallMaxM antennas (kSmallMaxM / 2 in
@@ -539,6 +799,43 @@ dmimo_status launch_typed(const BfDev& d, int64_t B, hipStream_t s) {
     return check_launch("beamform_kernel");
 }
 
+size_t ws_align(size_t n) { return (n + 255) & ~(size_t)255; }
+
+bool zf_wide(int64_t B, int64_t M) {
+    return B <= kWideMaxB && (M + kCols - 1) / kCols >= kWideMinTiles;
+}
+
+template <typename T2, int KT>
+void launch_wide_kt(const BfDev& d, const BfWide& wd, int64_t B, hipStream_t s) {
+    bfw_gram_kernel<T2, KT><<<dim3((unsigned)wd.T, (unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
+    bfw_prep_kernel<KT><<<dim3((unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
+    bfw_tile_kernel<T2, KT><<<dim3((unsigned)wd.T, (unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
+    bfw_final_kernel<KT><<<dim3((unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
+}
+
+template <typename T2>
+dmimo_status launch_wide(const BfDev& d, int64_t B, int prec, hipStream_t s) {
+    const int K = d.K;
+    const int64_t T = (d.M + kCols - 1) / kCols;
+    char* p = static_cast<char*>(const_cast<void*>(d.G));
+    p += ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8));
+    BfWide wd;
+    wd.T = T;
+    wd.ginv = reinterpret_cast<double2*>(p);
+    p += ws_align((size_t)B * K * K * sizeof(double2));
+    wd.scale = reinterpret_cast<double*>(p);
+    p += ws_align((size_t)B * K * sizeof(double));
+    wd.fail = reinterpret_cast<int32_t*>(p);
+    p += ws_align((size_t)B * sizeof(int32_t));
+    wd.gpart = reinterpret_cast<double2*>(p);
+    p += ws_align((size_t)B * T * K * K * sizeof(double2));
+    wd.lpart = reinterpret_cast<double*>(p);
+    if (K <= 8) launch_wide_kt<T2, 8>(d, wd, B, s);
+    else if (K <= 16) launch_wide_kt<T2, 16>(d, wd, B, s);
+    else launch_wide_kt<T2, 32>(d, wd, B, s);
+    return check_launch("beamform (wide ZF)");
+}
+
 // The one-pass kernel's antenna limit: LDS holds H and W, 8 x (MT + 1) each.
 int64_t small_max_m(int prec) { return prec == DMIMO_F64 ? kSmallMaxM / 2 : kSmallMaxM; }
 
@@ -551,6 +848,18 @@ dmimo_status launch_small(const BfDev& d, int64_t B, hipStream_t s) {
 }
 
 }  // namespace
+
+size_t beamform_zf_workspace_bytes(int64_t B, int K, int64_t M, int prec) {
+    size_t n = ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8));
+    if (!zf_wide(B, M) || (K <= kSmallK && M <= small_max_m(prec))) return n;
+    const int64_t T = (M + kCols - 1) / kCols;
+    n += ws_align((size_t)B * K * K * sizeof(double2));
+    n += ws_align((size_t)B * K * sizeof(double));
+    n += ws_align((size_t)B * sizeof(int32_t));
+    n += ws_align((size_t)B * T * K * K * sizeof(double2));
+    n += ws_align((size_t)B * T * sizeof(double));
+    return n;
+}
 
 dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
     if (a.B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "beamform: B too large");
@@ -577,6 +886,13 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
         d.pivot_tol = a.prec == DMIMO_F64 ? 1e-12 : 1e-6;
         if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, s);
         return launch_small<float2, kSmallMaxM>(d, a.B, s);
+    }
+    if (a.precoder == DMIMO_ZF && zf_wide(a.B, a.M)) {
+        // G from FP64 tile sums: the FP64 Gram's tolerance for FP64 input,
+        // the FP32 one otherwise
+        d.pivot_tol = a.prec == DMIMO_F64 ? 1e-12 : 1e-6;
+        if (a.prec == DMIMO_F64) return launch_wide<double2>(d, a.B, a.prec, s);
+        return launch_wide<float2>(d, a.B, a.prec, s);
     }
     if (a.precoder == DMIMO_ZF) {
         dmimo_status st = launch_gram(a.B, a.K, a.M, a.H, a.prec, a.ws, s);

@@ -45,6 +45,14 @@ def test_workspace_size(lib):
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 16, 256, 0, D.F32) == 1024 * 16 * 16 * 8
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 3, 5, 9, 0, D.F64) == 1280  # 3*25*16 = 1200 -> 256-aligned
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, 1024, 16, 256, 0, D.F32) == 0
+    # few deployments with at least 8 tiles of 64 antennas: the Gram, G^-1,
+    # scale, failed pivot, per-tile gain shares and per-tile sqrt(p_m) sums
+    a = lambda n: (n + 255) // 256 * 256
+    B, K, M, T = 2, 32, 1024, 16
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, B, K, M, 0, D.F32) == (
+        a(B * K * K * 8) + a(B * K * K * 16) + a(B * K * 8) + a(B * 4) + a(B * T * K * K * 16) + a(B * T * 8))
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 65, K, M, 0, D.F32) == a(65 * K * K * 8)
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1, K, 448, 0, D.F32) == a(K * K * 8)
     assert lib.dmimo_workspace_size(D.CALL_POWERMAP, 1, 8, 64, 100, D.F32) == 0
 
 

@@ -329,6 +329,42 @@ def test_beamform_shapes(D, K, M):
     _check_beamform(D, c64(H), "mr", None, 0.5, 1.0, "f32", 0.01, 1e-6)
 
 
+# ZF of few deployments with many antennas runs on the wide path (B <= 64 and
+# at least 8 tiles of 64 antennas: G^-1 once, tiles in parallel workgroups,
+# gain shares summed in tile order); B = 65 and M = 448 fall outside it
+@pytest.mark.parametrize("B,K,M,prec", [(1, 32, 1024, "f32"), (2, 16, 512, "f32"), (3, 20, 700, "f64"),
+                                        (1, 5, 449, "f32"), (64, 8, 512, "f32"), (65, 8, 512, "f32"),
+                                        (2, 12, 448, "f32"), (1, 16, 600, "f16x3")])
+def test_beamform_wide_zf(D, B, K, M, prec):
+    say(f"beamform ZF wide B={B} K={K} M={M} prec={prec}")
+    rng = np.random.default_rng(B + K + M)
+    H = WL.complex_normal(rng, (B, K, M))
+    Hin = H if prec == "f64" else c64(H)
+    tol = {"f64": (1e-7, 1e-9), "f32": (0.01, 1e-4), "f16x3": (MAP_TOL["f16x3"], 1e-4)}[prec]
+    _check_beamform(D, Hin, "zf", np.linspace(1, 4, K), 0.5, 0.0, prec, tol[0], tol[1])
+    _check_beamform(D, Hin, "zf", None, 0.5, 1.0, prec, tol[0], tol[1])
+
+
+def test_beamform_wide_singular_deployment_is_isolated(D):
+    say("beamform ZF wide path, singular deployment")
+    rng = np.random.default_rng(33)
+    B, K, M = 3, 9, 600
+    aps = np.stack([WL.uniform_positions(rng, M, 40, 40, 4.0) for _ in range(B)])
+    users = np.stack([WL.uniform_positions(rng, K, 40, 40, 1.2) for _ in range(B)])
+    users[1, 7] = users[1, 2]          # duplicate user in deployment 1
+    Hc = np.stack([O.los_channel(users[b], aps[b], 3.5e9) for b in range(B)])
+    H = c64(Hc)
+    r = D.beamform(dev(H), "zf", None, 1e-12, 1.0, "f32")
+    info = host(r.info)
+    assert info[1] > 0 and info[[0, 2]].tolist() == [0, 0]
+    assert not np.any(host(r.W)[1]) and not np.any(host(r.p_ant)[1])
+    assert host(r.rsum)[1] == 0.0 and host(r.l21)[1] == 0.0 and not np.any(host(r.sinr)[1])
+    Wr, sing = O.zf_precoder(H.astype(np.complex128), None, 1e-12, 1.0)
+    assert sing[1] and not sing[[0, 2]].any()
+    for b in (0, 2):
+        assert np.linalg.norm(host(r.W)[b] - Wr[b]) / np.linalg.norm(Wr[b]) < 1e-4
+
+
 def test_beamform_singular_deployment_is_isolated(D):
     say("beamform ZF singular deployment")
     rng = np.random.default_rng(31)
