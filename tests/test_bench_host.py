@@ -1,0 +1,68 @@
+"""Host-side behaviour of bench.py that needs no GPU: the one-GPU rule, the
+missing-GPU exit, and the rule that HBM traffic is reported only for the
+kernel sources it was measured on."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(args, env_extra=None):
+    env = dict(os.environ)
+    env.update(env_extra or {})
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], cwd=ROOT,
+                          env=env, capture_output=True, text=True, timeout=300)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run(["--gpus", "2"])
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_a_multi_rank_launch_is_refused():
+    r = _run([], {"WORLD_SIZE": "2", "RANK": "0", "LOCAL_RANK": "0"})
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_no_gpu_exits_without_a_result_line():
+    import torch
+    if torch.cuda.is_available():
+        return
+    r = _run(["--steps", "1", "--warmup", "0"])
+    assert r.returncode == 1
+    assert "needs a GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"source_hash": "abc", "bytes_per_launch": 1234}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.load_traffic("abc") == 1234
+    assert bench.load_traffic("abd") is None
+    f.write_text("not json")
+    assert bench.load_traffic("abc") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    assert bench.load_traffic("abc") is None
+
+
+def test_source_hash_covers_every_listed_file():
+    h = bench._src_hash(bench.POWERMAP_SOURCES)
+    assert len(h) == 16 and int(h, 16) >= 0
+    for f in bench.POWERMAP_SOURCES:
+        assert os.path.exists(os.path.join(ROOT, f)), f
+    assert bench._src_hash(bench.POWERMAP_SOURCES[:-1]) != h
+
+
+def test_algorithmic_slots_per_term():
+    # the synthesis count, plus the VALU contraction of the K <= 2 kernel
+    assert bench.alg_slots_per_term(8) == bench.SYNTH_SLOTS == 32
+    assert bench.alg_slots_per_term(1) == 36
+    assert bench.alg_slots_per_term(2) == 40
