@@ -162,6 +162,50 @@ struct TileRoles {
     }
 };
 
+// Stages H[b][:, m0 .. m0 + mc) into h (LDS) with 256 threads: a thread's
+// KT/4 loads are all issued before its LDS stores.
+template <typename T2>
+struct Scalar;
+template <>
+struct Scalar<float2> {
+    using type = float;
+};
+template <>
+struct Scalar<double2> {
+    using type = double;
+};
+
+// (The staged values are kept as scalar arrays, which stay in registers; an
+// array of vector-type unions can end up in scratch.)
+template <typename T2, int KT>
+__device__ __forceinline__ void stage_tile(const T2* Hb, int K, int64_t M, int64_t m0, int mc,
+                                           T2 (*h)[kCols + 1]) {
+    using S = typename Scalar<T2>::type;
+    constexpr int IT = KT * kCols / kThreads;
+    S vx[IT], vy[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + kThreads * it;
+        const int k = e / kCols, c = e - k * kCols;
+        if (k < K && c < mc) {
+            const T2 t = Hb[(int64_t)k * M + m0 + c];
+            vx[it] = t.x;
+            vy[it] = t.y;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + kThreads * it;
+        const int k = e / kCols, c = e - k * kCols;
+        if (k < K && c < mc) {
+            T2 t;
+            t.x = vx[it];
+            t.y = vy[it];
+            h[k][c] = t;
+        }
+    }
+}
+
 // One tile, with H[b][:, m0 .. m0 + mc) already in h (LDS): forms and stores
 // W and p_m (scale[k] per user; ZF: W = scale conj(G^-1 h)), adds sqrt(p_m) to
 // l21 and, if want_gain, the tile's share of A = H W^T to acc.
@@ -352,10 +396,7 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
     for (int64_t m0 = 0; m0 < M; m0 += kCols) {
         const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
         __syncthreads();
-        for (int e = tid; e < K * kCols; e += kThreads) {
-            const int k = e / kCols, c = e - k * kCols;
-            if (c < mc) S.u.t.h[k][c] = Hb[(int64_t)k * M + m0 + c];
-        }
+        stage_tile<T2, KT>(Hb, K, M, m0, mc, S.u.t.h);
         __syncthreads();
         bf_tile<T2, KT>(a, b, m0, mc, R, S.ginv, S.scale, S.u.t.h, S.u.t.w, want_gain, acc, l21);
     }
@@ -414,10 +455,7 @@ __global__ __launch_bounds__(kThreads) void bfw_gram_kernel(BfDev a, BfWide wd) 
     const int64_t M = a.M, m0 = t * kCols;
     const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
-    for (int e = tid; e < K * kCols; e += kThreads) {
-        const int k = e / kCols, c = e - k * kCols;
-        if (c < mc) h[k][c] = Hb[(int64_t)k * M + m0 + c];
-    }
+    stage_tile<T2, KT>(Hb, K, M, m0, mc, h);
     __syncthreads();
     const TileRoles<KT> R;
     double2 acc[BS][BS];
@@ -462,7 +500,8 @@ __global__ __launch_bounds__(kThreads) void bfw_prep_kernel(BfDev a, BfWide wd) 
     const int K = a.K, tid = threadIdx.x;
     for (int e = tid; e < K * K; e += kThreads) {
         double2 s = make_double2(0.0, 0.0);
-        for (int64_t t = 0; t < wd.T; ++t) {
+#pragma unroll 8
+        for (int64_t t = 0; t < wd.T; ++t) {   // loads issued together, sums in tile order
             const double2 v = wd.gpart[(b * wd.T + t) * K * K + e];
             s.x += v.x;
             s.y += v.y;
@@ -503,10 +542,7 @@ __global__ __launch_bounds__(kThreads) void bfw_tile_kernel(BfDev a, BfWide wd) 
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
     for (int e = tid; e < K * K; e += kThreads) ginv[e / K][e - (e / K) * K] = wd.ginv[b * K * K + e];
     if (tid < K) scale[tid] = wd.scale[b * K + tid];
-    for (int e = tid; e < K * kCols; e += kThreads) {
-        const int k = e / kCols, c = e - k * kCols;
-        if (c < mc) h[k][c] = Hb[(int64_t)k * M + m0 + c];
-    }
+    stage_tile<T2, KT>(Hb, K, M, m0, mc, h);
     __syncthreads();
     const TileRoles<KT> R;
     double2 acc[BS][BS];
@@ -551,7 +587,8 @@ __global__ __launch_bounds__(kThreads) void bfw_final_kernel(BfDev a, BfWide wd)
     if (want_gain) {
         for (int e = tid; e < K * K; e += kThreads) {
             double2 s = make_double2(0.0, 0.0);
-            for (int64_t t = 0; t < wd.T; ++t) {
+#pragma unroll 8
+            for (int64_t t = 0; t < wd.T; ++t) {   // loads issued together, sums in tile order
                 const double2 v = wd.gpart[(b * wd.T + t) * K * K + e];
                 s.x += v.x;
                 s.y += v.y;

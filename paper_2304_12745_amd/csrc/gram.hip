@@ -41,13 +41,23 @@ __global__ __launch_bounds__(256) void gram_valu_kernel(const T2* __restrict__ H
     for (int64_t m0 = 0; m0 < M; m0 += kTile) {
         const int mc = (int)std::min<int64_t>(kTile, M - m0);
         __syncthreads();
-        for (int e = tid; e < K * kTile; e += blockDim.x) {
-            const int k = e / kTile;
-            const int mm = e - k * kTile;
-            if (mm < mc) {
-                const T2 h = Hb[(int64_t)k * M + m0 + mm];
-                sre[k][mm] = (R)h.x;
-                sim[k][mm] = (R)h.y;
+        {   // 256 threads; a thread's loads all issued before its LDS stores
+            constexpr int IT = KT * kTile / 256;
+            T2 hv[IT];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int e = tid + 256 * it;
+                const int k = e / kTile, mm = e - k * kTile;
+                if (k < K && mm < mc) hv[it] = Hb[(int64_t)k * M + m0 + mm];
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int e = tid + 256 * it;
+                const int k = e / kTile, mm = e - k * kTile;
+                if (k < K && mm < mc) {
+                    sre[k][mm] = (R)hv[it].x;
+                    sim[k][mm] = (R)hv[it].y;
+                }
             }
         }
         __syncthreads();

@@ -127,12 +127,23 @@ __global__ __launch_bounds__(NT) void pa_prepare_kernel(const float2* H, int K, 
     for (int m0 = 0; m0 < M; m0 += kPrepChunk) {
         const int mc = M - m0 < kPrepChunk ? M - m0 : kPrepChunk;
         __syncthreads();
-        for (int e = tid; e < K * kPrepChunk; e += NT) {
-            const int k = e / kPrepChunk, c = e - k * kPrepChunk;
-            if (c < mc) {
-                const float2 h = Hb[(int64_t)k * M + m0 + c];
-                S.u.h[k][c] = h;
-                p += (double)h.x * h.x + (double)h.y * h.y;
+        {   // a thread's loads all issued before its LDS stores
+            constexpr int IT = KM * kPrepChunk / NT;
+            float2 hv[IT];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int e = tid + NT * it;
+                const int k = e / kPrepChunk, c = e - k * kPrepChunk;
+                if (k < K && c < mc) hv[it] = Hb[(int64_t)k * M + m0 + c];
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int e = tid + NT * it;
+                const int k = e / kPrepChunk, c = e - k * kPrepChunk;
+                if (k < K && c < mc) {
+                    S.u.h[k][c] = hv[it];
+                    p += (double)hv[it].x * hv[it].x + (double)hv[it].y * hv[it].y;
+                }
             }
         }
         __syncthreads();

@@ -60,14 +60,24 @@ __device__ __forceinline__ float* part_ptr(const LgDev& a, int parity, int64_t b
 
 // Planar image of rows of X (K x M complex64) at the slab's antennas, scaled
 // and optionally conjugated: sX[R][c], R < 32 real parts, R >= 32 imaginary.
+// 256 threads; the loop is unrolled so that all of a thread's loads are in
+// flight together.
+constexpr int kLgThreads = 256;
 __device__ __forceinline__ void lg_load_slab(float* sX, const float2* X, int K, int M, int c0,
                                              float scale, bool conj) {
-    for (int e = threadIdx.x; e < kLgMaxK * kLgSlab; e += blockDim.x) {
+    float2 x[kLgMaxK * kLgSlab / kLgThreads];
+#pragma unroll
+    for (int it = 0; it < kLgMaxK * kLgSlab / kLgThreads; ++it) {
+        const int e = threadIdx.x + kLgThreads * it;
         const int k = e / kLgSlab, c = e - k * kLgSlab;
-        float2 x = make_float2(0.f, 0.f);
-        if (k < K && c0 + c < M) x = X[(int64_t)k * M + c0 + c];
-        sX[k * kLgStride + c] = scale * x.x;
-        sX[(kLgMaxK + k) * kLgStride + c] = conj ? -(scale * x.y) : scale * x.y;
+        x[it] = (k < K && c0 + c < M) ? X[(int64_t)k * M + c0 + c] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < kLgMaxK * kLgSlab / kLgThreads; ++it) {
+        const int e = threadIdx.x + kLgThreads * it;
+        const int k = e / kLgSlab, c = e - k * kLgSlab;
+        sX[k * kLgStride + c] = scale * x[it].x;
+        sX[(kLgMaxK + k) * kLgStride + c] = conj ? -(scale * x[it].y) : scale * x[it].y;
     }
 }
 
@@ -131,7 +141,8 @@ __global__ __launch_bounds__(64) void lg_reduce_kernel(LgDev a, int par) {
     const int i1 = ra * kLgRows + (same ? cb : 32 + cb);
     const int i2 = (32 + ra) * kLgRows + (same ? 32 + cb : cb);
     float x = 0.f, y = 0.f;
-    for (int sl = 0; sl < a.S; ++sl) {
+#pragma unroll 8
+    for (int sl = 0; sl < a.S; ++sl) {   // loads issued together, sums in slab order
         x += p0[(int64_t)sl * kLgPart + i1];
         y += p0[(int64_t)sl * kLgPart + i2];
     }
@@ -160,6 +171,7 @@ __global__ __launch_bounds__(256) void lg_layer_kernel(LgDev a, int layer, int p
     lg_load_slab(sW, Wb, a.K, a.M, c0, 1.0f, false);
     {
         const float4* Eb = reinterpret_cast<const float4*>(a.E + b * kLgPart);
+#pragma unroll
         for (int e = tid; e < kLgPart / 4; e += 256) {
             const int row = e >> 4, c4 = e & 15;
             *reinterpret_cast<float4*>(sE + row * kLgStride + 4 * c4) = Eb[e];
@@ -227,6 +239,7 @@ __global__ __launch_bounds__(256) void lg_final_kernel(LgDev a, int par) {
     for (int e = tid; e < K * K; e += 256) {
         const int k = e / K, j = e - k * K;
         float re = 0.f, im = 0.f;
+#pragma unroll 8
         for (int sl = 0; sl < a.S; ++sl) {
             const float* q = p0 + (int64_t)sl * kLgPart;
             re += q[j * kLgRows + k] - q[(32 + j) * kLgRows + 32 + k];
@@ -253,10 +266,17 @@ __global__ __launch_bounds__(256) void lg_final_kernel(LgDev a, int par) {
     double l = 0.0;
     for (int m = tid; m < M; m += 256) {
         double p = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const float2 w = Wb[(int64_t)k * M + m];
-            p += (double)w.x * w.x + (double)w.y * w.y;
-            Wb[(int64_t)k * M + m] = make_float2(wsf * w.x, wsf * w.y);
+        float2 wv[kLgMaxK];   // all K loads of the antenna issued together
+#pragma unroll
+        for (int k = 0; k < kLgMaxK; ++k)
+            if (k < K) wv[k] = Wb[(int64_t)k * M + m];
+#pragma unroll
+        for (int k = 0; k < kLgMaxK; ++k) {
+            if (k < K) {
+                const float2 w = wv[k];
+                p += (double)w.x * w.x + (double)w.y * w.y;
+                Wb[(int64_t)k * M + m] = make_float2(wsf * w.x, wsf * w.y);
+            }
         }
         if (a.p_ant) a.p_ant[b * M + m] = ws * ws * p;
         l += sqrt(p);
