@@ -446,14 +446,14 @@ __global__ __launch_bounds__(64 * NW) void pgd_mfma_kernel(PgdDev a) {
     const float2* Hb = a.H + b * K * M;
     const PgdScale cs = pgd_scale(a, b);
 
-    load_planar(sX, stride, AW * NW, Hb, K, M, false, cs.hs);
+    load_planar<AW / 8>(sX, stride, AW * NW, Hb, K, M, false, cs.hs);
     __syncthreads();
     float HA[AW / 4], HB[NQ][4];
     read_op_a(sX, stride, L, HA);
     read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    if (a.W0) load_planar(sX, stride, AW * NW, a.W0 + b * K * M, K, M, false, 1.0f);
-    else load_planar(sX, stride, AW * NW, Hb, K, M, true, cs.hs);         // W(0) = H^*
+    if (a.W0) load_planar<AW / 8>(sX, stride, AW * NW, a.W0 + b * K * M, K, M, false, 1.0f);
+    else load_planar<AW / 8>(sX, stride, AW * NW, Hb, K, M, true, cs.hs);         // W(0) = H^*
     __syncthreads();
     float WD[NQ][4], WA[AW / 4];
     read_out_d(sX, stride, L, WD);
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(64 * NW) void pgd_x3_kernel(PgdDev a) {
     const float2* Hb = a.H + b * K * M;
     const PgdScale cs = pgd_scale(a, b);
 
-    load_planar(sX, stride, 64 * NW, Hb, K, M, false, cs.hs);
+    load_planar<8>(sX, stride, 64 * NW, Hb, K, M, false, cs.hs);
     __syncthreads();
     u32x4 HAh[2], HAl[2];
     {
@@ -601,8 +601,8 @@ __global__ __launch_bounds__(64 * NW) void pgd_x3_kernel(PgdDev a) {
         split_x4(h, HBh[q], HBl[q]);
     }
     __syncthreads();
-    if (a.W0) load_planar(sX, stride, 64 * NW, a.W0 + b * K * M, K, M, false, 1.0f);
-    else load_planar(sX, stride, 64 * NW, Hb, K, M, true, cs.hs);         // W(0) = H^*
+    if (a.W0) load_planar<8>(sX, stride, 64 * NW, a.W0 + b * K * M, K, M, false, 1.0f);
+    else load_planar<8>(sX, stride, 64 * NW, Hb, K, M, true, cs.hs);         // W(0) = H^*
     __syncthreads();
     float WD[4][4], WA[16];
     read_out_d<64>(sX, stride, L, WD);

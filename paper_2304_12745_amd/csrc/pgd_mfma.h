@@ -54,14 +54,29 @@ struct PgdLane {
 
 // scale * X (K x M, complex64, row-major) into the planar image, zero padded
 // to 8 x ncol, optionally conjugated.  All threads of the block take part.
+// IT = 8 ncol / blockDim.x iterations per thread, a compile-time count so
+// that all of a thread's loads are issued before its LDS stores.
+template <int IT>
 __device__ __forceinline__ void load_planar(float* sX, int stride, int ncol, const float2* X, int K,
                                             int M, bool conj, float scale = 1.0f) {
-    for (int e = threadIdx.x; e < 8 * ncol; e += blockDim.x) {
+    float vx[IT], vy[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + blockDim.x * it;
         const int k = e / ncol, m = e - k * ncol;
         float2 x = make_float2(0.f, 0.f);
-        if (k < K && m < M) x = X[k * M + m];
-        sX[k * stride + m] = scale * x.x;
-        sX[(8 + k) * stride + m] = conj ? -(scale * x.y) : scale * x.y;
+        if (e < 8 * ncol && k < K && m < M) x = X[k * M + m];
+        vx[it] = x.x;
+        vy[it] = x.y;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + blockDim.x * it;
+        const int k = e / ncol, m = e - k * ncol;
+        if (e < 8 * ncol) {
+            sX[k * stride + m] = scale * vx[it];
+            sX[(8 + k) * stride + m] = conj ? -(scale * vy[it]) : scale * vy[it];
+        }
     }
 }
 

@@ -76,13 +76,13 @@ __global__ __launch_bounds__(64 * NW) void ufpgd_grad_kernel(UfpgdDev a) {
     const float2* Hb = a.H + ch * K * M;
     const bool grad = a.tapeV != nullptr;
 
-    load_planar(sX, stride, AW * nw, Hb, K, M, false);
+    load_planar<AW / 8>(sX, stride, AW * nw, Hb, K, M, false);
     __syncthreads();
     float HA[AW / 4], HB[NQ][4];
     read_op_a(sX, stride, L, HA);
     read_op_b2(sX, stride, L, HB);
     __syncthreads();
-    load_planar(sX, stride, AW * nw, Hb, K, M, true);  // W(0) = H^*
+    load_planar<AW / 8>(sX, stride, AW * nw, Hb, K, M, true);  // W(0) = H^*
     __syncthreads();
     float WD[NQ][4], WA[AW / 4];
     read_out_d(sX, stride, L, WD);
