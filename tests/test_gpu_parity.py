@@ -152,6 +152,29 @@ def test_channel_wide_rows(D, M, B, kind):
             assert e <= tol, (prec, b, e)
 
 
+# the materialised channels bench.py times, in the same launch configuration:
+# the room's 512 x 512 grid x 64 APs (four antennas per lane) and the hall's
+# 2048 x 2048 grid x 1024 APs (34.4 GB; antenna coordinates in LDS); sampled
+# rows against the oracle
+@pytest.mark.parametrize("name", ["room", "hall"])
+def test_channel_bench_configuration_sampled(D, name):
+    import torch
+    say(f"channel materialised, bench configuration: {name}")
+    w = WL.room_workload() if name == "room" else WL.hall_workload()
+    g, M = w.grid, w.M
+    H = D.channel(D.channel_params(w.freq_hz), dev(w.ap_xyz), D.grid_points(g), prec="f32")
+    assert tuple(H.shape) == (1, g.n, M)
+    rng = np.random.default_rng(77)
+    rows = np.concatenate([[0, g.n - 1, g.nx - 1, g.nx], rng.choice(g.n, 300, replace=False)])
+    Hs = H[0][torch.from_numpy(rows).to(H.device)].cpu().numpy()
+    del H
+    torch.cuda.empty_cache()
+    ref = O.los_channel(grid_pts(g)[rows], w.ap_xyz[0], w.freq_hz)
+    e = np.max(np.abs(Hs - ref) / np.abs(ref))
+    say(f"    max |dh|/|h| over {rows.size} rows: {e:.2e}")
+    assert e <= 2e-6
+
+
 def test_channel_los_list_batched(D):
     say("channel LoS list, B=3")
     rng = np.random.default_rng(7)
