@@ -368,6 +368,17 @@ def test_beamform_wide_zf(D, B, K, M, prec):
     _check_beamform(D, Hin, "zf", None, 0.5, 1.0, prec, tol[0], tol[1])
 
 
+def test_beamform_hall_zf_wide_path(D):
+    # the hall's 32 users and 1024 APs (LoS, |h| ~ 1e-3) with the paper's
+    # scaling at 10 dB targets, as the PA phase of bench.py forms it
+    say("beamform ZF, hall deployment (wide path)")
+    w = WL.hall_workload()
+    H = c64(O.los_channel(w.user_xyz[0], w.ap_xyz[0], w.freq_hz)[None])
+    r = _check_beamform(D, H, "zf", np.full(w.K, 10.0), w.sigma2, 0.0, "f32", 0.01, 1e-4)
+    sinr_db = 10 * np.log10(host(r.sinr)[0])
+    assert np.all(np.abs(sinr_db - 10.0) < 0.01)
+
+
 def test_beamform_wide_singular_deployment_is_isolated(D):
     say("beamform ZF wide path, singular deployment")
     rng = np.random.default_rng(33)
