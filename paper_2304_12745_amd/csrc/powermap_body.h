@@ -136,7 +136,7 @@ __device__ __forceinline__ void f32_steps(const PmMapDev& a, int steps, int grp,
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
                 const double dx = px[t] - ax;
-                wave_term_rev_d2(fma(dx, dx, c), a.amp_rev, a.inv_dmin_rev, hr[t], hi[t]);
+                wave_term_rev_d2(fma(dx, dx, c), 1.0f, a.inv_dmin_rev, hr[t], hi[t]);
             }
         } else {
             const double ax = s_ap[mm * 3 + 0];
@@ -144,7 +144,7 @@ __device__ __forceinline__ void f32_steps(const PmMapDev& a, int steps, int grp,
             const double az = s_ap[mm * 3 + 2];
 #pragma unroll
             for (int t = 0; t < PT; ++t)
-                wave_term_rev(px[t] - ax, py[t] - ay, pz[t] - az, a.amp_rev, a.inv_dmin_rev, hr[t],
+                wave_term_rev(px[t] - ax, py[t] - ay, pz[t] - az, 1.0f, a.inv_dmin_rev, hr[t],
                               hi[t]);
         }
 #pragma unroll
@@ -234,7 +234,12 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
             int k, part;
             column_stream<NT>(q, j, k, part);
             float2 w = make_float2(0.f, 0.f);
-            if (k < K && mm < mc) w = a.W[(int64_t)k * M + m0 + mm];
+            if (k < K && mm < mc) {
+                // the constant amplitude factor 1 / (4 pi) rides on W (the sums
+                // are linear in it), so a term's amplitude is min(1/d, 1/d_min)
+                w = a.W[(int64_t)k * M + m0 + mm];
+                w = make_float2(a.amp_rev * w.x, a.amp_rev * w.y);
+            }
             s_b[mm * BS + q * 32 + j] = b_value(w, part, false);
             s_b[mm * BS + q * 32 + 16 + j] = b_value(w, part, true);
         }
