@@ -117,6 +117,10 @@ def parse_args():
     p.add_argument("--no-pa", action="store_true", help="skip the PA-aware precoder phase")
     p.add_argument("--no-channel", action="store_true",
                    help="skip the materialised-channel bandwidth phase")
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the batched Gram + ZF sweep over B")
+    p.add_argument("--serve-sweep", action="store_true",
+                   help="also serve at 500, 1000, 2000 and 4000 queries/s (3 s each)")
     return p.parse_args()
 
 
@@ -232,8 +236,19 @@ def main():
         out["mixed"] = mixed
     if not args.no_channel:
         out["channel"] = channel_phase(D, WL, torch, params, ap, gpts, N)
+    if not args.no_batched:
+        out["batched"] = batched_phase(D, torch)
     if args.serve_seconds > 0:
         out["serving"] = serving_phase(args, D, WL, torch)
+    if args.serve_sweep:
+        sweep = []
+        for rate in (500.0, 1000.0, 2000.0, 4000.0):
+            a2 = argparse.Namespace(**vars(args))
+            a2.serve_rate, a2.serve_seconds = rate, 3.0
+            r = serving_phase(a2, D, WL, torch)
+            sweep.append({k: r[k] for k in ("rate_qps", "queries", "p50_ms", "p99_ms", "max_ms",
+                                            "sustained_Gh_per_s", "offered_Gh_per_s")})
+        out["serving_sweep"] = sweep
     if not args.no_pgd:
         out["pgd"] = pgd_phase(args, D, WL, torch)
     if not args.no_pa:
@@ -326,6 +341,46 @@ def channel_phase(D, WL, torch, params, ap, gpts, N):
     out["workload"] = ("room: 512 x 512 grid x 64 APs (16.8 M terms); hall: 2048 x 2048 grid x "
                        "1024 APs (4.29 G terms); LoS, output H [N][M] in HBM")
     return out
+
+
+def batched_phase(D, torch):
+    """Batched Gram + ZF (dmimo_beamform at 1 W, -90 dBm) on B deployments of
+    K = 16 users and M = 256 antennas, B = 2^10 .. 2^17, with the FP32 and
+    the FP16x3 Gram.  The cost does not depend on the channel values, so H is
+    CN(0,1), drawn on the device by torch with a fixed seed.  Units: B K M
+    terms per call; time from HIP events around back-to-back calls."""
+    K, M = 16, 256
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    bmax = 1 << 17
+    H = torch.complex(torch.randn(bmax, K, M, generator=gen, device="cuda"),
+                      torch.randn(bmax, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
+    sweep = []
+    for prec in ("f32", "f16x3"):
+        for e in (10, 12, 14, 16, 17):
+            B = 1 << e
+            Hb = H[:B]
+            r = D.beamform(Hb, "zf", None, 1e-12, 1.0, prec)
+            reps = 20 if B <= 1 << 14 else 5
+            for _ in range(2):
+                D.beamform(Hb, "zf", None, 1e-12, 1.0, prec, out=r)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                D.beamform(Hb, "zf", None, 1e-12, 1.0, prec, out=r)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            sweep.append({"B": B, "prec": prec, "ms": round(ms, 4),
+                          "deployments_per_s": round(B / ms * 1e3, 1),
+                          "G_h_per_s": round(B * K * M / ms / 1e6, 2)})
+            del r
+    del H
+    torch.cuda.empty_cache()
+    return {"workload": "batched ZF: B deployments x K=16 users x M=256 antennas, H ~ CN(0,1) "
+                        "(device draws), total power 1 W, noise -90 dBm; Gram + inverse + W + epilogues",
+            "sweep": sweep}
 
 
 def serving_phase(args, D, WL, torch):
