@@ -327,6 +327,40 @@ def test_beamform_batched_rician_zf(D, prec):
                     1e-4 if prec != "bf16x3" else 1e-2)
 
 
+# the batched sweep of bench.py: B deployments of K = 16, M = 256 with H drawn
+# on the device (the same seeded draw), ZF at 1 W; sampled deployments against
+# the oracle.  The noise is sigma2 = 1 here (the launch is the same): at the
+# sweep's -90 dBm with unit channels the SINR would measure the FP32 rounding
+# interference of W, not the precoder.
+@pytest.mark.parametrize("B,prec", [(1024, "f32"), (131072, "f32"), (131072, "f16x3")])
+def test_beamform_batched_sweep_configuration_sampled(D, B, prec):
+    import torch
+    say(f"beamform ZF, batched sweep configuration B={B} prec={prec}")
+    K, M = 16, 256
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    bmax = 1 << 17
+    H = torch.complex(torch.randn(bmax, K, M, generator=gen, device="cuda"),
+                      torch.randn(bmax, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
+    Hb = H[:B]
+    r = D.beamform(Hb, "zf", None, 1.0, 1.0, prec)
+    rng = np.random.default_rng(B)
+    pick = np.concatenate([[0, B - 1], rng.choice(B, 14, replace=False)])
+    idx = torch.from_numpy(pick).to(H.device)
+    Hs = Hb[idx].cpu().numpy().astype(np.complex128)
+    W = r.W[idx].cpu().numpy()
+    sinr = r.sinr[idx].cpu().numpy()
+    assert not np.any(r.info[idx].cpu().numpy())
+    del H, Hb, r
+    torch.cuda.empty_cache()
+    Wr, sing = O.zf_precoder(Hs, None, 1.0, 1.0)
+    assert not sing.any()
+    ew = np.max(np.linalg.norm(W - Wr, axis=(1, 2)) / np.linalg.norm(Wr, axis=(1, 2)))
+    es = np.max(np.abs(10 * np.log10(sinr / O.user_sinr(Hs, Wr, 1.0))))
+    say(f"    W rel err {ew:.2e}, SINR max dB err {es:.2e}")
+    assert ew <= 1e-4 and es <= MAP_TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 def test_beamform_paper_zf_mixed(D, prec):
     # K <= 8 and M <= 256: G is formed in FP64 inside the one-pass kernel in
