@@ -218,6 +218,28 @@ def test_channel_near_field_clamp(D):
     assert abs(H[0, 0, 0]) == pytest.approx(1.0, rel=1e-12)
 
 
+# the FP64 phase at every fraction of a turn: one antenna, points on a line at
+# distances lambda (1 + i/4096) and next to each eighth of a turn.  With fewer
+# than two revolutions the oracle's own phase rounding stays near 3e-15, so the
+# sine and cosine of the fractional revolution are held to 2e-14 here (the
+# other FP64 channel tests allow 1e-11 for distances of thousands of turns).
+def test_channel_f64_phase_every_fraction(D):
+    say("channel FP64 phase over one turn")
+    f = 3.5e9
+    lam = O.wavelength(f)
+    frac = np.arange(4096) / 4096.0
+    edges = np.arange(1, 17) / 8.0
+    frac = np.concatenate([frac, np.nextafter(edges, 0.0) - 1.0, np.nextafter(edges, 3.0) - 1.0])
+    d = lam * (1.0 + frac)
+    pts = np.stack([d, np.zeros_like(d), np.zeros_like(d)], axis=1)[None]
+    aps = np.zeros((1, 1, 3))
+    H = host(D.channel(D.channel_params(f), dev(aps), D.list_points(dev(pts), d.size), prec="f64"))
+    ref = O.los_channel(pts[0], aps[0], f)
+    e = np.max(np.abs(H[0] - ref) / np.abs(ref))
+    say(f"    max |dh|/|h| over {d.size} fractions: {e:.2e}")
+    assert e <= 2e-14
+
+
 # ---------------------------------------------------------------------------
 # dmimo_gram
 # ---------------------------------------------------------------------------
