@@ -139,7 +139,8 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *             every mode (the MIX modes then equal DMIMO_F32 bit for bit).
  *             ZF calls of at most 64 deployments with at least 8 tiles of 64
  *             antennas (M > 448) also form G in FP64, from per-tile sums
- *             computed in parallel workgroups and added in tile order.
+ *             computed in parallel workgroups and added in tile order (MR
+ *             calls of that shape sum ||H||_F^2 the same way).
  * Outputs (device; any may be NULL except W):
  *   W      [B][K][M] precoder, same complex type as H.
  *   p_ant  FP64 [B][M]  per-antenna power p_m = sum_k |w_km|^2.
@@ -154,7 +155,12 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *                       p_ant, l21, sinr and rsum are zero for that deployment.
  *   ws, ws_bytes  device workspace of at least
  *                 dmimo_workspace_size(DMIMO_CALL_BEAMFORM_ZF, B, K, M, 0, prec) bytes
- *                 (ZF; MR needs none and accepts NULL). */
+ *                 for ZF, or of dmimo_workspace_size(DMIMO_CALL_BEAMFORM_MR, ...)
+ *                 for MR and equal-gain MR.  The MR size is 0 (NULL accepted)
+ *                 except for calls of at most 64 deployments with M > 448, which
+ *                 spread each deployment over parallel workgroups of 64 antennas
+ *                 and keep per-tile shares there.  A smaller workspace returns
+ *                 DMIMO_E_WORKSPACE. */
 dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
                             const void* H, const double* gamma_lin, double sigma2,
                             double p_total, int32_t prec, void* W, double* p_ant,

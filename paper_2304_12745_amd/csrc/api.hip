@@ -155,7 +155,9 @@ size_t dmimo_workspace_size(int32_t call, int32_t B, int32_t K, int32_t M, int32
     if (B <= 0 || K <= 0) return 0;
     switch (call) {
         case DMIMO_CALL_BEAMFORM_ZF:
-            return beamform_zf_workspace_bytes(B, K, M, prec);
+            return beamform_workspace_bytes(DMIMO_ZF, B, K, M, prec);
+        case DMIMO_CALL_BEAMFORM_MR:
+            return beamform_workspace_bytes(DMIMO_MR, B, K, M, prec);
         case DMIMO_CALL_PA_PRECODER: {
             if (K > 32 || M < 1 || M > 4096) return 0;
             const size_t f = align256((size_t)B * 2 * sizeof(double));
@@ -225,9 +227,8 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, c
         if (!(gam[k] >= 0.0) || !std::isfinite(gam[k]))
             return fail(DMIMO_E_ARG, "beamform: gamma_lin must be finite and >= 0");
     }
-    const size_t need = precoder == DMIMO_ZF
-                            ? dmimo_workspace_size(DMIMO_CALL_BEAMFORM_ZF, B, K, M, 0, prec)
-                            : 0;
+    const size_t need = dmimo_workspace_size(
+        precoder == DMIMO_ZF ? DMIMO_CALL_BEAMFORM_ZF : DMIMO_CALL_BEAMFORM_MR, B, K, M, 0, prec);
     if (B == 0) return DMIMO_OK;
     if (!H || !W) return fail(DMIMO_E_ARG, "beamform: NULL H or W");
     if (need > 0 && (!ws || ws_bytes < need)) {

@@ -419,18 +419,22 @@ __global__ __launch_bounds__(kThreads) void beamform_kernel(BfDev a) {
 }
 
 // ---------------------------------------------------------------------------
-// ZF of few deployments with many antennas (B <= kWideMaxB, at least
-// kWideMinTiles tiles of 64 antennas), every step spread over the tiles:
-//   bfw_gram_kernel   per (tile, deployment): the tile's share of G, FP64;
-//   bfw_prep_kernel   per deployment: G = the shares summed in tile order
+// Few deployments with many antennas (B <= kWideMaxB, at least kWideMinTiles
+// tiles of 64 antennas), every step spread over the tiles:
+//   bfw_gram_kernel   ZF, per (tile, deployment): the tile's share of G, FP64;
+//   bfw_prep_kernel   ZF, per deployment: G = the shares summed in tile order
 //                     (FP64 in every mode), inverted by Gauss-Jordan;
-//   bfw_tile_kernel   per (tile, deployment): W, p_m and the tile's share of
-//                     the gains A = H W^T;
+//   bfw_norm_kernel   MR with p_total > 0, per (tile, deployment): the tile's
+//                     share of ||H||_F^2;
+//   bfw_tile_kernel   per (tile, deployment): the scale (MR: from the norm
+//                     shares in tile order, the same bits in every tile), W,
+//                     p_m and the tile's share of the gains A = H W^T;
 //   bfw_final_kernel  per deployment: the shares summed in tile order, SINR,
 //                     sum rate, ||W||_{2,1}.
-// Workspace after the Gram slot: G^-1 [B][K][K] and scale [B][K] (FP64), the
-// failed pivot [B], tile shares [B][T][K][K] (FP64: first of G, then of the
-// gains) and sqrt(p_m) sums [B][T].
+// Workspace: ZF first holds the Gram slot, G^-1 [B][K][K] and scale [B][K]
+// (FP64) and the failed pivot [B]; then, for every precoder, tile shares
+// [B][T][K][K] (FP64; ZF: first of G, then of the gains) and sqrt(p_m) sums
+// [B][T]; MR and equal-gain MR end with the ||H||_F^2 shares [B][T].
 // ---------------------------------------------------------------------------
 constexpr int64_t kWideMaxB = 64;
 constexpr int64_t kWideMinTiles = 8;
@@ -441,8 +445,44 @@ struct BfWide {
     int32_t* fail;
     double2* gpart;
     double* lpart;
+    double* npart;
     int64_t T;
 };
+
+// The tile's share of ||H||_F^2: each thread's staged values in a fixed order,
+// then the block sum.
+template <typename T2, int KT>
+__global__ __launch_bounds__(kThreads) void bfw_norm_kernel(BfDev a, BfWide wd) {
+    __shared__ double red[kThreads / 64];
+    using S = typename Scalar<T2>::type;
+    constexpr int IT = KT * kCols / kThreads;
+    const int64_t t = blockIdx.x, b = blockIdx.y;
+    const int K = a.K;
+    const int64_t M = a.M, m0 = t * kCols;
+    const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
+    const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
+    S vx[IT], vy[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + kThreads * it;
+        const int k = e / kCols, c = e - k * kCols;
+        vx[it] = 0;
+        vy[it] = 0;
+        if (k < K && c < mc) {
+            const T2 v = Hb[(int64_t)k * M + m0 + c];
+            vx[it] = v.x;
+            vy[it] = v.y;
+        }
+    }
+    double f = 0.0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const double x = vx[it], y = vy[it];
+        f += x * x + y * y;
+    }
+    f = block_sum(f, red);
+    if (threadIdx.x == 0) wd.npart[b * wd.T + t] = f;
+}
 
 // The tile's share of G = H H^H, FP64 sums, in the gain-share slot of the
 // workspace (consumed by bfw_prep_kernel before the tiles overwrite it).
@@ -534,14 +574,28 @@ __global__ __launch_bounds__(kThreads) void bfw_tile_kernel(BfDev a, BfWide wd) 
     const int K = a.K, tid = threadIdx.x;
     const int64_t M = a.M, m0 = t * kCols;
     const int mc = (int)(M - m0 < kCols ? M - m0 : kCols);
-    const int fail = wd.fail[b];
+    const bool zf = a.precoder == DMIMO_ZF;
+    const int fail = zf ? wd.fail[b] : 0;
     if (fail) {
         zf_failed<T2>(a, b, fail, m0, m0 + mc, false);
         return;
     }
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
-    for (int e = tid; e < K * K; e += kThreads) ginv[e / K][e - (e / K) * K] = wd.ginv[b * K * K + e];
-    if (tid < K) scale[tid] = wd.scale[b * K + tid];
+    if (zf) {
+        for (int e = tid; e < K * K; e += kThreads) ginv[e / K][e - (e / K) * K] = wd.ginv[b * K * K + e];
+        if (tid < K) scale[tid] = wd.scale[b * K + tid];
+    } else if (a.precoder == DMIMO_MR && a.p_total > 0.0) {
+        // ||H||_F^2 from the tiles' shares: a fixed order, so every tile of
+        // the deployment gets the same scale
+        double f = 0.0;
+        for (int64_t i = tid; i < wd.T; i += kThreads) f += wd.npart[b * wd.T + i];
+        f = block_sum(f, red);
+        if (tid < K) scale[tid] = sqrt(a.p_total) / sqrt(f);
+    } else if (tid < K) {
+        scale[tid] = a.precoder == DMIMO_MR_PHASE && a.p_total > 0.0
+                         ? sqrt(a.p_total / ((double)K * (double)M))
+                         : 1.0;
+    }
     stage_tile<T2, KT>(Hb, K, M, m0, mc, h);
     __syncthreads();
     const TileRoles<KT> R;
@@ -572,7 +626,7 @@ __global__ __launch_bounds__(kThreads) void bfw_final_kernel(BfDev a, BfWide wd)
     __shared__ double red[kThreads / 64];
     const int64_t b = blockIdx.x;
     const int K = a.K, tid = threadIdx.x;
-    const int fail = wd.fail[b];
+    const int fail = a.precoder == DMIMO_ZF ? wd.fail[b] : 0;
     if (fail) {
         if (a.sinr)
             for (int k = tid; k < K; k += kThreads) a.sinr[b * K + k] = 0.0;
@@ -838,39 +892,71 @@ dmimo_status launch_typed(const BfDev& d, int64_t B, hipStream_t s) {
 
 size_t ws_align(size_t n) { return (n + 255) & ~(size_t)255; }
 
-bool zf_wide(int64_t B, int64_t M) {
+bool wide_shape(int64_t B, int64_t M) {
     return B <= kWideMaxB && (M + kCols - 1) / kCols >= kWideMinTiles;
+}
+
+// Byte offsets of the wide path's workspace (layout above bfw_norm_kernel);
+// MR and equal-gain MR share one layout.
+struct WideLayout {
+    size_t ginv = 0, scale = 0, fail = 0, gpart = 0, lpart = 0, npart = 0, total = 0;
+};
+
+WideLayout wide_layout(int precoder, int64_t B, int K, int64_t M, int prec) {
+    const int64_t T = (M + kCols - 1) / kCols;
+    WideLayout L;
+    size_t n = 0;
+    if (precoder == DMIMO_ZF) {
+        n = ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8));   // Gram slot
+        L.ginv = n;
+        n += ws_align((size_t)B * K * K * sizeof(double2));
+        L.scale = n;
+        n += ws_align((size_t)B * K * sizeof(double));
+        L.fail = n;
+        n += ws_align((size_t)B * sizeof(int32_t));
+    }
+    L.gpart = n;
+    n += ws_align((size_t)B * T * K * K * sizeof(double2));
+    L.lpart = n;
+    n += ws_align((size_t)B * T * sizeof(double));
+    if (precoder != DMIMO_ZF) {
+        L.npart = n;
+        n += ws_align((size_t)B * T * sizeof(double));
+    }
+    L.total = n;
+    return L;
 }
 
 template <typename T2, int KT>
 void launch_wide_kt(const BfDev& d, const BfWide& wd, int64_t B, hipStream_t s) {
-    bfw_gram_kernel<T2, KT><<<dim3((unsigned)wd.T, (unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
-    bfw_prep_kernel<KT><<<dim3((unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
-    bfw_tile_kernel<T2, KT><<<dim3((unsigned)wd.T, (unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
-    bfw_final_kernel<KT><<<dim3((unsigned)B), dim3(kThreads), 0, s>>>(d, wd);
+    const dim3 tiles((unsigned)wd.T, (unsigned)B), one((unsigned)B), block(kThreads);
+    if (d.precoder == DMIMO_ZF) {
+        bfw_gram_kernel<T2, KT><<<tiles, block, 0, s>>>(d, wd);
+        bfw_prep_kernel<KT><<<one, block, 0, s>>>(d, wd);
+    } else if (d.precoder == DMIMO_MR && d.p_total > 0.0) {
+        bfw_norm_kernel<T2, KT><<<tiles, block, 0, s>>>(d, wd);
+    }
+    bfw_tile_kernel<T2, KT><<<tiles, block, 0, s>>>(d, wd);
+    bfw_final_kernel<KT><<<one, block, 0, s>>>(d, wd);
 }
 
 template <typename T2>
 dmimo_status launch_wide(const BfDev& d, int64_t B, int prec, hipStream_t s) {
     const int K = d.K;
-    const int64_t T = (d.M + kCols - 1) / kCols;
+    const WideLayout L = wide_layout(d.precoder == DMIMO_ZF ? DMIMO_ZF : DMIMO_MR, B, K, d.M, prec);
     char* p = static_cast<char*>(const_cast<void*>(d.G));
-    p += ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8));
     BfWide wd;
-    wd.T = T;
-    wd.ginv = reinterpret_cast<double2*>(p);
-    p += ws_align((size_t)B * K * K * sizeof(double2));
-    wd.scale = reinterpret_cast<double*>(p);
-    p += ws_align((size_t)B * K * sizeof(double));
-    wd.fail = reinterpret_cast<int32_t*>(p);
-    p += ws_align((size_t)B * sizeof(int32_t));
-    wd.gpart = reinterpret_cast<double2*>(p);
-    p += ws_align((size_t)B * T * K * K * sizeof(double2));
-    wd.lpart = reinterpret_cast<double*>(p);
+    wd.T = (d.M + kCols - 1) / kCols;
+    wd.ginv = d.precoder == DMIMO_ZF ? reinterpret_cast<double2*>(p + L.ginv) : nullptr;
+    wd.scale = d.precoder == DMIMO_ZF ? reinterpret_cast<double*>(p + L.scale) : nullptr;
+    wd.fail = d.precoder == DMIMO_ZF ? reinterpret_cast<int32_t*>(p + L.fail) : nullptr;
+    wd.gpart = reinterpret_cast<double2*>(p + L.gpart);
+    wd.lpart = reinterpret_cast<double*>(p + L.lpart);
+    wd.npart = d.precoder == DMIMO_ZF ? nullptr : reinterpret_cast<double*>(p + L.npart);
     if (K <= 8) launch_wide_kt<T2, 8>(d, wd, B, s);
     else if (K <= 16) launch_wide_kt<T2, 16>(d, wd, B, s);
     else launch_wide_kt<T2, 32>(d, wd, B, s);
-    return check_launch("beamform (wide ZF)");
+    return check_launch("beamform (wide path)");
 }
 
 // The one-pass kernel's antenna limit: LDS holds H and W, 8 x (MT + 1) each.
@@ -886,16 +972,11 @@ dmimo_status launch_small(const BfDev& d, int64_t B, hipStream_t s) {
 
 }  // namespace
 
-size_t beamform_zf_workspace_bytes(int64_t B, int K, int64_t M, int prec) {
-    size_t n = ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8));
-    if (!zf_wide(B, M) || (K <= kSmallK && M <= small_max_m(prec))) return n;
-    const int64_t T = (M + kCols - 1) / kCols;
-    n += ws_align((size_t)B * K * K * sizeof(double2));
-    n += ws_align((size_t)B * K * sizeof(double));
-    n += ws_align((size_t)B * sizeof(int32_t));
-    n += ws_align((size_t)B * T * K * K * sizeof(double2));
-    n += ws_align((size_t)B * T * sizeof(double));
-    return n;
+size_t beamform_workspace_bytes(int precoder, int64_t B, int K, int64_t M, int prec) {
+    const int layout = precoder == DMIMO_ZF ? DMIMO_ZF : DMIMO_MR;
+    if (!wide_shape(B, M) || (K <= kSmallK && M <= small_max_m(prec)))
+        return layout == DMIMO_ZF ? ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8)) : 0;
+    return wide_layout(layout, B, K, M, prec).total;
 }
 
 dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
@@ -924,9 +1005,9 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
         if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, s);
         return launch_small<float2, kSmallMaxM>(d, a.B, s);
     }
-    if (a.precoder == DMIMO_ZF && zf_wide(a.B, a.M)) {
-        // G from FP64 tile sums: the FP64 Gram's tolerance for FP64 input,
-        // the FP32 one otherwise
+    if (wide_shape(a.B, a.M)) {
+        // ZF: G from FP64 tile sums, so the FP64 Gram's tolerance for FP64
+        // input and the FP32 one otherwise
         d.pivot_tol = a.prec == DMIMO_F64 ? 1e-12 : 1e-6;
         if (a.prec == DMIMO_F64) return launch_wide<double2>(d, a.B, a.prec, s);
         return launch_wide<float2>(d, a.B, a.prec, s);

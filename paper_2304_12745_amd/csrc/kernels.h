@@ -32,9 +32,10 @@ struct BeamformArgs {
 };
 
 dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s);
-// Workspace of a ZF launch_beamform: the Gram, plus the wide path's G^-1 and
-// per-tile gain shares when it applies (few deployments, many antennas).
-size_t beamform_zf_workspace_bytes(int64_t B, int K, int64_t M, int prec);
+// Workspace of a launch_beamform call.  ZF: the Gram, plus the wide path's
+// G^-1 and per-tile shares when that path applies (few deployments, many
+// antennas).  MR and equal-gain MR: the wide path's per-tile shares, else 0.
+size_t beamform_workspace_bytes(int precoder, int64_t B, int K, int64_t M, int prec);
 
 struct PowermapArgs {
     WaveConst w;

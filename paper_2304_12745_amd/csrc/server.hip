@@ -241,7 +241,7 @@ bool ServerImpl::admit_one(Query* q) {
     const size_t users_b = align256((size_t)K * 3 * 8);
     const size_t h_b = align256((size_t)K * M * 8);
     const size_t w_b = align256((size_t)K * M * 8);
-    const size_t g_b = align256(beamform_zf_workspace_bytes(1, K, M, q->prec));
+    const size_t g_b = align256(beamform_workspace_bytes(q->precoder, 1, K, M, q->prec));
     const size_t pa_b = q->precoder == DMIMO_PA ? align256(2 * sizeof(double)) : 0;
     q->bytes = users_b + h_b + w_b + g_b + pa_b;
     if (in_use + q->footprint > budget) return false;
@@ -588,7 +588,7 @@ dmimo_status dmimo_server_submit(dmimo_server* srv, int32_t dep_id, int32_t K,
         q->sinr = sinr_out_dev;
         q->terms = P.n * (int64_t)M;
         const size_t scratch = align256((size_t)K * 24) + 2 * align256((size_t)K * M * 8) +
-                               align256(beamform_zf_workspace_bytes(1, K, M, prec)) +
+                               align256(beamform_workspace_bytes(precoder, 1, K, M, prec)) +
                                (precoder == DMIMO_PA ? align256(2 * sizeof(double)) : 0);
         q->footprint = scratch + (size_t)P.n * 4 * (sinr_out_dev ? 2 : 1);
         if (q->footprint > S.budget - S.geom_bytes) {

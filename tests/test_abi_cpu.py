@@ -53,6 +53,13 @@ def test_workspace_size(lib):
         a(B * K * K * 8) + a(B * K * K * 16) + a(B * K * 8) + a(B * 4) + a(B * T * K * K * 16) + a(B * T * 8))
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 65, K, M, 0, D.F32) == a(65 * K * K * 8)
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1, K, 448, 0, D.F32) == a(K * K * 8)
+    # MR and equal-gain MR: nothing, except on the wide path, where they take
+    # per-tile gain shares, sqrt(p_m) sums and ||H||_F^2 shares
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, B, K, M, 0, D.F32) == (
+        a(B * T * K * K * 16) + a(B * T * 8) + a(B * T * 8))
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, 65, K, M, 0, D.F32) == 0
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, 1, K, 448, 0, D.F32) == 0
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, 1, 8, 256, 0, D.F32) == 0
     assert lib.dmimo_workspace_size(D.CALL_POWERMAP, 1, 8, 64, 100, D.F32) == 0
 
 
@@ -104,6 +111,8 @@ def test_beamform_validation(lib):
     assert bf(H=None) == 1
     assert bf(ws_bytes=16) == 4              # workspace too small
     assert bf(ws=None) == 4
+    assert bf(precoder=D.MR, B=1, K=2, M=512, ws=None) == 4     # MR on the wide path
+    assert bf(precoder=D.MR_PHASE, B=1, K=2, M=512, ws_bytes=256) == 4
     assert bf(B=0) == 0                      # empty batch
     assert bf(B=-1) == 2
     g = (ctypes.c_double * 2)(1.0, -3.0)

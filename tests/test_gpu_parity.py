@@ -424,6 +424,31 @@ def test_beamform_wide_zf(D, B, K, M, prec):
     _check_beamform(D, Hin, "zf", None, 0.5, 1.0, prec, tol[0], tol[1])
 
 
+# MR and equal-gain MR of few deployments with many antennas take the same
+# wide path (MR: ||H||_F^2 from per-tile shares summed in tile order; no norm
+# for p_total <= 0 or equal gain); B = 65 and M = 448 fall outside it
+@pytest.mark.parametrize("precoder", ["mr", "mr_phase"])
+@pytest.mark.parametrize("B,K,M,prec", [(1, 32, 1024, "f32"), (3, 20, 700, "f64"), (1, 5, 449, "f32"),
+                                        (64, 8, 512, "f32"), (65, 8, 512, "f32"), (2, 12, 448, "f32"),
+                                        (1, 16, 4096, "f32"), (2, 3, 1000, "f16x3")])
+def test_beamform_wide_mr(D, precoder, B, K, M, prec):
+    say(f"beamform {precoder} wide B={B} K={K} M={M} prec={prec}")
+    rng = np.random.default_rng(B * K + M)
+    H = WL.complex_normal(rng, (B, K, M))
+    Hin = H if prec == "f64" else c64(H)
+    tol = (1e-8, 1e-12) if prec == "f64" else (0.01, 1e-6)
+    for p_total in (2.0, 0.0):
+        _check_beamform(D, Hin, precoder, None, 0.5, p_total, prec, tol[0], tol[1])
+
+
+def test_beamform_hall_mr_wide_path(D):
+    say("beamform MR, hall deployment (wide path)")
+    w = WL.hall_workload()
+    H = c64(O.los_channel(w.user_xyz[0], w.ap_xyz[0], w.freq_hz)[None])
+    r = _check_beamform(D, H, "mr", None, w.sigma2, 1.0, "f32", 0.01, 1e-6)
+    assert abs(float(np.sum(np.abs(host(r.W)) ** 2)) - 1.0) < 1e-5
+
+
 def test_beamform_hall_zf_wide_path(D):
     # the hall's 32 users and 1024 APs (LoS, |h| ~ 1e-3) with the paper's
     # scaling at 10 dB targets, as the PA phase of bench.py forms it
