@@ -121,7 +121,7 @@ constexpr int f32_lds_bytes() {
 // The antenna steps of one LDS chunk: each step synthesises PT terms per lane
 // (antenna 4 s + grp) and feeds them to the MFMAs.  ROW: slot 1 of s_ap holds
 // fma(dy, dy, dz * dz) of the workgroup's grid row.
-template <int NT, int PT, bool ROW>
+template <int NT, int PT, bool ROW, bool GUARD = true>
 __device__ __forceinline__ void f32_steps(const PmMapDev& a, int steps, int grp, int col,
                                           const double* s_ap, const float* s_b, const double (&px)[PT],
                                           const double (&py)[PT], const double (&pz)[PT],
@@ -136,7 +136,7 @@ __device__ __forceinline__ void f32_steps(const PmMapDev& a, int steps, int grp,
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
                 const double dx = px[t] - ax;
-                wave_term_rev_d2(fma(dx, dx, c), 1.0f, a.inv_dmin_rev, hr[t], hi[t]);
+                wave_term_rev_d2<GUARD>(fma(dx, dx, c), 1.0f, a.inv_dmin_rev, hr[t], hi[t]);
             }
         } else {
             const double ax = s_ap[mm * 3 + 0];
@@ -195,9 +195,18 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
     // When every point of the workgroup lies on one grid row, y and z are the
     // same for all of them, so fma(dy, dy, dz * dz) is formed once per antenna
     // (slot 1 of s_ap) and a term needs only dx: d2 = fma(dx, dx, C), the
-    // same bits as the general path.
+    // same bits as the general path.  A chunk whose antennas all have
+    // C >= 1.001 d_min^2 (every antenna off the row by more than d_min, as
+    // for a map plane below ceiling access points) gives d2 >= C for every
+    // term, so it runs without the zero guard and the near-field clamp (K <= 8,
+    // where the synthesis bounds the kernel; wider kernels are MFMA-heavy and
+    // keep one loop).
+    // Padding slots take C = 1 (wavelengths squared, far above d_min^2) and
+    // multiply zero weights.
     bool row = false;
     double ry = 0.0, rz = 0.0;
+    const double dmin_rev = 1.0 / (double)a.inv_dmin_rev;
+    const double far_c = 1.001 * dmin_rev * dmin_rev;
     if (a.P.kind == DMIMO_PTS_GRID) {
         const int64_t last = min(wg_first + (int64_t)16 * PT * WAVES, N) - 1;
         row = wg_first / a.P.nx == last / a.P.nx;
@@ -210,7 +219,7 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
         __syncthreads();
         if (row) {
             for (int mm = tid; mm < kChunk; mm += NTH) {
-                double ax = 0.0, c = 0.0;
+                double ax = 0.0, c = 1.0;
                 if (mm < mc) {
                     const double* q = a.ap + (int64_t)(m0 + mm) * 3;
                     ax = q[0] * a.inv_lam;
@@ -245,7 +254,9 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
         }
         __syncthreads();
         const int steps = (mc + 3) >> 2;
-        if (row)
+        if (NT == 1 && row && __all(s_ap[lane * 3 + 1] >= far_c))
+            f32_steps<NT, PT, true, false>(a, steps, grp, col, s_ap, s_b, px, py, pz, acc);
+        else if (row)
             f32_steps<NT, PT, true>(a, steps, grp, col, s_ap, s_b, px, py, pz, acc);
         else
             f32_steps<NT, PT, false>(a, steps, grp, col, s_ap, s_b, px, py, pz, acc);

@@ -60,15 +60,20 @@ __device__ __forceinline__ void point_rev(const PmMapDev& a, int64_t n, double& 
 //   h  = amp * (cos 2 pi fr - j sin 2 pi fr), with amp = 1 / (4 pi max(d, d_min)).
 // The hardware sin / cos take revolutions directly.  `scale` multiplies the
 // amplitude (the FP16 split path uses it to place h in the FP16 range).
+// GUARD = false when the caller knows d2 >= 1.001 d_min^2: the zero guard of
+// the reciprocal square root and the near-field clamp then change no bit
+// (rs stays below 1 / d_min by far more than the instruction's one-ulp error)
+// and are left out.
+template <bool GUARD = true>
 __device__ __forceinline__ void wave_term_rev_d2(double d2, float amp_scaled, float inv_dmin_rev,
                                                  float& hr, float& hi) {
-    const float rs = __builtin_amdgcn_rsqf(fmaxf((float)d2, 1e-30f));
+    const float rs = __builtin_amdgcn_rsqf(GUARD ? fmaxf((float)d2, 1e-30f) : (float)d2);
     const double y = (double)rs;
     const double s0 = d2 * y;
     const double e = fma(-s0, s0, d2);
     const double d = fma(e, 0.5 * y, s0);
     const float fr = (float)__builtin_amdgcn_fract(d);
-    const float amp = amp_scaled * fminf(rs, inv_dmin_rev);
+    const float amp = amp_scaled * (GUARD ? fminf(rs, inv_dmin_rev) : rs);
     hr = amp * __builtin_amdgcn_cosf(fr);
     hi = -amp * __builtin_amdgcn_sinf(fr);
 }
