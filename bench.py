@@ -8,8 +8,8 @@ One step is one pass of the whole path, with inputs already resident in HBM:
   1. dmimo_channel   user channels H (K x M, complex64)
   2. dmimo_beamform  MR at 1 W                      (+ p_m, L2,1, SINR_k, R_sum)
   3. dmimo_beamform  ZF at 1 W: FP64 Gram and inverse (+ the same epilogues)
-  4. dmimo_powermap  MR power + SINR + best-stream maps, 512 x 512 grid at z = 1.2 m
-  5. dmimo_powermap  ZF power + SINR + best-stream maps, same grid
+  4. dmimo_powermap_batch  MR and ZF power + SINR + best-stream maps, 512 x 512
+                           grid at z = 1.2 m, both maps in one launch
 
 value = channel terms h[n,m] synthesised and consumed per second, over the
 whole step (K M for each of 1-3, N M for each map), in G h/s.
@@ -173,16 +173,17 @@ def main():
             keep = b > 1e-6 * b.max()     # the -60 dB floor of the error rule
             dev_db[p] = float((10 * torch.log10(a[keep] / b[keep])).abs().max())
         mixed = {"dtype": "f16x3 (FP16 hi/lo x3 MFMA, FP32 accumulate)",
-                 "ms_per_step": round(ms_mix, 5), "map_launch_ms": round(launch_mix, 5),
+                 "ms_per_step": round(ms_mix, 5), "maps_launch_ms": round(launch_mix, 5),
                  "speedup_vs_f32_step": round(ms_per_step / ms_mix, 3),
                  "max_db_vs_f32_maps": dev_db}
 
     terms_per_step = 3 * K * M + 2 * N * M
     value = terms_per_step / (ms_per_step * 1e-3) / 1e9
-    alg = alg_slots_per_term(K) * N * M
+    terms_per_launch = 2 * N * M          # both maps in one launch
+    alg = alg_slots_per_term(K) * terms_per_launch
     achieved = alg / (map_launch_ms * 1e-3) / 1e12
     peak = VALU_PEAK_SLOTS / 1e12
-    mfma_tflops = 8 * K * N * M / (map_launch_ms * 1e-3) / 1e12
+    mfma_tflops = 8 * K * terms_per_launch / (map_launch_ms * 1e-3) / 1e12
     khash = _src_hash(POWERMAP_SOURCES)
     traffic = load_traffic(khash)
 
@@ -207,14 +208,14 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "powermap_mfma_kernel<1,4,8>",
+            "kernel": "powermap_mfma_kernel<1,4,8>, grid 512 x 2 (MR and ZF maps in one launch)",
             "achieved": round(achieved, 3),
             "peak": round(peak, 3),
             "unit": "T VALU lane-slots/s",
             "frac": round(achieved / peak, 4),
             "traffic": traffic,
             "launch_ms": round(map_launch_ms, 5),
-            "event_samples": 2 * len(range(0, args.steps, max(1, args.event_every))),
+            "event_samples": len(range(0, args.steps, max(1, args.event_every))),
             "alg_slots_per_term": alg_slots_per_term(K),
             "mfma_f32": {"achieved": round(mfma_tflops, 3), "peak": MFMA_F32_PEAK / 1e12,
                          "unit": "TFLOP/s", "frac": round(mfma_tflops * 1e12 / MFMA_F32_PEAK, 4),
@@ -223,10 +224,11 @@ def main():
             # (SQ_VALU_MFMA_COEXEC_CYCLES = 0), so its floor is the sum of the
             # synthesis at the VALU peak and the contraction at the MFMA peak
             "serial_valu_mfma": {
-                "floor_ms": round((alg / VALU_PEAK_SLOTS + 8 * K * N * M / MFMA_F32_PEAK) * 1e3, 5),
-                "frac": round((alg / VALU_PEAK_SLOTS + 8 * K * N * M / MFMA_F32_PEAK) * 1e3
+                "floor_ms": round((alg / VALU_PEAK_SLOTS + 8 * K * terms_per_launch / MFMA_F32_PEAK)
+                                  * 1e3, 5),
+                "frac": round((alg / VALU_PEAK_SLOTS + 8 * K * terms_per_launch / MFMA_F32_PEAK) * 1e3
                               / map_launch_ms, 4)},
-            "terms_per_launch": N * M,
+            "terms_per_launch": terms_per_launch,
             "source_hash": khash,
         },
     }
@@ -262,22 +264,29 @@ def main():
 def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     """Warm up, then time exactly args.steps steps of the room workload.
 
-    One step, in order on torch's current stream: the user channel, MR and
-    ZF precoders (Gram and inverse inside), the MR map, the ZF map.  One
-    pair of HIP events on that stream brackets the two map launches of every
-    args.event_every-th timed step (a pair around each launch would add its
-    own dispatch gap to each; a pair on every step adds about 7 us per step).  (A variant with the MR
-    branch on a second stream was measured slower: 0.114 vs 0.094 ms/step,
-    because the cross-queue event waits cost more than the overlap saves.)
-    Returns (ms per step, mean map launch ms, maps, precoders).
+    One step, in order on torch's current stream: the user channel, the MR
+    and ZF precoders (Gram and inverse inside), written into one [2][K][M]
+    array, then the MR and ZF maps in one dmimo_powermap_batch launch (map p
+    on grid row p).  One pair of HIP events on that stream brackets the map
+    launch of every args.event_every-th timed step (a pair on every step
+    adds about 7 us per step).  (A variant with the MR branch on a second
+    stream was measured slower: 0.114 vs 0.094 ms/step, because the
+    cross-queue event waits cost more than the overlap saves.)
+    Returns (ms per step, mean ms of the two-map launch, maps per precoder,
+    precoders).
     """
     import torch
     K, M, N = w.K, w.M, w.grid.n
     dev = H.device
-    maps = {p: D.MapResult(torch.empty(N, device=dev), torch.empty(N, device=dev),
-                           torch.empty(N, dtype=torch.int32, device=dev), None)
-            for p in ("mr", "zf")}
-    bf = {p: D.beamform_outputs(1, K, M, prec, dev, precoder=p) for p in ("mr", "zf")}
+    Wst = torch.empty((2, K, M), dtype=torch.complex64, device=dev)
+    both = D.MapResult(torch.empty((2, N), device=dev), torch.empty((2, N), device=dev),
+                       torch.empty((2, N), dtype=torch.int32, device=dev), None)
+    maps = {p: D.MapResult(both.power[i], both.sinr[i], both.best_k[i], None)
+            for i, p in enumerate(("mr", "zf"))}
+    bf = {}
+    for i, p in enumerate(("mr", "zf")):
+        bf[p] = D.beamform_outputs(1, K, M, prec, dev, precoder=p)
+        bf[p].W = Wst[i:i + 1]
 
     def step(e=None):
         D.channel(params, ap, upts, prec="f32", out=H)
@@ -285,8 +294,7 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
         D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=bf["zf"])
         if e is not None:
             e[0].record()
-        for p in ("mr", "zf"):
-            D.powermap(params, ap0, bf[p].W[0], gpts, w.sigma2, prec, out=maps[p])
+        D.powermap_batch(params, ap0, Wst, gpts, w.sigma2, prec, out=both)
         if e is not None:
             e[1].record()
 
@@ -301,8 +309,7 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
         step(events.get(i))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    # one event pair brackets the two back-to-back map launches of a sampled step
-    launch = sum(e[0].elapsed_time(e[1]) for e in events.values()) / (2 * len(events))
+    launch = sum(e[0].elapsed_time(e[1]) for e in events.values()) / len(events)
     return ms, launch, maps, bf
 
 

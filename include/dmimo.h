@@ -186,6 +186,20 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M,
                             void* power, void* sinr, int32_t* best_k, void* per_stream,
                             void* stream);
 
+/* The maps of `maps` precoders of one deployment over the same points in one
+ * launch, as Sec. VI compares the coverage of several precoders (MR, ZF, the
+ * PA-aware one) on one room: map p is dmimo_powermap of W[p].  Saves the
+ * per-launch ramp and drain of every map after the first.
+ *   maps    0 <= maps <= 65535 (0: nothing to do).
+ *   W       device [maps][K][M] (complex128 for DMIMO_F64, else complex64).
+ *   power, sinr, best_k  device [maps][N]; per_stream [maps][N][K].
+ *   Every other argument, and every output value, as for dmimo_powermap. */
+dmimo_status dmimo_powermap_batch(const dmimo_channel_params* params, int32_t M,
+                                  const double* ap_xyz, int32_t maps, int32_t K, const void* W,
+                                  const dmimo_points* pts, double sigma2, int32_t prec,
+                                  void* power, void* sinr, int32_t* best_k, void* per_stream,
+                                  void* stream);
+
 /* Proximal gradient descent on the PA-consumption Lagrangian
  * lambda ||W||_{2,1} + ||H W^T - sigma D_gamma^{1/2}||_F^2 (Sec. III eq. l; Sec. IV
  * eq. proxgd), and its deep-unfolded form with per-layer parameters (Sec. V,

@@ -255,10 +255,12 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, c
     return launch_beamform(a, as_stream(stream));
 }
 
-dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const double* ap_xyz,
-                            int32_t K, const void* W, const dmimo_points* pts, double sigma2,
-                            int32_t prec, void* power, void* sinr, int32_t* best_k,
-                            void* per_stream, void* stream) {
+namespace {
+
+dmimo_status powermap_maps(const dmimo_channel_params* params, int32_t M, const double* ap_xyz,
+                           int32_t maps, int32_t K, const void* W, const dmimo_points* pts,
+                           double sigma2, int32_t prec, void* power, void* sinr, int32_t* best_k,
+                           void* per_stream, void* stream) {
     clear_error();
     WaveConst w;
     dmimo_status st = make_wave_const(params, &w);
@@ -267,6 +269,7 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const
         return fail(DMIMO_E_UNSUPPORTED, "powermap: only the LoS model is mapped");
     PointsDev P;
     if ((st = make_points(pts, &P))) return st;
+    if (maps < 0 || maps > 65535) return fail(DMIMO_E_SHAPE, "powermap: 0 <= maps <= 65535");
     if (M < 1 || K < 1) return fail(DMIMO_E_SHAPE, "powermap: K and M must be >= 1");
     if (K > DMIMO_K_MAX) return fail(DMIMO_E_SHAPE, "powermap: K exceeds DMIMO_K_MAX");
     if (!valid_prec(prec)) return fail(DMIMO_E_DTYPE, "powermap: unknown precision");
@@ -274,13 +277,14 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const
         return fail(DMIMO_E_ARG, "powermap: sigma2 must be >= 0");
     if (sinr && !(sigma2 > 0.0)) return fail(DMIMO_E_ARG, "powermap: SINR map needs sigma2 > 0");
     if (P.n > (int64_t)INT32_MAX * 8) return fail(DMIMO_E_SHAPE, "powermap: too many points");
-    if (P.n == 0) return DMIMO_OK;
+    if (P.n == 0 || maps == 0) return DMIMO_OK;
     if (!ap_xyz || !W || !power) return fail(DMIMO_E_ARG, "powermap: NULL ap_xyz, W or power");
     PowermapArgs a;
     a.w = w;
     a.P = P;
     a.M = M;
     a.K = K;
+    a.maps = maps;
     a.ap = ap_xyz;
     a.W = W;
     a.sigma2 = sigma2;
@@ -290,6 +294,25 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const
     a.best_k = best_k;
     a.per_stream = per_stream;
     return launch_powermap(a, as_stream(stream));
+}
+
+}  // namespace
+
+dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M, const double* ap_xyz,
+                            int32_t K, const void* W, const dmimo_points* pts, double sigma2,
+                            int32_t prec, void* power, void* sinr, int32_t* best_k,
+                            void* per_stream, void* stream) {
+    return powermap_maps(params, M, ap_xyz, 1, K, W, pts, sigma2, prec, power, sinr, best_k,
+                         per_stream, stream);
+}
+
+dmimo_status dmimo_powermap_batch(const dmimo_channel_params* params, int32_t M,
+                                  const double* ap_xyz, int32_t maps, int32_t K, const void* W,
+                                  const dmimo_points* pts, double sigma2, int32_t prec,
+                                  void* power, void* sinr, int32_t* best_k, void* per_stream,
+                                  void* stream) {
+    return powermap_maps(params, M, ap_xyz, maps, K, W, pts, sigma2, prec, power, sinr, best_k,
+                         per_stream, stream);
 }
 
 dmimo_status dmimo_pgd(int32_t B, int32_t K, int32_t M, const void* H, const double* gamma_lin,

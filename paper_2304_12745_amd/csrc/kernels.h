@@ -37,11 +37,15 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s);
 // antennas).  MR and equal-gain MR: the wide path's per-tile shares, else 0.
 size_t beamform_workspace_bytes(int precoder, int64_t B, int K, int64_t M, int prec);
 
+// `maps` precoders over the same antennas and points, one launch: W
+// [maps][K][M], every output [maps][N] ([maps][N][K] per stream); map p is
+// grid row p (blockIdx.y) of every map kernel.
 struct PowermapArgs {
     WaveConst w;
     PointsDev P;
     int M;
     int K;
+    int maps = 1;
     const double* ap;
     const void* W;
     double sigma2;

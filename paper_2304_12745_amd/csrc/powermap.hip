@@ -45,6 +45,20 @@ struct PmDev {
     void* per_stream;
 };
 
+// Map p of a batched launch (grid row p): its weights and outputs.
+template <bool F64>
+__device__ __forceinline__ PmDev map_of(PmDev a, int64_t p) {
+    using R = typename PmTypes<F64>::R;
+    using C = typename PmTypes<F64>::C;
+    const int64_t N = a.P.n;
+    a.W = reinterpret_cast<const C*>(a.W) + p * a.K * a.M;
+    a.power = reinterpret_cast<R*>(a.power) + p * N;
+    if (a.sinr) a.sinr = reinterpret_cast<R*>(a.sinr) + p * N;
+    if (a.best_k) a.best_k += p * N;
+    if (a.per_stream) a.per_stream = reinterpret_cast<R*>(a.per_stream) + p * N * a.K;
+    return a;
+}
+
 template <bool F64, typename R>
 __device__ __forceinline__ void epilogue(const PmDev& a, int64_t n, const R* zr, const R* zi,
                                          int K) {
@@ -76,7 +90,8 @@ __device__ __forceinline__ void epilogue(const PmDev& a, int64_t n, const R* zr,
 
 // KT: accumulator count (compile time); K <= KT at run time.
 template <int KT, bool F64>
-__global__ __launch_bounds__(256) void powermap_valu_kernel(PmDev a) {
+__global__ __launch_bounds__(256) void powermap_valu_kernel(PmDev a0) {
+    const PmDev a = map_of<F64>(a0, blockIdx.y);
     using R = typename PmTypes<F64>::R;
     using C = typename PmTypes<F64>::C;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -122,13 +137,13 @@ __global__ __launch_bounds__(256) void powermap_valu_kernel(PmDev a) {
 
 template <int KT>
 __global__ __launch_bounds__(256) void powermap_valu_f32_kernel(PmMapDev a) {
-    map_valu_wg<KT>(a, (int64_t)blockIdx.x * 256);
+    map_valu_wg<KT>(map_of(a, blockIdx.y), (int64_t)blockIdx.x * 256);
 }
 
 template <bool F64>
-dmimo_status launch_valu(const PmDev& d, hipStream_t s) {
+dmimo_status launch_valu(const PmDev& d, int maps, hipStream_t s) {
     const int64_t blocks = ceil_div(d.P.n, 256);
-    dim3 grid((unsigned)blocks), block(256);
+    dim3 grid((unsigned)blocks, (unsigned)maps), block(256);
     const int K = d.K;
     if (K == 1) powermap_valu_kernel<1, F64><<<grid, block, 0, s>>>(d);
     else if (K <= 2) powermap_valu_kernel<2, F64><<<grid, block, 0, s>>>(d);
@@ -154,12 +169,12 @@ dmimo_status launch_powermap(const PowermapArgs& a, hipStream_t s) {
     d.sinr = a.sinr;
     d.best_k = a.best_k;
     d.per_stream = a.per_stream;
-    if (a.prec == DMIMO_F64) return launch_valu<true>(d, s);
+    if (a.prec == DMIMO_F64) return launch_valu<true>(d, a.maps, s);
     if (a.prec == DMIMO_F32) {
         // one or two streams: four or eight FMA per term stay on the VALU
         if (a.K <= 2) {
             const PmMapDev m = make_map_dev(a);
-            dim3 grid((unsigned)ceil_div(a.P.n, 256)), block(256);
+            dim3 grid((unsigned)ceil_div(a.P.n, 256), (unsigned)a.maps), block(256);
             if (a.K == 1) powermap_valu_f32_kernel<1><<<grid, block, 0, s>>>(m);
             else powermap_valu_f32_kernel<2><<<grid, block, 0, s>>>(m);
             return check_launch("powermap_valu_f32_kernel");

@@ -24,6 +24,17 @@ struct PmMapDev {
     float* per_stream;
 };
 
+// Map p of a batched launch: its weights and outputs.
+__device__ __forceinline__ PmMapDev map_of(PmMapDev a, int64_t p) {
+    const int64_t N = a.P.n;
+    a.W += p * a.K * a.M;
+    a.power += p * N;
+    if (a.sinr) a.sinr += p * N;
+    if (a.best_k) a.best_k += p * N;
+    if (a.per_stream) a.per_stream += p * N * a.K;
+    return a;
+}
+
 inline PmMapDev make_map_dev(const PowermapArgs& a) {
     PmMapDev d;
     d.P = a.P;

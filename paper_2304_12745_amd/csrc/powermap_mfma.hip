@@ -11,14 +11,15 @@ namespace {
 template <int NT, int PT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void powermap_mfma_kernel(PmMapDev a) {
     __shared__ __attribute__((aligned(16))) char smem[f32_lds_bytes<NT, PT, WAVES>()];
-    map_f32_wg<NT, PT, WAVES>(a, (int64_t)blockIdx.x * (WAVES * 16 * PT), smem);
+    map_f32_wg<NT, PT, WAVES>(map_of(a, blockIdx.y), (int64_t)blockIdx.x * (WAVES * 16 * PT), smem);
 }
 
 template <int NT, int PT, bool BF16, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4))) void powermap_x3_kernel(PmMapDev a) {
     __shared__ __attribute__((aligned(16))) char smem[x3_lds_bytes<NT, PT, WAVES>()];
     __shared__ float s_red[WAVES];
-    map_x3_wg<NT, PT, BF16, WAVES>(a, (int64_t)blockIdx.x * (WAVES * 16 * PT), smem, s_red);
+    map_x3_wg<NT, PT, BF16, WAVES>(map_of(a, blockIdx.y), (int64_t)blockIdx.x * (WAVES * 16 * PT), smem,
+                                   s_red);
 }
 
 #ifndef DMIMO_PM_WAVES
@@ -27,49 +28,49 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4)))
 constexpr int kWaves = DMIMO_PM_WAVES;
 
 template <int PT, typename F>
-dmimo_status launch_blocks(const PmMapDev& d, F&& launch) {
+dmimo_status launch_blocks(const PmMapDev& d, int maps, F&& launch) {
     const int64_t blocks = ceil_div(d.P.n, kWaves * 16 * PT);
     if (blocks > 0x7fffffff) return fail(DMIMO_E_SHAPE, "powermap: too many points");
-    launch(dim3((unsigned)blocks));
+    launch(dim3((unsigned)blocks, (unsigned)maps));
     return check_launch("powermap_mfma");
 }
 
 template <int NT>
-dmimo_status launch_f32(const PmMapDev& d, hipStream_t s) {
+dmimo_status launch_f32(const PmMapDev& d, int maps, hipStream_t s) {
     // four 16-point tiles per wave at K <= 8 (measured 6% faster than two)
     constexpr int PT = NT == 1 ? 4 : 2;
     return launch_blocks<PT>(
-        d, [&](dim3 g) { powermap_mfma_kernel<NT, PT, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
+        d, maps, [&](dim3 g) { powermap_mfma_kernel<NT, PT, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
 }
 
 template <int NT, bool BF16>
-dmimo_status launch_x3(const PmMapDev& d, hipStream_t s) {
+dmimo_status launch_x3(const PmMapDev& d, int maps, hipStream_t s) {
     // one 16-point tile per wave for K > 8 keeps the kernel within 128 VGPRs
     // (4 waves per SIMD) without spills
     constexpr int PT = NT == 1 ? 2 : 1;
     return launch_blocks<PT>(
-        d, [&](dim3 g) { powermap_x3_kernel<NT, PT, BF16, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
+        d, maps, [&](dim3 g) { powermap_x3_kernel<NT, PT, BF16, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
 }
 
 }  // namespace
 
 dmimo_status launch_powermap_f32_mfma(const PowermapArgs& a, hipStream_t s) {
     const PmMapDev d = make_map_dev(a);
-    if (a.K <= 8) return launch_f32<1>(d, s);
-    if (a.K <= 16) return launch_f32<2>(d, s);
-    return launch_f32<4>(d, s);
+    if (a.K <= 8) return launch_f32<1>(d, a.maps, s);
+    if (a.K <= 16) return launch_f32<2>(d, a.maps, s);
+    return launch_f32<4>(d, a.maps, s);
 }
 
 dmimo_status launch_powermap_mfma(const PowermapArgs& a, hipStream_t s) {
     const PmMapDev d = make_map_dev(a);
     if (a.prec == DMIMO_MIX_BF16X3) {
-        if (a.K <= 8) return launch_x3<1, true>(d, s);
-        if (a.K <= 16) return launch_x3<2, true>(d, s);
-        return launch_x3<4, true>(d, s);
+        if (a.K <= 8) return launch_x3<1, true>(d, a.maps, s);
+        if (a.K <= 16) return launch_x3<2, true>(d, a.maps, s);
+        return launch_x3<4, true>(d, a.maps, s);
     }
-    if (a.K <= 8) return launch_x3<1, false>(d, s);
-    if (a.K <= 16) return launch_x3<2, false>(d, s);
-    return launch_x3<4, false>(d, s);
+    if (a.K <= 8) return launch_x3<1, false>(d, a.maps, s);
+    if (a.K <= 16) return launch_x3<2, false>(d, a.maps, s);
+    return launch_x3<4, false>(d, a.maps, s);
 }
 
 }  // namespace dmimo

@@ -59,6 +59,8 @@ _SIGS = {
                        _vp, _vp, _vp, _sz, _vp],
     "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
+    "dmimo_powermap_batch": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _i32, _vp,
+                             ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
     "dmimo_pgd": [_i32, _i32, _i32, _vp, _vp, _f64, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "dmimo_pa_precoder": [_i32, _i32, _i32, _vp, _vp, _f64, _i32, _vp, _vp, _i32, _vp, _vp, _vp,
@@ -291,6 +293,32 @@ def powermap(params: ChannelParams, ap_xyz, W, points: Points, sigma2=1e-12, pre
                                 ctypes.byref(points), float(sigma2), prec, _ptr(out.power),
                                 _ptr(out.sinr), _ptr(out.best_k), _ptr(out.per_stream),
                                 _stream(stream)), "dmimo_powermap")
+    return out
+
+
+def powermap_batch(params: ChannelParams, ap_xyz, W, points: Points, sigma2=1e-12, prec="f32",
+                   want_sinr=True, want_best=True, want_per_stream=False, out=None,
+                   stream=None) -> MapResult:
+    """The maps of several precoders over the same points in one launch
+    (dmimo_powermap_batch).  W [P][K][M]; outputs [P][N] ([P][N][K] per stream)."""
+    import torch
+    prec = _prec(prec)
+    P, K, M = W.shape
+    if not W.is_contiguous():
+        raise ValueError("powermap_batch: W must be contiguous [P][K][M]")
+    N = points.nx * points.ny if points.kind == PTS_GRID else points.n
+    dev = W.device
+    rd = _rdtype(prec)
+    if out is None:
+        out = MapResult(
+            torch.empty((P, N), dtype=rd, device=dev),
+            torch.empty((P, N), dtype=rd, device=dev) if want_sinr else None,
+            torch.empty((P, N), dtype=torch.int32, device=dev) if want_best else None,
+            torch.empty((P, N, K), dtype=rd, device=dev) if want_per_stream else None)
+    _check(lib().dmimo_powermap_batch(ctypes.byref(params), M, _ptr(ap_xyz), P, K, _ptr(W),
+                                      ctypes.byref(points), float(sigma2), prec, _ptr(out.power),
+                                      _ptr(out.sinr), _ptr(out.best_k), _ptr(out.per_stream),
+                                      _stream(stream)), "dmimo_powermap_batch")
     return out
 
 

@@ -120,6 +120,19 @@ def test_beamform_validation(lib):
     assert b"workspace" in lib.dmimo_last_error() or bf(ws_bytes=16) == 4
 
 
+def test_powermap_batch_validation(lib):
+    p = D.channel_params(3.5e9)
+    pts = D.Points(D.PTS_GRID, 4, 4, 0, 0, 1, 1, 1, None, 0)
+    def pmb(maps, W=FAKE, power=FAKE, K=2, M=4):
+        return lib.dmimo_powermap_batch(ctypes.byref(p), M, FAKE, maps, K, W, ctypes.byref(pts),
+                                        1e-9, D.F32, power, None, None, None, None)
+    assert pmb(-1) == 2
+    assert pmb(65536) == 2
+    assert pmb(0, W=None, power=None) == 0      # no maps: valid, launches nothing
+    assert pmb(2, W=None) == 1
+    assert pmb(2, K=0) == 2
+
+
 def test_gram_and_channel_validation(lib):
     assert lib.dmimo_gram(2, 0, 4, FAKE, D.F32, FAKE, None) == 2
     assert lib.dmimo_gram(2, 40, 64, FAKE, D.F32, FAKE, None) == 2

@@ -644,3 +644,48 @@ def test_powermap_hall_sampled(D, prec):
     check_db(power[rows].ravel(), O.power_map(Hg, Wc), MAP_TOL[prec], what="power rows")
     s_ref, _ = O.sinr_map(Hg, Wc, w.sigma2)
     check_db(sinr[rows].ravel(), s_ref, MAP_TOL[prec], what="sinr rows")
+
+
+# several precoders over the same points in one launch (map p on grid row p of
+# the kernel) equal one call per precoder bit for bit, in every kernel family:
+# FP32 VALU (K <= 2), FP32 MFMA (K <= 8, 16, 32), FP64, FP16x3, BF16x3; a
+# ragged grid (41 x 29) and a ragged antenna chunk (M = 70)
+@pytest.mark.parametrize("prec,K", [("f32", 2), ("f32", 8), ("f32", 12), ("f32", 32), ("f64", 8),
+                                    ("f16x3", 8), ("bf16x3", 20)])
+def test_powermap_batch_equals_single_maps(D, prec, K):
+    import torch
+    say(f"powermap batch of 3 precoders, K={K}, {prec}")
+    rng = np.random.default_rng(K + 7)
+    M, P = 70, 3
+    aps = WL.uniform_positions(rng, M, 20, 20, 3.0)
+    g = WL.Grid(0.0, 0.0, 20 / 41, 20 / 29, 1.2, 41, 29)
+    Wn = WL.complex_normal(rng, (P, K, M)) * 0.05
+    W = dev(Wn if prec == "f64" else c64(Wn))
+    params = D.channel_params(3.5e9)
+    apd = dev(aps)
+    r = D.powermap_batch(params, apd, W, D.grid_points(g), 1e-9, prec, want_per_stream=True)
+    assert tuple(r.power.shape) == (P, g.nx * g.ny)
+    for p in range(P):
+        one = D.powermap(params, apd, W[p].contiguous(), D.grid_points(g), 1e-9, prec,
+                         want_per_stream=True)
+        for a, b in ((r.power[p], one.power), (r.sinr[p], one.sinr), (r.best_k[p], one.best_k),
+                     (r.per_stream[p], one.per_stream)):
+            assert torch.equal(a, b), p
+
+
+# the bench step's two maps (MR and ZF of the room's 8 users, 512 x 512 grid)
+# in one launch equal the two single calls bit for bit
+def test_powermap_batch_room_step_maps(D):
+    import torch
+    say("powermap batch: room MR + ZF maps, 512 x 512")
+    w = WL.room_workload()
+    aps = w.ap_xyz[0]
+    Hu = O.los_channel(w.user_xyz[0], aps, w.freq_hz)
+    Wst = np.stack([O.mr_precoder(Hu[None], 1.0)[0], O.zf_precoder(Hu[None], None, w.sigma2, 1.0)[0][0]])
+    W = dev(c64(Wst))
+    params, apd, pts = D.channel_params(w.freq_hz), dev(aps), D.grid_points(w.grid)
+    r = D.powermap_batch(params, apd, W, pts, w.sigma2, "f32")
+    for p in range(2):
+        one = D.powermap(params, apd, W[p].contiguous(), pts, w.sigma2, "f32")
+        assert torch.equal(r.power[p], one.power) and torch.equal(r.sinr[p], one.sinr)
+        assert torch.equal(r.best_k[p], one.best_k)
