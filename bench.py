@@ -6,13 +6,14 @@ z = 4 m) of a 20x20x4 m room, 3.5 GHz, K = 8 users at z = 1.2 m, noise -90 dBm.
 One step is one pass of the whole path, with inputs already resident in HBM:
 
   1. dmimo_channel   user channels H (K x M, complex64)
-  2. dmimo_beamform  MR at 1 W                      (+ p_m, L2,1, SINR_k, R_sum)
-  3. dmimo_beamform  ZF at 1 W: FP64 Gram and inverse (+ the same epilogues)
-  4. dmimo_powermap_batch  MR and ZF power + SINR + best-stream maps, 512 x 512
+  2. dmimo_beamform_multi  MR and ZF at 1 W in one launch (+ p_m, L2,1,
+                           SINR_k, R_sum); ZF with its FP64 Gram and inverse
+  3. dmimo_powermap_batch  MR and ZF power + SINR + best-stream maps, 512 x 512
                            grid at z = 1.2 m, both maps in one launch
 
 value = channel terms h[n,m] synthesised and consumed per second, over the
-whole step (K M for each of 1-3, N M for each map), in G h/s.
+whole step (K M for the channels and for each precoder, N M for each map), in
+G h/s.
 
 The JSON line also carries:
 * ``roofline`` for the dominant kernel (the FP32 power map).  It is bound by
@@ -264,10 +265,10 @@ def main():
 def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     """Warm up, then time exactly args.steps steps of the room workload.
 
-    One step, in order on torch's current stream: the user channel, the MR
-    and ZF precoders (Gram and inverse inside), written into one [2][K][M]
-    array, then the MR and ZF maps in one dmimo_powermap_batch launch (map p
-    on grid row p).  One pair of HIP events on that stream brackets the map
+    One step, in order on torch's current stream: the user channel; the MR
+    and ZF precoders of those channels (Gram and inverse inside) in one
+    dmimo_beamform_multi launch, W written into one [2][K][M] array; the MR
+    and ZF maps in one dmimo_powermap_batch launch (map p on grid row p).  One pair of HIP events on that stream brackets the map
     launch of every args.event_every-th timed step (a pair on every step
     adds about 7 us per step).  (A variant with the MR branch on a second
     stream was measured slower: 0.114 vs 0.094 ms/step, because the
@@ -278,20 +279,19 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     import torch
     K, M, N = w.K, w.M, w.grid.n
     dev = H.device
-    Wst = torch.empty((2, K, M), dtype=torch.complex64, device=dev)
     both = D.MapResult(torch.empty((2, N), device=dev), torch.empty((2, N), device=dev),
                        torch.empty((2, N), dtype=torch.int32, device=dev), None)
     maps = {p: D.MapResult(both.power[i], both.sinr[i], both.best_k[i], None)
             for i, p in enumerate(("mr", "zf"))}
-    bf = {}
-    for i, p in enumerate(("mr", "zf")):
-        bf[p] = D.beamform_outputs(1, K, M, prec, dev, precoder=p)
-        bf[p].W = Wst[i:i + 1]
+    pcs = ("mr", "zf")
+    pre = D.beamform_multi(H, pcs, None, w.sigma2, w.p_total, prec)   # outputs [2][1][...]
+    Wst = pre.W.view(2, K, M)
+    bf = {p: D.BeamformResult(pre.W[i], pre.p_ant[i], pre.l21[i], pre.sinr[i], pre.rsum[i],
+                              pre.info[i]) for i, p in enumerate(pcs)}
 
     def step(e=None):
         D.channel(params, ap, upts, prec="f32", out=H)
-        D.beamform(H, "mr", None, w.sigma2, w.p_total, prec, out=bf["mr"])
-        D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=bf["zf"])
+        D.beamform_multi(H, pcs, None, w.sigma2, w.p_total, prec, out=pre)
         if e is not None:
             e[0].record()
         D.powermap_batch(params, ap0, Wst, gpts, w.sigma2, prec, out=both)

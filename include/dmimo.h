@@ -167,6 +167,32 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
                             double* l21, double* sinr, double* rsum, int32_t* info,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* Several precoders of the same channels in one call, as Sec. VI compares MR
+ * and ZF (and the PA-aware precoder) on one deployment: precoder p is
+ * dmimo_beamform(precoders[p], ...) with every output at offset p of a
+ * leading [P] dimension, so that the results equal P separate calls bit for
+ * bit.  When every precoder takes the one-pass kernel (K <= 8, M <= 256; 128
+ * for DMIMO_F64) the P precoders run side by side in one launch; other shapes
+ * make one launch sequence per precoder, in order.
+ *   P          0 <= P <= 8 (0: nothing to do); precoders host [P] of
+ *              DMIMO_MR, DMIMO_ZF, DMIMO_MR_PHASE.
+ *   W          device [P][B][K][M]; p_ant [P][B][M]; l21, rsum, info [P][B];
+ *              sinr [P][B][K] (any may be NULL except W).
+ *   ws         device workspace of dmimo_beamform_multi_workspace_size(...)
+ *              bytes: precoder p's dmimo_workspace_size, each rounded up to
+ *              256 B, in order.
+ *   Every other argument as for dmimo_beamform; an invalid precoder or shape
+ *   in any entry fails the whole call before any launch. */
+dmimo_status dmimo_beamform_multi(int32_t P, const int32_t* precoders, int32_t B, int32_t K,
+                                  int32_t M, const void* H, const double* gamma_lin,
+                                  double sigma2, double p_total, int32_t prec, void* W,
+                                  double* p_ant, double* l21, double* sinr, double* rsum,
+                                  int32_t* info, void* ws, size_t ws_bytes, void* stream);
+/* Workspace bytes of dmimo_beamform_multi (0 for an invalid list).  Pure host
+ * function. */
+size_t dmimo_beamform_multi_workspace_size(int32_t P, const int32_t* precoders, int32_t B,
+                                           int32_t K, int32_t M, int32_t prec);
+
 /* Fused channel synthesis and coherent sums at N points.  h[n][m] is never
  * stored.
  *   z_k[n]    = sum_m h[n][m] w_km         (x = W^T s, Sec. II-A)

@@ -202,12 +202,12 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
     return launch_gram(B, K, M, H, prec, G, as_stream(stream));
 }
 
-dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, const void* H,
-                            const double* gamma_lin, double sigma2, double p_total,
-                            int32_t prec, void* W, double* p_ant, double* l21, double* sinr,
-                            double* rsum, int32_t* info, void* ws, size_t ws_bytes,
-                            void* stream) {
-    clear_error();
+namespace {
+
+// Argument checks shared by the beamform calls; fills gam with the targets.
+dmimo_status check_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, double sigma2,
+                            double p_total, int32_t prec, const double* sinr_or_rsum,
+                            const double* gamma_lin, double* gam) {
     if (precoder != DMIMO_MR && precoder != DMIMO_ZF && precoder != DMIMO_MR_PHASE)
         return fail(DMIMO_E_DTYPE, "beamform: unknown precoder");
     if (B < 0) return fail(DMIMO_E_SHAPE, "beamform: B must be >= 0");
@@ -219,22 +219,20 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, c
     if (!(sigma2 >= 0.0) || !std::isfinite(sigma2))
         return fail(DMIMO_E_ARG, "beamform: sigma2 must be >= 0");
     if (!std::isfinite(p_total)) return fail(DMIMO_E_ARG, "beamform: p_total must be finite");
-    if ((sinr || rsum) && !(sigma2 > 0.0))
+    if (sinr_or_rsum && !(sigma2 > 0.0))
         return fail(DMIMO_E_ARG, "beamform: SINR outputs need sigma2 > 0");
-    double gam[DMIMO_K_MAX];
     for (int k = 0; k < K; ++k) {
         gam[k] = gamma_lin ? gamma_lin[k] : 1.0;
         if (!(gam[k] >= 0.0) || !std::isfinite(gam[k]))
             return fail(DMIMO_E_ARG, "beamform: gamma_lin must be finite and >= 0");
     }
-    const size_t need = dmimo_workspace_size(
-        precoder == DMIMO_ZF ? DMIMO_CALL_BEAMFORM_ZF : DMIMO_CALL_BEAMFORM_MR, B, K, M, 0, prec);
-    if (B == 0) return DMIMO_OK;
-    if (!H || !W) return fail(DMIMO_E_ARG, "beamform: NULL H or W");
-    if (need > 0 && (!ws || ws_bytes < need)) {
-        set_error("beamform: workspace needs %zu bytes, got %zu", need, ws ? ws_bytes : 0);
-        return DMIMO_E_WORKSPACE;
-    }
+    return DMIMO_OK;
+}
+
+BeamformArgs beamform_args(int32_t precoder, int32_t B, int32_t K, int32_t M, const void* H,
+                           const double* gam, double sigma2, double p_total, int32_t prec,
+                           void* W, double* p_ant, double* l21, double* sinr, double* rsum,
+                           int32_t* info, void* ws) {
     BeamformArgs a;
     a.precoder = precoder;
     a.B = B;
@@ -252,7 +250,67 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, c
     a.rsum = rsum;
     a.info = info;
     a.ws = ws;
-    return launch_beamform(a, as_stream(stream));
+    return a;
+}
+
+}  // namespace
+
+dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, const void* H,
+                            const double* gamma_lin, double sigma2, double p_total,
+                            int32_t prec, void* W, double* p_ant, double* l21, double* sinr,
+                            double* rsum, int32_t* info, void* ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    double gam[DMIMO_K_MAX];
+    dmimo_status st = check_beamform(precoder, B, K, M, sigma2, p_total, prec,
+                                     sinr ? sinr : rsum, gamma_lin, gam);
+    if (st) return st;
+    const size_t need = dmimo_workspace_size(
+        precoder == DMIMO_ZF ? DMIMO_CALL_BEAMFORM_ZF : DMIMO_CALL_BEAMFORM_MR, B, K, M, 0, prec);
+    if (B == 0) return DMIMO_OK;
+    if (!H || !W) return fail(DMIMO_E_ARG, "beamform: NULL H or W");
+    if (need > 0 && (!ws || ws_bytes < need)) {
+        set_error("beamform: workspace needs %zu bytes, got %zu", need, ws ? ws_bytes : 0);
+        return DMIMO_E_WORKSPACE;
+    }
+    return launch_beamform(beamform_args(precoder, B, K, M, H, gam, sigma2, p_total, prec, W, p_ant,
+                                         l21, sinr, rsum, info, ws),
+                           as_stream(stream));
+}
+
+dmimo_status dmimo_beamform_multi(int32_t P, const int32_t* precoders, int32_t B, int32_t K,
+                                  int32_t M, const void* H, const double* gamma_lin,
+                                  double sigma2, double p_total, int32_t prec, void* W,
+                                  double* p_ant, double* l21, double* sinr, double* rsum,
+                                  int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (P < 0 || P > 8) return fail(DMIMO_E_SHAPE, "beamform_multi: 0 <= P <= 8");
+    if (P > 0 && !precoders) return fail(DMIMO_E_ARG, "beamform_multi: NULL precoders");
+    double gam[DMIMO_K_MAX];
+    for (int i = 0; i < P; ++i) {
+        dmimo_status st = check_beamform(precoders[i], B, K, M, sigma2, p_total, prec,
+                                         sinr ? sinr : rsum, gamma_lin, gam);
+        if (st) return st;
+    }
+    if (P == 0 || B == 0) return DMIMO_OK;
+    if (!H || !W) return fail(DMIMO_E_ARG, "beamform_multi: NULL H or W");
+    const size_t need = dmimo_beamform_multi_workspace_size(P, precoders, B, K, M, prec);
+    if (need > 0 && (!ws || ws_bytes < need)) {
+        set_error("beamform_multi: workspace needs %zu bytes, got %zu", need, ws ? ws_bytes : 0);
+        return DMIMO_E_WORKSPACE;
+    }
+    return launch_beamform_multi(beamform_args(precoders[0], B, K, M, H, gam, sigma2, p_total,
+                                               prec, W, p_ant, l21, sinr, rsum, info, ws),
+                                 P, precoders, as_stream(stream));
+}
+
+size_t dmimo_beamform_multi_workspace_size(int32_t P, const int32_t* precoders, int32_t B,
+                                           int32_t K, int32_t M, int32_t prec) {
+    if (P < 1 || P > 8 || !precoders || B <= 0 || K <= 0 || M <= 0) return 0;
+    for (int i = 0; i < P; ++i)
+        if (precoders[i] != DMIMO_MR && precoders[i] != DMIMO_ZF && precoders[i] != DMIMO_MR_PHASE)
+            return 0;
+    return beamform_multi_workspace_bytes(P, precoders, B, K, M, prec);
 }
 
 namespace {

@@ -32,8 +32,12 @@ namespace {
 constexpr int kCols = 64;   // antennas per tile
 constexpr int kThreads = 256;
 
+constexpr int kMultiMax = 8;   // precoders per multi-precoder call
+
 struct BfDev {
     int precoder;
+    int precs[kMultiMax];   // one-pass kernel: precoder of grid row p
+    int64_t B;
     int K;
     int64_t M;
     const void* H;
@@ -708,9 +712,17 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
     const int K = a.K;
     const int M = (int)a.M;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // grid row `row`: precoder precs[row] and its outputs, [P][B][...]
+    const int64_t row = blockIdx.y;
+    const int precoder = a.precs[row];
+    double* const p_ant = a.p_ant ? a.p_ant + row * a.B * M : nullptr;
+    double* const l21_out = a.l21 ? a.l21 + row * a.B : nullptr;
+    double* const sinr = a.sinr ? a.sinr + row * a.B * K : nullptr;
+    double* const rsum = a.rsum ? a.rsum + row * a.B : nullptr;
+    int32_t* const info = a.info ? a.info + row * a.B : nullptr;
     const T2* Hb = reinterpret_cast<const T2*>(a.H) + b * K * M;
-    T2* Wb = reinterpret_cast<T2*>(a.W) + b * K * M;
-    const bool zf = a.precoder == DMIMO_ZF;
+    T2* Wb = reinterpret_cast<T2*>(a.W) + (row * a.B + b) * K * M;
+    const bool zf = precoder == DMIMO_ZF;
     // antenna (tid / 4 within a tile of 64) and user phase (tid % 4) in step 4;
     // entry (tid / 4 = 8 i + j) and antenna phase (tid % 4) in steps 2 and 5
     const int cc = tid >> 2, rg = tid & 3;
@@ -784,17 +796,17 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
                 z.y = 0;
                 Wb[e] = z;
             }
-            if (a.p_ant)
-                for (int m = tid; m < M; m += kThreads) a.p_ant[b * M + m] = 0.0;
-            if (a.sinr && tid < K) a.sinr[b * K + tid] = 0.0;
+            if (p_ant)
+                for (int m = tid; m < M; m += kThreads) p_ant[b * M + m] = 0.0;
+            if (sinr && tid < K) sinr[b * K + tid] = 0.0;
             if (tid == 0) {
-                if (a.l21) a.l21[b] = 0.0;
-                if (a.rsum) a.rsum[b] = 0.0;
-                if (a.info) a.info[b] = S.fail;
+                if (l21_out) l21_out[b] = 0.0;
+                if (rsum) rsum[b] = 0.0;
+                if (info) info[b] = S.fail;
             }
             return;
         }
-    } else if (a.precoder == DMIMO_MR) {
+    } else if (precoder == DMIMO_MR) {
         const double fs = S.red[0] + S.red[1] + S.red[2] + S.red[3];
         mr_scale = a.p_total > 0.0 ? sqrt(a.p_total) / sqrt(fs) : 1.0;
     } else {
@@ -819,7 +831,7 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
                 w = make_double2(S.scale[k] * x.x, -S.scale[k] * x.y);
             } else {
                 const double2 h = to_d2(S.h[k][c]);
-                if (a.precoder == DMIMO_MR) {
+                if (precoder == DMIMO_MR) {
                     w = make_double2(mr_scale * h.x, -mr_scale * h.y);
                 } else {
                     const double mag = sqrt(h.x * h.x + h.y * h.y);
@@ -838,7 +850,7 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
         pm += __shfl_xor(pm, 1, 64);
         pm += __shfl_xor(pm, 2, 64);
         if (rg == 0) {
-            if (a.p_ant) a.p_ant[b * M + c] = pm;
+            if (p_ant) p_ant[b * M + c] = pm;
             l21 += sqrt(pm);
         }
     }
@@ -847,7 +859,7 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
     __syncthreads();
 
     // 5.
-    const bool want_gain = a.sinr || a.rsum;
+    const bool want_gain = sinr || rsum;
     if (want_gain) {
         double2 s = make_double2(0.0, 0.0);
         if (ei < K && ej < K)
@@ -870,14 +882,14 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
             else intf += p;
         }
         const double snr = sig / (intf + a.sigma2);
-        if (a.sinr) a.sinr[b * K + lane] = snr;
+        if (sinr) sinr[b * K + lane] = snr;
         rate = log2(1.0 + snr);
     }
     rate = wave_sum(rate);
     if (lane == 0) {
-        if (a.rsum) a.rsum[b] = rate;
-        if (a.l21) a.l21[b] = S.red2[0] + S.red2[1] + S.red2[2] + S.red2[3];
-        if (a.info) a.info[b] = 0;
+        if (rsum) rsum[b] = rate;
+        if (l21_out) l21_out[b] = S.red2[0] + S.red2[1] + S.red2[2] + S.red2[3];
+        if (info) info[b] = 0;
     }
 }
 
@@ -963,8 +975,8 @@ dmimo_status launch_wide(const BfDev& d, int64_t B, int prec, hipStream_t s) {
 int64_t small_max_m(int prec) { return prec == DMIMO_F64 ? kSmallMaxM / 2 : kSmallMaxM; }
 
 template <typename T2, int MT_WIDE>
-dmimo_status launch_small(const BfDev& d, int64_t B, hipStream_t s) {
-    dim3 grid((unsigned)B), block(kThreads);
+dmimo_status launch_small(const BfDev& d, int64_t B, int P, hipStream_t s) {
+    dim3 grid((unsigned)B, (unsigned)P), block(kThreads);
     if (d.M <= 64) beamform_small_kernel<T2, 64><<<grid, block, 0, s>>>(d);
     else beamform_small_kernel<T2, MT_WIDE><<<grid, block, 0, s>>>(d);
     return check_launch("beamform_small_kernel");
@@ -983,6 +995,8 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
     if (a.B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "beamform: B too large");
     BfDev d;
     d.precoder = a.precoder;
+    for (int i = 0; i < kMultiMax; ++i) d.precs[i] = a.precoder;
+    d.B = a.B;
     d.K = a.K;
     d.M = a.M;
     d.H = a.H;
@@ -1002,8 +1016,8 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
         // G is formed in FP64 in the kernel, so the FP64 Gram's tolerance
         // applies to FP64 input and the FP32 one to every other mode
         d.pivot_tol = a.prec == DMIMO_F64 ? 1e-12 : 1e-6;
-        if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, s);
-        return launch_small<float2, kSmallMaxM>(d, a.B, s);
+        if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, 1, s);
+        return launch_small<float2, kSmallMaxM>(d, a.B, 1, s);
     }
     if (wide_shape(a.B, a.M)) {
         // ZF: G from FP64 tile sums, so the FP64 Gram's tolerance for FP64
@@ -1018,6 +1032,61 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
     }
     if (a.prec == DMIMO_F64) return launch_typed<double2>(d, a.B, s);
     return launch_typed<float2>(d, a.B, s);
+}
+
+size_t beamform_multi_workspace_bytes(int P, const int* precoders, int64_t B, int K, int64_t M,
+                                      int prec) {
+    size_t n = 0;
+    for (int i = 0; i < P; ++i) n += ws_align(beamform_workspace_bytes(precoders[i], B, K, M, prec));
+    return n;
+}
+
+dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* precoders,
+                                   hipStream_t s) {
+    if (P < 1 || P > kMultiMax) return fail(DMIMO_E_SHAPE, "beamform: 1 <= P <= 8 precoders");
+    if (a.B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "beamform: B too large");
+    if (a.K <= kSmallK && a.M <= small_max_m(a.prec)) {
+        // every precoder on the one-pass kernel: precoder p on grid row p
+        BfDev d;
+        d.precoder = precoders[0];
+        for (int i = 0; i < kMultiMax; ++i) d.precs[i] = precoders[i < P ? i : 0];
+        d.B = a.B;
+        d.K = a.K;
+        d.M = a.M;
+        d.H = a.H;
+        for (int k = 0; k < DMIMO_K_MAX; ++k) d.gamma[k] = a.gamma[k];
+        d.sigma2 = a.sigma2;
+        d.p_total = a.p_total;
+        d.pivot_tol = a.prec == DMIMO_F64 ? 1e-12 : 1e-6;
+        d.W = a.W;
+        d.p_ant = a.p_ant;
+        d.l21 = a.l21;
+        d.sinr = a.sinr;
+        d.rsum = a.rsum;
+        d.info = a.info;
+        d.G = a.ws;
+        if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, P, s);
+        return launch_small<float2, kSmallMaxM>(d, a.B, P, s);
+    }
+    // otherwise one call per precoder, in order, each with its workspace slice
+    const size_t esz = a.prec == DMIMO_F64 ? 16 : 8;
+    char* ws = static_cast<char*>(a.ws);
+    for (int i = 0; i < P; ++i) {
+        BeamformArgs one = a;
+        one.precoder = precoders[i];
+        const int64_t r = i;
+        one.W = static_cast<char*>(a.W) + r * a.B * a.K * a.M * esz;
+        one.p_ant = a.p_ant ? a.p_ant + r * a.B * a.M : nullptr;
+        one.l21 = a.l21 ? a.l21 + r * a.B : nullptr;
+        one.sinr = a.sinr ? a.sinr + r * a.B * a.K : nullptr;
+        one.rsum = a.rsum ? a.rsum + r * a.B : nullptr;
+        one.info = a.info ? a.info + r * a.B : nullptr;
+        one.ws = ws;
+        const dmimo_status st = launch_beamform(one, s);
+        if (st) return st;
+        ws += ws_align(beamform_workspace_bytes(precoders[i], a.B, a.K, a.M, a.prec));
+    }
+    return DMIMO_OK;
 }
 
 }  // namespace dmimo

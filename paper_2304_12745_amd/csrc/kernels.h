@@ -36,6 +36,13 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s);
 // G^-1 and per-tile shares when that path applies (few deployments, many
 // antennas).  MR and equal-gain MR: the wide path's per-tile shares, else 0.
 size_t beamform_workspace_bytes(int precoder, int64_t B, int K, int64_t M, int prec);
+// precoders[0 .. P) of the same channels (1 <= P <= 8): outputs of precoder p at
+// offset p of a leading [P] dimension, workspace slices in order, each rounded
+// up to 256 B.  One launch when every precoder takes the one-pass kernel
+// (precoder p on grid row p), else one launch_beamform per precoder.
+dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* precoders, hipStream_t s);
+size_t beamform_multi_workspace_bytes(int P, const int* precoders, int64_t B, int K, int64_t M,
+                                      int prec);
 
 // `maps` precoders over the same antennas and points, one launch: W
 // [maps][K][M], every output [maps][N] ([maps][N][K] per stream); map p is

@@ -59,6 +59,9 @@ _SIGS = {
                        _vp, _vp, _vp, _sz, _vp],
     "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
+    "dmimo_beamform_multi": [_i32, _vp, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp,
+                             _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+    "dmimo_beamform_multi_workspace_size": [_i32, _vp, _i32, _i32, _i32, _i32],
     "dmimo_powermap_batch": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _i32, _vp,
                              ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
@@ -89,7 +92,7 @@ _SIGS = {
     "dmimo_last_error": [],
     "dmimo_version": [],
 }
-_RESTYPES = {"dmimo_workspace_size": _sz, "dmimo_ufpgd_workspace_size": _sz, "dmimo_status_string": ctypes.c_char_p,
+_RESTYPES = {"dmimo_workspace_size": _sz, "dmimo_beamform_multi_workspace_size": _sz, "dmimo_ufpgd_workspace_size": _sz, "dmimo_status_string": ctypes.c_char_p,
              "dmimo_last_error": ctypes.c_char_p, "dmimo_version": ctypes.c_char_p}
 
 
@@ -262,6 +265,45 @@ def beamform(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f3
                                 _ptr(out.rsum), _ptr(out.info), _ptr(ws),
                                 ws.numel() if ws is not None else 0, _stream(stream)),
            "dmimo_beamform")
+    return out
+
+
+def beamform_multi(H, precoders=("mr", "zf"), gamma_lin=None, sigma2=1.0, p_total=0.0,
+                   prec="f32", outputs=True, out: Optional[BeamformResult] = None, ws=None,
+                   stream=None) -> BeamformResult:
+    """Several precoders of the same channels (dmimo_beamform_multi): every
+    output gains a leading [P] dimension (W [P][B][K][M]); the results equal
+    one beamform() per precoder bit for bit."""
+    import torch
+    prec = _prec(prec)
+    pcs = [PRECODERS[p] if isinstance(p, str) else int(p) for p in precoders]
+    P = len(pcs)
+    B, K, M = H.shape
+    dev = H.device
+    arr = (ctypes.c_int32 * max(P, 1))(*pcs)
+    if out is None:
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = BeamformResult(
+            torch.empty((P, B, K, M), dtype=_cdtype(prec), device=dev),
+            torch.empty((P, B, M), **f64) if outputs else None,
+            torch.empty((P, B), **f64) if outputs else None,
+            torch.empty((P, B, K), **f64) if outputs else None,
+            torch.empty((P, B), **f64) if outputs else None,
+            torch.empty((P, B), dtype=torch.int32, device=dev) if outputs else None)
+    need = lib().dmimo_beamform_multi_workspace_size(P, arr, B, K, M, prec)
+    if ws is None:
+        ws = getattr(out, "ws", None)
+    if need and (ws is None or ws.numel() < need):
+        ws = torch.empty((need,), dtype=torch.uint8, device=dev)
+    out.ws = ws
+    g = None
+    if gamma_lin is not None:
+        g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+    _check(lib().dmimo_beamform_multi(P, arr, B, K, M, _ptr(H), g, float(sigma2), float(p_total),
+                                      prec, _ptr(out.W), _ptr(out.p_ant), _ptr(out.l21),
+                                      _ptr(out.sinr), _ptr(out.rsum), _ptr(out.info), _ptr(ws),
+                                      ws.numel() if ws is not None else 0, _stream(stream)),
+           "dmimo_beamform_multi")
     return out
 
 

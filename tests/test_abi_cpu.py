@@ -120,6 +120,33 @@ def test_beamform_validation(lib):
     assert b"workspace" in lib.dmimo_last_error() or bf(ws_bytes=16) == 4
 
 
+def test_beamform_multi_validation(lib):
+    arr = (ctypes.c_int32 * 2)(D.MR, D.ZF)
+    def bm(P=2, pcs=arr, B=2, K=2, M=4, ws=FAKE, ws_bytes=1 << 20, W=FAKE):
+        return lib.dmimo_beamform_multi(P, pcs, B, K, M, FAKE, None, 1.0, 1.0, D.F32, W, None,
+                                        None, None, None, None, ws, ws_bytes, None)
+    assert bm(P=-1) == 2
+    assert bm(P=9) == 2
+    assert bm(P=0, pcs=None) == 0                # nothing to do
+    assert bm(pcs=None) == 1
+    assert bm(pcs=(ctypes.c_int32 * 2)(D.MR, 7)) == 3
+    assert bm(K=5, M=4) == 2                     # ZF needs K <= M
+    assert bm(ws=None) == 4                      # ZF's Gram slot
+    assert bm(W=None) == 1
+    assert bm(B=0) == 0
+    # the workspace: each precoder's size rounded up to 256 B, in order
+    a = lambda n: (n + 255) // 256 * 256
+    ws = lib.dmimo_workspace_size
+    assert lib.dmimo_beamform_multi_workspace_size(2, arr, 3, 5, 9, D.F64) == (
+        a(ws(D.CALL_BEAMFORM_MR, 3, 5, 9, 0, D.F64)) + a(ws(D.CALL_BEAMFORM_ZF, 3, 5, 9, 0, D.F64)))
+    wide = (ctypes.c_int32 * 3)(D.ZF, D.MR, D.ZF)
+    z = ws(D.CALL_BEAMFORM_ZF, 2, 32, 1024, 0, D.F32)
+    m = ws(D.CALL_BEAMFORM_MR, 2, 32, 1024, 0, D.F32)
+    assert m > 0 and z > m
+    assert lib.dmimo_beamform_multi_workspace_size(3, wide, 2, 32, 1024, D.F32) == a(z) + a(m) + a(z)
+    assert lib.dmimo_beamform_multi_workspace_size(2, (ctypes.c_int32 * 2)(D.MR, 9), 2, 2, 4, D.F32) == 0
+
+
 def test_powermap_batch_validation(lib):
     p = D.channel_params(3.5e9)
     pts = D.Points(D.PTS_GRID, 4, 4, 0, 0, 1, 1, 1, None, 0)

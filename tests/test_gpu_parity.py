@@ -449,6 +449,34 @@ def test_beamform_hall_mr_wide_path(D):
     assert abs(float(np.sum(np.abs(host(r.W)) ** 2)) - 1.0) < 1e-5
 
 
+# several precoders of the same channels in one call equal one call per
+# precoder bit for bit: the one-pass kernel with precoder p on grid row p
+# (FP32, FP64, FP16x3 Gram mode; ragged M; a singular deployment for ZF), and
+# the per-precoder sequence elsewhere (K = 12; the wide path at M = 600)
+@pytest.mark.parametrize("B,K,M,prec", [(1, 8, 64, "f32"), (5, 3, 37, "f64"), (7, 8, 256, "f16x3"),
+                                        (3, 12, 100, "f32"), (2, 6, 600, "f32")])
+def test_beamform_multi_equals_single_calls(D, B, K, M, prec):
+    import torch
+    say(f"beamform_multi B={B} K={K} M={M} prec={prec}")
+    rng = np.random.default_rng(B * 100 + K + M)
+    H = WL.complex_normal(rng, (B, K, M))
+    if B == 5:
+        H[0, 1] = H[0, 0]                      # ZF fails on deployment 0 only
+    Hd = dev(H if prec == "f64" else c64(H))
+    pcs = ["mr", "zf", "mr_phase", "zf"]
+    gamma = np.linspace(1, 3, K)
+    for p_total in (1.0, 0.0):
+        r = D.beamform_multi(Hd, pcs, gamma, 0.5, p_total, prec)
+        assert tuple(r.W.shape) == (len(pcs), B, K, M)
+        for i, pc in enumerate(pcs):
+            one = D.beamform(Hd, pc, gamma, 0.5, p_total, prec)
+            for x, y in ((r.W[i], one.W), (r.p_ant[i], one.p_ant), (r.l21[i], one.l21),
+                         (r.sinr[i], one.sinr), (r.rsum[i], one.rsum), (r.info[i], one.info)):
+                assert torch.equal(x, y), (pc, p_total)
+    if B == 5:
+        assert host(r.info)[1, 0] > 0 and np.all(host(r.info)[1, 1:] == 0)
+
+
 def test_beamform_hall_zf_wide_path(D):
     # the hall's 32 users and 1024 APs (LoS, |h| ~ 1e-3) with the paper's
     # scaling at 10 dB targets, as the PA phase of bench.py forms it
