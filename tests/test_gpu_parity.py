@@ -475,6 +475,10 @@ def test_beamform_multi_equals_single_calls(D, B, K, M, prec):
                 assert torch.equal(x, y), (pc, p_total)
     if B == 5:
         assert host(r.info)[1, 0] > 0 and np.all(host(r.info)[1, 1:] == 0)
+    # W alone (every optional output NULL)
+    w_only = D.beamform_multi(Hd, pcs, gamma, 0.5, 1.0, prec, outputs=False)
+    for i, pc in enumerate(pcs):
+        assert torch.equal(w_only.W[i], D.beamform(Hd, pc, gamma, 0.5, 1.0, prec).W), pc
 
 
 def test_beamform_hall_zf_wide_path(D):
@@ -678,24 +682,29 @@ def test_powermap_hall_sampled(D, prec):
 # the kernel) equal one call per precoder bit for bit, in every kernel family:
 # FP32 VALU (K <= 2), FP32 MFMA (K <= 8, 16, 32), FP64, FP16x3, BF16x3; a
 # ragged grid (41 x 29) and a ragged antenna chunk (M = 70)
-@pytest.mark.parametrize("prec,K", [("f32", 2), ("f32", 8), ("f32", 12), ("f32", 32), ("f64", 8),
-                                    ("f16x3", 8), ("bf16x3", 20)])
-def test_powermap_batch_equals_single_maps(D, prec, K):
+@pytest.mark.parametrize("prec,K,kind", [("f32", 2, "grid"), ("f32", 8, "grid"), ("f32", 12, "grid"),
+                                         ("f32", 32, "grid"), ("f64", 8, "grid"), ("f16x3", 8, "grid"),
+                                         ("bf16x3", 20, "grid"), ("f32", 8, "list"), ("f64", 3, "list")])
+def test_powermap_batch_equals_single_maps(D, prec, K, kind):
     import torch
-    say(f"powermap batch of 3 precoders, K={K}, {prec}")
+    say(f"powermap batch of 3 precoders, K={K}, {prec}, {kind} points")
     rng = np.random.default_rng(K + 7)
     M, P = 70, 3
     aps = WL.uniform_positions(rng, M, 20, 20, 3.0)
     g = WL.Grid(0.0, 0.0, 20 / 41, 20 / 29, 1.2, 41, 29)
+    if kind == "grid":
+        pts, n = D.grid_points(g), g.nx * g.ny
+    else:
+        xyz = dev(WL.uniform_positions(rng, 1000, 20, 20, 1.2)[None])
+        pts, n = D.list_points(xyz, 1000), 1000
     Wn = WL.complex_normal(rng, (P, K, M)) * 0.05
     W = dev(Wn if prec == "f64" else c64(Wn))
     params = D.channel_params(3.5e9)
     apd = dev(aps)
-    r = D.powermap_batch(params, apd, W, D.grid_points(g), 1e-9, prec, want_per_stream=True)
-    assert tuple(r.power.shape) == (P, g.nx * g.ny)
+    r = D.powermap_batch(params, apd, W, pts, 1e-9, prec, want_per_stream=True)
+    assert tuple(r.power.shape) == (P, n)
     for p in range(P):
-        one = D.powermap(params, apd, W[p].contiguous(), D.grid_points(g), 1e-9, prec,
-                         want_per_stream=True)
+        one = D.powermap(params, apd, W[p].contiguous(), pts, 1e-9, prec, want_per_stream=True)
         for a, b in ((r.power[p], one.power), (r.sinr[p], one.sinr), (r.best_k[p], one.best_k),
                      (r.per_stream[p], one.per_stream)):
             assert torch.equal(a, b), p
