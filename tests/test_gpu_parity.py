@@ -656,6 +656,34 @@ def test_powermap_single_point_single_antenna(D):
     assert host(r.power)[0] == pytest.approx(5.1624e-6, rel=1e-4)
 
 
+# antennas in the map plane, some exactly on grid points (d = 0, the near-field
+# clamp active) and some within d_min of a row: the FP32 row loop keeps its
+# zero guard and clamp for those chunks (the guard-free loop runs only where
+# every antenna of the chunk is more than d_min off the row); K = 8, M = 70
+# (a ragged second chunk), against the oracle at every point
+def test_powermap_antennas_in_the_map_plane(D):
+    say("powermap: antennas in the map plane (guarded row loop), K=8, M=70")
+    rng = np.random.default_rng(5)
+    f = 3.5e9
+    g = WL.Grid(0.0, 0.0, 0.25, 0.25, 1.2, 64, 64)        # points at (i + 0.5) / 4
+    pts = grid_pts(g)
+    M, K = 70, 8
+    aps = WL.uniform_positions(rng, M, 16, 16, 4.0)
+    on = rng.choice(64 * 64, 12, replace=False)
+    aps[:12] = pts[on]                                    # on grid points, z = 1.2
+    aps[12:20, 2] = 1.2 + rng.uniform(-0.005, 0.005, 8)   # within d_min of the plane
+    users = WL.uniform_positions(rng, K, 16, 16, 1.2)
+    W = c64(O.mr_precoder(O.los_channel(users, aps, f), 1.0))
+    r = D.powermap(D.channel_params(f), dev(aps), dev(W), D.grid_points(g), 1e-12, "f32")
+    power = host(r.power)
+    assert np.all(np.isfinite(power)) and np.all(np.isfinite(host(r.sinr)))
+    Hg = O.los_channel(pts, aps, f)
+    Wc = W.astype(np.complex128)
+    check_db(power, O.power_map(Hg, Wc), MAP_TOL["f32"], what="power")
+    s_ref, _ = O.sinr_map(Hg, Wc, 1e-12)
+    check_db(host(r.sinr), s_ref, MAP_TOL["f32"], what="sinr")
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 def test_powermap_hall_sampled(D, prec):
     # the full-size hall map (N = 2048^2, M = 1024, K = 32) in one launch,
