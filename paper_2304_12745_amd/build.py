@@ -42,13 +42,24 @@ COMMON = [
 ]
 
 
+# Per-source extras.  The PGD-family kernels read their MFMA results on the
+# VALU every layer; the VGPR form of MFMA writes them to ordinary VGPRs, so
+# the layer loop needs no accumulator-register copies (16 fewer VALU
+# instructions per layer in pgd_mfma_kernel; the results are the same bits).
+EXTRA = {
+    "pgd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "ufpgd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "pgd_large.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
