@@ -256,8 +256,10 @@ dmimo_status launch_channel(const WaveConst& w, const PointsDev& P, bool rician,
         a.si = (int32_t)(a.sn - (int64_t)a.sj * P.nx);
     }
     dim3 grid((unsigned)blocks), block(256);
-    if (!f64 && !rician && apl == 0 && a.lds_ap && M % 2 == 0 && M >= 512 && P.n > 0 &&
-        ceil_div(P.n, kRowsPerWg) <= 0x7fffffff) {
+    // (at least 256 workgroups of rows; fewer rows, e.g. a deployment's users,
+    // keep one row per wave, which spreads them over more CUs)
+    if (!f64 && !rician && apl == 0 && a.lds_ap && M % 2 == 0 && M >= 512 &&
+        P.n >= 256 * kRowsPerWg && ceil_div(P.n, kRowsPerWg) <= 0x7fffffff) {
         channel_rows_kernel<<<dim3((unsigned)ceil_div(P.n, kRowsPerWg)), block, lds, s>>>(a);
         return check_launch("channel_rows_kernel");
     }

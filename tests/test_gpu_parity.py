@@ -152,6 +152,29 @@ def test_channel_wide_rows(D, M, B, kind):
             assert e <= tol, (prec, b, e)
 
 
+# one deployment with wide rows and at least 4096 points takes the row-per-
+# workgroup kernel (16 consecutive rows per workgroup, 16-byte stores of
+# antenna pairs): a grid of 4801 points (the last workgroup holds one row) and
+# a list of 4100, every term against the oracle
+@pytest.mark.parametrize("kind,n", [("grid", 4801), ("list", 4100)])
+def test_channel_rows_per_workgroup(D, kind, n):
+    say(f"channel rows per workgroup: {kind} N={n} M=1024")
+    rng = np.random.default_rng(n)
+    M, f = 1024, 5.8e9
+    aps = WL.uniform_positions(rng, M, 50, 50, 5.0)
+    if kind == "grid":
+        g = WL.Grid(0.0, 0.0, 50 / 4801, 50.0, 1.0, 4801, 1)
+        pts, desc = grid_pts(g), D.grid_points(g)
+    else:
+        pts = WL.uniform_positions(rng, n, 50, 50, 1.0)
+        desc = D.list_points(dev(pts[None]), n)
+    H = host(D.channel(D.channel_params(f), dev(aps[None]), desc, prec="f32"))[0]
+    ref = O.los_channel(pts, aps, f)
+    e = np.max(np.abs(H - ref) / np.abs(ref))
+    say(f"    max |dh|/|h| = {e:.2e}")
+    assert e <= 2e-6
+
+
 # the materialised channels bench.py times, in the same launch configuration:
 # the room's 512 x 512 grid x 64 APs (four antennas per lane) and the hall's
 # 2048 x 2048 grid x 1024 APs (34.4 GB; antenna coordinates in LDS); sampled
