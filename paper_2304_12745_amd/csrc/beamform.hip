@@ -1,6 +1,9 @@
 // Precoders and their epilogues, one 256-thread workgroup per deployment.
 // Deployments of at most 8 users and 256 antennas (128 in FP64) take the
-// one-pass kernel further down; the general kernel follows.
+// one-pass kernel further down (several precoders of the same channels in one
+// launch, precoder p on grid row p); calls of at most 64 deployments with
+// M > 448 take the wide path, which spreads each deployment over workgroups
+// of 64 antennas; the general kernel follows.
 //
 // ZF (eq. optim1 constraint H W^T = sigma D_gamma^{1/2}, or total-power
 // scaling) runs after the Gram kernel has written G = H H^H to the workspace:

@@ -11,6 +11,9 @@
 // over the rows.  A lane keeps its row as (b, n), and on a grid as
 // n = j nx + i, and advances them by the fixed stride with carries: the loop
 // has no integer division, which would cost as much as the terms of a row.
+// One deployment with wide rows and at least 4096 points (FP32 LoS, M even)
+// takes channel_rows_kernel instead: a workgroup writes whole rows together
+// with 16-byte stores of antenna pairs.
 #include <type_traits>
 
 #include "kernels.h"
