@@ -178,12 +178,18 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
     const int K = a.K;
     const int64_t base = wg_first + (int64_t)wave * (16 * PT);
 
+    const bool grid = a.P.kind == DMIMO_PTS_GRID;
+    const WgGrid wg = grid ? wg_grid(a, wg_first, 16 * PT * WAVES) : WgGrid{};
     double px[PT], py[PT], pz[PT];
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
-        int64_t n = base + 16 * t + col;
-        n = n < N ? n : N - 1;
-        point_rev(a, n, px[t], py[t], pz[t]);
+        if (grid) {
+            wg_point_rev(a, wg, wave * (16 * PT) + 16 * t + col, px[t], py[t], pz[t]);
+        } else {
+            int64_t n = base + 16 * t + col;
+            n = n < N ? n : N - 1;
+            point_rev(a, n, px[t], py[t], pz[t]);
+        }
     }
 
     f32x4 acc[PT][NT];
@@ -207,11 +213,10 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
     double ry = 0.0, rz = 0.0;
     const double dmin_rev = 1.0 / (double)a.inv_dmin_rev;
     const double far_c = 1.001 * dmin_rev * dmin_rev;
-    if (a.P.kind == DMIMO_PTS_GRID) {
-        const int64_t last = min(wg_first + (int64_t)16 * PT * WAVES, N) - 1;
-        row = wg_first / a.P.nx == last / a.P.nx;
+    if (grid) {
+        row = wg.one_row;
         double rx;
-        point_rev(a, wg_first < N ? wg_first : N - 1, rx, ry, rz);
+        wg_point_rev(a, wg, 0, rx, ry, rz);
     }
 
     for (int m0 = 0; m0 < M; m0 += kChunk) {
@@ -358,12 +363,18 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
     const float hscale = BF16 ? 1.0f : kHScale;
     const float amp_s = a.amp_rev * hscale;
 
+    const bool grid = a.P.kind == DMIMO_PTS_GRID;
+    const WgGrid wg = grid ? wg_grid(a, wg_first, 16 * PT * WAVES) : WgGrid{};
     double px[PT], py[PT], pz[PT];
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
-        int64_t n = base + 16 * t + (lane & 15);
-        n = n < N ? n : N - 1;
-        point_rev(a, n, px[t], py[t], pz[t]);
+        if (grid) {
+            wg_point_rev(a, wg, wave * (16 * PT) + 16 * t + (lane & 15), px[t], py[t], pz[t]);
+        } else {
+            int64_t n = base + 16 * t + (lane & 15);
+            n = n < N ? n : N - 1;
+            point_rev(a, n, px[t], py[t], pz[t]);
+        }
     }
 
     // One accumulator per tile.  For FP16 it holds the sum so far in units of
@@ -384,11 +395,10 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
     constexpr bool kRows = ROWS && NT >= 2 && !BF16;
     bool row = false;
     double ry = 0.0, rz = 0.0;
-    if (kRows && a.P.kind == DMIMO_PTS_GRID) {
-        const int64_t last = min(wg_first + (int64_t)16 * PT * WAVES, N) - 1;
-        row = wg_first / a.P.nx == last / a.P.nx;
+    if (kRows && grid) {
+        row = wg.one_row;
         double rx;
-        point_rev(a, wg_first < N ? wg_first : N - 1, rx, ry, rz);
+        wg_point_rev(a, wg, 0, rx, ry, rz);
     }
 
     // table item of this thread: (step, tile, lane) = 8 antennas

@@ -62,6 +62,45 @@ __device__ __forceinline__ void point_rev(const PmMapDev& a, int64_t n, double& 
     z *= a.inv_lam;
 }
 
+// Grid points of a workgroup, wg_first + o for 0 <= o < npts (npts <= 2^20),
+// by their offset from the workgroup's first point (i0, j0): one division per
+// workgroup, and none per point when the workgroup lies within one grid row.
+// Coordinates as point_rev, so the same bits.
+struct WgGrid {
+    int64_t first, last;   // wg_first, and its last point clamped to N - 1
+    int64_t i0, j0;
+    bool one_row;
+};
+
+__device__ __forceinline__ WgGrid wg_grid(const PmMapDev& a, int64_t wg_first, int npts) {
+    WgGrid w;
+    w.first = wg_first;
+    w.last = min(wg_first + (int64_t)npts, a.P.n) - 1;
+    w.j0 = wg_first / a.P.nx;
+    w.i0 = wg_first - w.j0 * a.P.nx;
+    w.one_row = w.i0 + (w.last - wg_first) < a.P.nx;
+    return w;
+}
+
+// Point min(wg_first + o, N - 1) in wavelengths.
+__device__ __forceinline__ void wg_point_rev(const PmMapDev& a, const WgGrid& w, int o, double& x,
+                                             double& y, double& z) {
+    const int64_t oc = min((int64_t)o, w.last - w.first);
+    int64_t i, j;
+    if (w.one_row) {
+        i = w.i0 + oc;
+        j = w.j0;
+    } else {
+        const uint32_t u = (uint32_t)(w.i0 + oc), nx = (uint32_t)a.P.nx;
+        const uint32_t q = u / nx;
+        i = u - q * nx;
+        j = w.j0 + q;
+    }
+    x = (a.P.x0 + ((double)i + 0.5) * a.P.dx) * a.inv_lam;
+    y = (a.P.y0 + ((double)j + 0.5) * a.P.dy) * a.inv_lam;
+    z = a.P.z * a.inv_lam;
+}
+
 // One spherical-wave term with every length in wavelengths.
 //   d2 = dx^2 + dy^2 + dz^2 (FP64).
 //   d  = sqrt(d2): an FP32 rsq seed refined by one FP64 Newton step
