@@ -152,7 +152,6 @@ def main():
     ap = torch.from_numpy(w.ap_xyz).to(dev)            # [1][M][3]
     ap0 = ap[0].contiguous()
     users = torch.from_numpy(w.user_xyz).to(dev)       # [1][K][3]
-    upts = D.list_points(users, K)
     gpts = D.grid_points(w.grid)
     H = torch.empty((1, K, M), dtype=torch.complex64, device=dev)
 
@@ -161,11 +160,11 @@ def main():
     cp_dst = torch.empty_like(cp_src)
     cp_dst.copy_(cp_src)
 
-    ms_per_step, map_launch_ms, maps, bf = run_steps(args, "f32", w, D, params, ap, ap0, upts,
+    ms_per_step, map_launch_ms, maps, bf = run_steps(args, "f32", w, D, params, ap, ap0, users,
                                                      gpts, H)
     mixed = None
     if not args.no_mixed:
-        ms_mix, launch_mix, maps_mix, _ = run_steps(args, "f16x3", w, D, params, ap, ap0, upts,
+        ms_mix, launch_mix, maps_mix, _ = run_steps(args, "f16x3", w, D, params, ap, ap0, users,
                                                     gpts, H)
         dev_db = {}
         for p in ("mr", "zf"):
@@ -262,13 +261,14 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
+def run_steps(args, prec, w, D, params, ap, ap0, users, gpts, H):
     """Warm up, then time exactly args.steps steps of the room workload.
 
-    One step, in order on torch's current stream: the user channel; the MR
-    and ZF precoders of those channels (Gram and inverse inside) in one
-    dmimo_beamform_multi launch, W written into one [2][K][M] array; the MR
-    and ZF maps in one dmimo_powermap_batch launch (map p on grid row p).  One pair of HIP events on that stream brackets the map
+    One step, in order on torch's current stream: the user channels and the
+    MR and ZF precoders of those channels (Gram and inverse inside) in one
+    dmimo_beamform_users launch, H written to ``H`` and W into one [2][K][M]
+    array; the MR and ZF maps in one dmimo_powermap_batch launch (map p on
+    grid row p).  One pair of HIP events on that stream brackets the map
     launch of every args.event_every-th timed step (a pair on every step
     adds about 7 us per step).  (A variant with the MR branch on a second
     stream was measured slower: 0.114 vs 0.094 ms/step, because the
@@ -284,14 +284,14 @@ def run_steps(args, prec, w, D, params, ap, ap0, upts, gpts, H):
     maps = {p: D.MapResult(both.power[i], both.sinr[i], both.best_k[i], None)
             for i, p in enumerate(("mr", "zf"))}
     pcs = ("mr", "zf")
-    pre = D.beamform_multi(H, pcs, None, w.sigma2, w.p_total, prec)   # outputs [2][1][...]
+    pre = D.beamform_users(params, ap, users, pcs, None, w.sigma2, w.p_total, prec,
+                           H=H)                                     # outputs [2][1][...]
     Wst = pre.W.view(2, K, M)
     bf = {p: D.BeamformResult(pre.W[i], pre.p_ant[i], pre.l21[i], pre.sinr[i], pre.rsum[i],
                               pre.info[i]) for i, p in enumerate(pcs)}
 
     def step(e=None):
-        D.channel(params, ap, upts, prec="f32", out=H)
-        D.beamform_multi(H, pcs, None, w.sigma2, w.p_total, prec, out=pre)
+        D.beamform_users(params, ap, users, pcs, None, w.sigma2, w.p_total, prec, out=pre)
         if e is not None:
             e[0].record()
         D.powermap_batch(params, ap0, Wst, gpts, w.sigma2, prec, out=both)

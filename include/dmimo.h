@@ -188,6 +188,28 @@ dmimo_status dmimo_beamform_multi(int32_t P, const int32_t* precoders, int32_t B
                                   double sigma2, double p_total, int32_t prec, void* W,
                                   double* p_ant, double* l21, double* sinr, double* rsum,
                                   int32_t* info, void* ws, size_t ws_bytes, void* stream);
+/* The users' LoS channels and several precoders of them in one call, the
+ * channel synthesis of dmimo_channel and the precoders that Sec. VI compares:
+ * H = dmimo_channel(params, B, M, ap_xyz, list points user_xyz,
+ * out = DMIMO_F64 if prec is DMIMO_F64 else DMIMO_F32), then
+ * dmimo_beamform_multi(P, precoders, ..., H, ...), with the same results bit
+ * for bit.  For the one-pass shapes (K <= 8, M <= 256; 128 for DMIMO_F64) one
+ * launch does both: each workgroup synthesises its deployment's K x M terms
+ * with the channel kernel's arithmetic instead of reading H, and the
+ * workgroups of the first precoder write H.  Other shapes launch the channel
+ * kernel, then the precoders.
+ *   params     LoS model only (DMIMO_E_UNSUPPORTED otherwise).
+ *   ap_xyz     device FP64 [B][M][3]; user_xyz device FP64 [B][K][3].
+ *   H          device [B][K][M] output, complex FP64 for prec DMIMO_F64, else
+ *              complex FP32.
+ *   Every other argument, and the workspace, as for dmimo_beamform_multi. */
+dmimo_status dmimo_beamform_users(int32_t P, const int32_t* precoders,
+                                  const dmimo_channel_params* params, int32_t B, int32_t K,
+                                  int32_t M, const double* ap_xyz, const double* user_xyz,
+                                  const double* gamma_lin, double sigma2, double p_total,
+                                  int32_t prec, void* H, void* W, double* p_ant, double* l21,
+                                  double* sinr, double* rsum, int32_t* info, void* ws,
+                                  size_t ws_bytes, void* stream);
 /* Workspace bytes of dmimo_beamform_multi (0 for an invalid list).  Pure host
  * function. */
 size_t dmimo_beamform_multi_workspace_size(int32_t P, const int32_t* precoders, int32_t B,

@@ -304,6 +304,40 @@ dmimo_status dmimo_beamform_multi(int32_t P, const int32_t* precoders, int32_t B
                                  P, precoders, as_stream(stream));
 }
 
+dmimo_status dmimo_beamform_users(int32_t P, const int32_t* precoders,
+                                  const dmimo_channel_params* params, int32_t B, int32_t K,
+                                  int32_t M, const double* ap_xyz, const double* user_xyz,
+                                  const double* gamma_lin, double sigma2, double p_total,
+                                  int32_t prec, void* H, void* W, double* p_ant, double* l21,
+                                  double* sinr, double* rsum, int32_t* info, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    clear_error();
+    WaveConst w;
+    dmimo_status st = make_wave_const(params, &w);
+    if (st) return st;
+    if (params->model != DMIMO_CH_LOS)
+        return fail(DMIMO_E_UNSUPPORTED, "beamform_users: LoS channel model only");
+    if (P < 0 || P > 8) return fail(DMIMO_E_SHAPE, "beamform_users: 0 <= P <= 8");
+    if (P > 0 && !precoders) return fail(DMIMO_E_ARG, "beamform_users: NULL precoders");
+    double gam[DMIMO_K_MAX];
+    for (int i = 0; i < P; ++i) {
+        st = check_beamform(precoders[i], B, K, M, sigma2, p_total, prec, sinr ? sinr : rsum,
+                            gamma_lin, gam);
+        if (st) return st;
+    }
+    if (P == 0 || B == 0) return DMIMO_OK;
+    if (!ap_xyz || !user_xyz) return fail(DMIMO_E_ARG, "beamform_users: NULL ap_xyz or user_xyz");
+    if (!H || !W) return fail(DMIMO_E_ARG, "beamform_users: NULL H or W");
+    const size_t need = dmimo_beamform_multi_workspace_size(P, precoders, B, K, M, prec);
+    if (need > 0 && (!ws || ws_bytes < need)) {
+        set_error("beamform_users: workspace needs %zu bytes, got %zu", need, ws ? ws_bytes : 0);
+        return DMIMO_E_WORKSPACE;
+    }
+    return launch_beamform_users(beamform_args(precoders[0], B, K, M, H, gam, sigma2, p_total,
+                                               prec, W, p_ant, l21, sinr, rsum, info, ws),
+                                 P, precoders, w, ap_xyz, user_xyz, as_stream(stream));
+}
+
 size_t dmimo_beamform_multi_workspace_size(int32_t P, const int32_t* precoders, int32_t B,
                                            int32_t K, int32_t M, int32_t prec) {
     if (P < 1 || P > 8 || !precoders || B <= 0 || K <= 0 || M <= 0) return 0;

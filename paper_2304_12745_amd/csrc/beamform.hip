@@ -1,7 +1,8 @@
 // Precoders and their epilogues, one 256-thread workgroup per deployment.
 // Deployments of at most 8 users and 256 antennas (128 in FP64) take the
 // one-pass kernel further down (several precoders of the same channels in one
-// launch, precoder p on grid row p); calls of at most 64 deployments with
+// launch, precoder p on grid row p; it can also synthesise the users' LoS
+// channels itself and write them out); calls of at most 64 deployments with
 // M > 448 take the wide path, which spreads each deployment over workgroups
 // of 64 antennas; the general kernel follows.
 //
@@ -55,7 +56,29 @@ struct BfDev {
     double* rsum;
     int32_t* info;
     const void* G;
+    // one-pass kernel only: the users' channels synthesised in the kernel
+    // (user_xyz != NULL) from [B][K][3] users and [B][M][3] antennas, and
+    // written to H_out by grid row 0
+    const double* user_xyz;
+    const double* ap_xyz;
+    double inv_lam, amp_c, inv_dmin;
+    void* H_out;
 };
+
+// One LoS term of the channel synthesis, with the channel kernel's arithmetic
+// (the same bits): h = amp (cos - j sin) of the FP32 or FP64 term.
+template <typename T2>
+__device__ __forceinline__ T2 synth_term(const BfDev& a, double dx, double dy, double dz);
+template <>
+__device__ __forceinline__ float2 synth_term<float2>(const BfDev& a, double dx, double dy, double dz) {
+    const TermF32 t = wave_term_f32(dx, dy, dz, a.inv_lam, (float)a.amp_c, (float)a.inv_dmin);
+    return make_float2(t.amp * t.c, -t.amp * t.s);
+}
+template <>
+__device__ __forceinline__ double2 synth_term<double2>(const BfDev& a, double dx, double dy, double dz) {
+    const TermF64 t = wave_term_f64(dx, dy, dz, a.inv_lam, a.amp_c, a.inv_dmin);
+    return make_double2(t.amp * t.c, -t.amp * t.s);
+}
 
 template <typename T2>
 __device__ __forceinline__ double2 to_d2(T2 v) {
@@ -733,11 +756,26 @@ __global__ __launch_bounds__(kThreads) void beamform_small_kernel(BfDev a) {
 
     // 1.
     double f = 0.0;
-    for (int e = tid; e < K * M; e += kThreads) {
-        const int k = e / M, c = e - k * M;
-        const T2 v = Hb[e];
-        S.h[k][c] = v;
-        f += (double)v.x * v.x + (double)v.y * v.y;
+    if (a.user_xyz) {
+        // the users' channels of this deployment, synthesised here
+        const double* ub = a.user_xyz + b * K * 3;
+        const double* apb = a.ap_xyz + b * M * 3;
+        T2* Ho = reinterpret_cast<T2*>(a.H_out) + b * K * M;
+        for (int e = tid; e < K * M; e += kThreads) {
+            const int k = e / M, c = e - k * M;
+            const T2 v = synth_term<T2>(a, ub[3 * k + 0] - apb[3 * c + 0], ub[3 * k + 1] - apb[3 * c + 1],
+                                        ub[3 * k + 2] - apb[3 * c + 2]);
+            S.h[k][c] = v;
+            if (row == 0) Ho[e] = v;
+            f += (double)v.x * v.x + (double)v.y * v.y;
+        }
+    } else {
+        for (int e = tid; e < K * M; e += kThreads) {
+            const int k = e / M, c = e - k * M;
+            const T2 v = Hb[e];
+            S.h[k][c] = v;
+            f += (double)v.x * v.x + (double)v.y * v.y;
+        }
     }
     f = wave_sum(f);
     if (lane == 0) S.red[wv] = f;
@@ -1015,6 +1053,10 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
     d.rsum = a.rsum;
     d.info = a.info;
     d.G = a.ws;
+    d.user_xyz = nullptr;
+    d.ap_xyz = nullptr;
+    d.inv_lam = d.amp_c = d.inv_dmin = 0.0;
+    d.H_out = nullptr;
     if (a.K <= kSmallK && a.M <= small_max_m(a.prec)) {
         // G is formed in FP64 in the kernel, so the FP64 Gram's tolerance
         // applies to FP64 input and the FP32 one to every other mode
@@ -1044,10 +1086,13 @@ size_t beamform_multi_workspace_bytes(int P, const int* precoders, int64_t B, in
     return n;
 }
 
-dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* precoders,
-                                   hipStream_t s) {
+namespace {
+
+dmimo_status multi_impl(const BeamformArgs& a, int P, const int* precoders, const WaveConst* w,
+                        const double* ap_xyz, const double* user_xyz, hipStream_t s) {
     if (P < 1 || P > kMultiMax) return fail(DMIMO_E_SHAPE, "beamform: 1 <= P <= 8 precoders");
     if (a.B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "beamform: B too large");
+    const bool synth = user_xyz != nullptr;
     if (a.K <= kSmallK && a.M <= small_max_m(a.prec)) {
         // every precoder on the one-pass kernel: precoder p on grid row p
         BfDev d;
@@ -1068,8 +1113,26 @@ dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* prec
         d.rsum = a.rsum;
         d.info = a.info;
         d.G = a.ws;
+        d.user_xyz = user_xyz;
+        d.ap_xyz = ap_xyz;
+        d.inv_lam = synth ? w->inv_lam : 0.0;
+        d.amp_c = synth ? w->amp_c : 0.0;
+        d.inv_dmin = synth ? w->inv_dmin : 0.0;
+        d.H_out = synth ? const_cast<void*>(a.H) : nullptr;
         if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, P, s);
         return launch_small<float2, kSmallMaxM>(d, a.B, P, s);
+    }
+    if (synth) {
+        // the channel kernel first, then the precoders from H
+        PointsDev up;
+        up.kind = DMIMO_PTS_LIST;
+        up.nx = up.ny = 0;
+        up.x0 = up.y0 = up.dx = up.dy = up.z = 0.0;
+        up.xyz = user_xyz;
+        up.n = a.K;
+        const dmimo_status st = launch_channel(*w, up, false, a.B, a.M, ap_xyz, nullptr,
+                                               a.prec == DMIMO_F64, const_cast<void*>(a.H), s);
+        if (st) return st;
     }
     // otherwise one call per precoder, in order, each with its workspace slice
     const size_t esz = a.prec == DMIMO_F64 ? 16 : 8;
@@ -1090,6 +1153,19 @@ dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* prec
         ws += ws_align(beamform_workspace_bytes(precoders[i], a.B, a.K, a.M, a.prec));
     }
     return DMIMO_OK;
+}
+
+}  // namespace
+
+dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* precoders,
+                                   hipStream_t s) {
+    return multi_impl(a, P, precoders, nullptr, nullptr, nullptr, s);
+}
+
+dmimo_status launch_beamform_users(const BeamformArgs& a, int P, const int* precoders,
+                                   const WaveConst& w, const double* ap_xyz, const double* user_xyz,
+                                   hipStream_t s) {
+    return multi_impl(a, P, precoders, &w, ap_xyz, user_xyz, s);
 }
 
 }  // namespace dmimo

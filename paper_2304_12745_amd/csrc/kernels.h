@@ -43,6 +43,12 @@ size_t beamform_workspace_bytes(int precoder, int64_t B, int K, int64_t M, int p
 dmimo_status launch_beamform_multi(const BeamformArgs& a, int P, const int* precoders, hipStream_t s);
 size_t beamform_multi_workspace_bytes(int P, const int* precoders, int64_t B, int K, int64_t M,
                                       int prec);
+// launch_beamform_multi of the users' LoS channels, H ([B][K][M], a.H) written
+// by the call: for the one-pass shapes synthesised inside the precoder kernel
+// (the channel kernel's terms, the same bits), else by the channel kernel first.
+dmimo_status launch_beamform_users(const BeamformArgs& a, int P, const int* precoders,
+                                   const WaveConst& w, const double* ap_xyz, const double* user_xyz,
+                                   hipStream_t s);
 
 // `maps` precoders over the same antennas and points, one launch: W
 // [maps][K][M], every output [maps][N] ([maps][N][K] per stream); map p is

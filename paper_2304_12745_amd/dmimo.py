@@ -62,6 +62,9 @@ _SIGS = {
     "dmimo_beamform_multi": [_i32, _vp, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp,
                              _vp, _vp, _vp, _vp, _vp, _sz, _vp],
     "dmimo_beamform_multi_workspace_size": [_i32, _vp, _i32, _i32, _i32, _i32],
+    "dmimo_beamform_users": [_i32, _vp, ctypes.POINTER(ChannelParams), _i32, _i32, _i32, _vp, _vp,
+                             _vp, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                             _vp],
     "dmimo_powermap_batch": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _i32, _vp,
                              ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_workspace_size": [_i32, _i32, _i32, _i32, _i32, _i32],
@@ -304,6 +307,59 @@ def beamform_multi(H, precoders=("mr", "zf"), gamma_lin=None, sigma2=1.0, p_tota
                                       _ptr(out.sinr), _ptr(out.rsum), _ptr(out.info), _ptr(ws),
                                       ws.numel() if ws is not None else 0, _stream(stream)),
            "dmimo_beamform_multi")
+    return out
+
+
+def beamform_users(params: ChannelParams, ap_xyz, user_xyz, precoders=("mr", "zf"),
+                   gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f32", outputs=True,
+                   out: Optional[BeamformResult] = None, H=None, ws=None,
+                   stream=None) -> BeamformResult:
+    """The users' LoS channels and several precoders of them
+    (dmimo_beamform_users): ap_xyz float64 [B][M][3], user_xyz float64
+    [B][K][3]; H [B][K][M] is written to ``H`` (allocated if None) and kept
+    as ``out.H``.  The results equal channel() followed by beamform_multi()
+    bit for bit."""
+    import torch
+    prec = _prec(prec)
+    pcs = [PRECODERS[p] if isinstance(p, str) else int(p) for p in precoders]
+    P = len(pcs)
+    B, M = ap_xyz.shape[0], ap_xyz.shape[1]
+    K = user_xyz.shape[1]
+    if tuple(user_xyz.shape) != (B, K, 3) or tuple(ap_xyz.shape) != (B, M, 3):
+        raise ValueError("beamform_users: ap_xyz [B][M][3] and user_xyz [B][K][3]")
+    if not (ap_xyz.is_contiguous() and user_xyz.is_contiguous()):
+        raise ValueError("beamform_users: contiguous coordinates required")
+    dev = ap_xyz.device
+    arr = (ctypes.c_int32 * max(P, 1))(*pcs)
+    if H is None:
+        H = getattr(out, "H", None)
+    if H is None:
+        H = torch.empty((B, K, M), dtype=_cdtype(prec), device=dev)
+    if out is None:
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = BeamformResult(
+            torch.empty((P, B, K, M), dtype=_cdtype(prec), device=dev),
+            torch.empty((P, B, M), **f64) if outputs else None,
+            torch.empty((P, B), **f64) if outputs else None,
+            torch.empty((P, B, K), **f64) if outputs else None,
+            torch.empty((P, B), **f64) if outputs else None,
+            torch.empty((P, B), dtype=torch.int32, device=dev) if outputs else None)
+    out.H = H
+    need = lib().dmimo_beamform_multi_workspace_size(P, arr, B, K, M, prec)
+    if ws is None:
+        ws = getattr(out, "ws", None)
+    if need and (ws is None or ws.numel() < need):
+        ws = torch.empty((need,), dtype=torch.uint8, device=dev)
+    out.ws = ws
+    g = None
+    if gamma_lin is not None:
+        g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+    _check(lib().dmimo_beamform_users(P, arr, ctypes.byref(params), B, K, M, _ptr(ap_xyz),
+                                      _ptr(user_xyz), g, float(sigma2), float(p_total), prec,
+                                      _ptr(H), _ptr(out.W), _ptr(out.p_ant), _ptr(out.l21),
+                                      _ptr(out.sinr), _ptr(out.rsum), _ptr(out.info), _ptr(ws),
+                                      ws.numel() if ws is not None else 0, _stream(stream)),
+           "dmimo_beamform_users")
     return out
 
 

@@ -147,6 +147,29 @@ def test_beamform_multi_validation(lib):
     assert lib.dmimo_beamform_multi_workspace_size(2, (ctypes.c_int32 * 2)(D.MR, 9), 2, 2, 4, D.F32) == 0
 
 
+def test_beamform_users_validation(lib):
+    arr = (ctypes.c_int32 * 2)(D.MR, D.ZF)
+    los = D.channel_params(3.5e9)
+    def bu(P=2, pcs=arr, prm=los, B=2, K=2, M=4, ap=FAKE, us=FAKE, H=FAKE, W=FAKE, ws=FAKE,
+           ws_bytes=1 << 20):
+        return lib.dmimo_beamform_users(P, pcs, ctypes.byref(prm), B, K, M, ap, us, None, 1.0,
+                                        1.0, D.F32, H, W, None, None, None, None, None, ws,
+                                        ws_bytes, None)
+    assert bu(prm=D.channel_params(3.5e9, model=D.CH_RICIAN, kappa_lin=4.0)) == 6
+    assert bu(prm=D.channel_params(-1.0)) == 1
+    assert bu(P=9) == 2
+    assert bu(pcs=None) == 1
+    assert bu(pcs=(ctypes.c_int32 * 2)(D.MR, 7)) == 3
+    assert bu(K=5, M=4) == 2                     # ZF needs K <= M
+    assert bu(ap=None) == 1
+    assert bu(us=None) == 1
+    assert bu(H=None) == 1
+    assert bu(W=None) == 1
+    assert bu(ws=None) == 4
+    assert bu(B=0, ap=None, us=None, H=None, W=None) == 0
+    assert bu(P=0, pcs=None) == 0
+
+
 def test_powermap_batch_validation(lib):
     p = D.channel_params(3.5e9)
     pts = D.Points(D.PTS_GRID, 4, 4, 0, 0, 1, 1, 1, None, 0)

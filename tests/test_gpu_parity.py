@@ -504,6 +504,42 @@ def test_beamform_multi_equals_single_calls(D, B, K, M, prec):
         assert torch.equal(w_only.W[i], D.beamform(Hd, pc, gamma, 0.5, 1.0, prec).W), pc
 
 
+@pytest.mark.parametrize("B,K,M,prec,d_min", [
+    (3, 4, 64, "f32", 0.0),        # one launch, synthesis in the precoder kernel
+    (2, 8, 256, "bf16x3", 2.5),    # one launch, near-field clamp on some terms
+    (2, 8, 128, "f64", 2.5),       # one launch, FP64 terms
+    (2, 12, 300, "f32", 0.0),      # channel kernel, then the precoders
+    (1, 9, 600, "f64", 0.0),       # channel kernel, then the wide path
+])
+def test_beamform_users_equals_channel_then_multi(D, B, K, M, prec, d_min):
+    import torch
+    say(f"beamform_users B={B} K={K} M={M} prec={prec} d_min={d_min}")
+    rng = np.random.default_rng(B * 1000 + K * 10 + M)
+    aps = np.stack([WL.uniform_positions(rng, M, 12, 12, 3.0) for _ in range(B)])
+    users = np.stack([WL.uniform_positions(rng, K, 12, 12, 1.5) for _ in range(B)])
+    params = D.channel_params(3.5e9, D.CH_LOS, 0.0, d_min)
+    ap_d, us_d = dev(aps), dev(users)
+    pcs = ["mr", "zf", "mr_phase"]
+    gamma = np.linspace(1, 2, K)
+    ch = "f64" if prec == "f64" else "f32"
+    H_ref = D.channel(params, ap_d, D.list_points(us_d, K), prec=ch)
+    ref = D.beamform_multi(H_ref, pcs, gamma, 1e-10, 0.0, prec)
+    r = D.beamform_users(params, ap_d, us_d, pcs, gamma, 1e-10, 0.0, prec)
+    assert torch.equal(r.H, H_ref)
+    for x, y in ((r.W, ref.W), (r.p_ant, ref.p_ant), (r.l21, ref.l21), (r.sinr, ref.sinr),
+                 (r.rsum, ref.rsum), (r.info, ref.info)):
+        assert torch.equal(x, y)
+    # the channel itself against the oracle's LoS definition
+    Ho = np.stack([O.los_channel(users[b], aps[b], 3.5e9, d_min=d_min) for b in range(B)])
+    err = np.abs(host(r.H) - Ho).max() / np.abs(Ho).max()
+    assert err < (1e-12 if prec == "f64" else 2e-6)
+    # second call into the same outputs, precoders in another order, W alone
+    r2 = D.beamform_users(params, ap_d, us_d, ["zf", "mr"], gamma, 1e-10, 1.0, prec,
+                          outputs=False)
+    ref2 = D.beamform_multi(H_ref, ["zf", "mr"], gamma, 1e-10, 1.0, prec, outputs=False)
+    assert torch.equal(r2.H, H_ref) and torch.equal(r2.W, ref2.W)
+
+
 def test_beamform_hall_zf_wide_path(D):
     # the hall's 32 users and 1024 APs (LoS, |h| ~ 1e-3) with the paper's
     # scaling at 10 dB targets, as the PA phase of bench.py forms it
