@@ -5,10 +5,11 @@ Workload ("room"): M = 64 APs on a jittered 8x8 ceiling grid (pitch 2.5 m,
 z = 4 m) of a 20x20x4 m room, 3.5 GHz, K = 8 users at z = 1.2 m, noise -90 dBm.
 One step is one pass of the whole path, with inputs already resident in HBM:
 
-  1. dmimo_channel   user channels H (K x M, complex64)
-  2. dmimo_beamform_multi  MR and ZF at 1 W in one launch (+ p_m, L2,1,
-                           SINR_k, R_sum); ZF with its FP64 Gram and inverse
-  3. dmimo_powermap_batch  MR and ZF power + SINR + best-stream maps, 512 x 512
+  1. dmimo_beamform_users  user channels H (K x M, complex64, synthesised in
+                           the launch and written out), and MR and ZF of them
+                           at 1 W (+ p_m, L2,1, SINR_k, R_sum) in one launch;
+                           ZF with its FP64 Gram and inverse
+  2. dmimo_powermap_batch  MR and ZF power + SINR + best-stream maps, 512 x 512
                            grid at z = 1.2 m, both maps in one launch
 
 value = channel terms h[n,m] synthesised and consumed per second, over the
