@@ -540,6 +540,27 @@ def test_beamform_users_equals_channel_then_multi(D, B, K, M, prec, d_min):
     assert torch.equal(r2.H, H_ref) and torch.equal(r2.W, ref2.W)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_beamform_users_room_step(D, prec):
+    # the room's users and APs at the benchmark's precoder settings (MR and ZF
+    # at 1 W), against the separate calls and the oracle's channel
+    import torch
+    say(f"beamform_users room K=8 M=64 prec={prec}")
+    w = WL.room_workload(nx=8, ny=8)
+    params = D.channel_params(w.freq_hz)
+    ap_d, us_d = dev(w.ap_xyz), dev(w.user_xyz)
+    H_ref = D.channel(params, ap_d, D.list_points(us_d, w.K), prec="f32")
+    ref = D.beamform_multi(H_ref, ["mr", "zf"], None, w.sigma2, w.p_total, prec)
+    r = D.beamform_users(params, ap_d, us_d, ["mr", "zf"], None, w.sigma2, w.p_total, prec)
+    assert torch.equal(r.H, H_ref)
+    for x, y in ((r.W, ref.W), (r.p_ant, ref.p_ant), (r.l21, ref.l21), (r.sinr, ref.sinr),
+                 (r.rsum, ref.rsum), (r.info, ref.info)):
+        assert torch.equal(x, y)
+    Ho = _room_users(w)
+    assert np.abs(host(r.H) - Ho).max() / np.abs(Ho).max() < 2e-6
+    assert host(r.p_ant).sum(axis=(1, 2)) == pytest.approx([w.p_total, w.p_total], rel=1e-5)
+
+
 def test_beamform_hall_zf_wide_path(D):
     # the hall's 32 users and 1024 APs (LoS, |h| ~ 1e-3) with the paper's
     # scaling at 10 dB targets, as the PA phase of bench.py forms it
