@@ -7,9 +7,12 @@
 //   * admission: pending queries are admitted while a slot is free and
 //     their HBM footprint (server scratch + output maps) fits the budget.
 //     The scratch comes from one arena allocated at creation; nothing is
-//     allocated afterwards.  An admitted query gets its user channel
-//     (channel kernel) and precoder (beamform kernel; for ZF the Gram and an
-//     FP64 inverse) on the server stream.
+//     allocated afterwards.  An admitted query gets its user channel and
+//     precoder on the server stream: for MR and ZF one launch of the
+//     one-pass beamform kernel, which synthesises the channel itself (ZF
+//     with its Gram and FP64 inverse), for other shapes the channel kernel
+//     and then the beamform kernels; for DMIMO_PA the channel kernel and
+//     the PA-aware precoder.
 //   * ticks: each tick is one launch of serve_kernel, a fixed grid that
 //     loops over a list of (query, 128- or 256-point tile) work items.  The
 //     items come from every active query, smallest remaining work first,
@@ -268,8 +271,8 @@ bool ServerImpl::admit_one(Query* q) {
     up.xyz = d_users;
     up.n = K;
     const double* ap = reinterpret_cast<const double*>(arena_base + d.off);
-    ok = ok && launch_channel(d.w, up, false, 1, d.M, ap, nullptr, false, H, stream) == DMIMO_OK;
     if (q->precoder == DMIMO_PA) {
+        ok = ok && launch_channel(d.w, up, false, 1, d.M, ap, nullptr, false, H, stream) == DMIMO_OK;
         void* pa_ws = base + users_b + h_b + w_b + g_b;
         ok = ok && launch_pa_precoder(1, K, d.M, H, pa_gamma, q->sigma2, pa_layers, pa_lam, pa_eta,
                                       W, nullptr, nullptr, nullptr, nullptr, pa_ws, DMIMO_F32,
@@ -288,7 +291,8 @@ bool ServerImpl::admit_one(Query* q) {
         ba.prec = q->prec;
         ba.W = W;
         ba.ws = G;
-        ok = ok && launch_beamform(ba, stream) == DMIMO_OK;
+        const int pc = q->precoder;
+        ok = ok && launch_beamform_users(ba, 1, &pc, d.w, ap, d_users, stream) == DMIMO_OK;
     }
     // map descriptor of the slot
     PmMapDev& m = h_slots[q->slot];
