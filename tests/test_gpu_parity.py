@@ -834,3 +834,41 @@ def test_powermap_batch_room_step_maps(D):
         one = D.powermap(params, apd, W[p].contiguous(), pts, w.sigma2, "f32")
         assert torch.equal(r.power[p], one.power) and torch.equal(r.sinr[p], one.sinr)
         assert torch.equal(r.best_k[p], one.best_k)
+
+
+def test_room_steps_on_two_streams_equal_one_stream(D):
+    # the benchmark's step (users' channels + MR/ZF in one launch, both maps in
+    # one launch) with steps alternating over two streams, each with its own
+    # outputs and no waits between them: every stream's outputs equal a
+    # single-stream step bit for bit
+    import torch
+    say("room step on two streams (128 x 128 maps)")
+    w = WL.room_workload(nx=128, ny=128)
+    K, M, N = w.K, w.M, w.grid.n
+    params = D.channel_params(w.freq_hz)
+    ap_d, us_d, gpts = dev(w.ap_xyz), dev(w.user_xyz), D.grid_points(w.grid)
+    ap0 = ap_d[0].contiguous()
+
+    def step(out_pre, out_maps, stream):
+        pre = D.beamform_users(params, ap_d, us_d, ("mr", "zf"), None, w.sigma2, w.p_total,
+                               "f32", out=out_pre, stream=stream)
+        maps = D.powermap_batch(params, ap0, pre.W.view(2, K, M), gpts, w.sigma2, "f32",
+                                out=out_maps, stream=stream)
+        return pre, maps
+
+    ref_pre, ref_maps = step(None, None, None)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [step(None, None, s) for s in streams]
+    torch.cuda.synchronize()
+    for i in range(40):
+        s = i % 2
+        step(outs[s][0], outs[s][1], streams[s])
+    torch.cuda.synchronize()
+    for pre, maps in outs:
+        assert torch.equal(pre.H, ref_pre.H) and torch.equal(pre.W, ref_pre.W)
+        assert torch.equal(pre.sinr, ref_pre.sinr) and torch.equal(pre.p_ant, ref_pre.p_ant)
+        for x, y in ((maps.power, ref_maps.power), (maps.sinr, ref_maps.sinr),
+                     (maps.best_k, ref_maps.best_k)):
+            assert torch.equal(x, y)
+    assert tuple(ref_maps.power.shape) == (2, N)
