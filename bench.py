@@ -137,8 +137,9 @@ def main():
     args = parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(grid points shard with no exchange; see the design notes).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the grid points of a map would shard across GPUs with no exchange).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
