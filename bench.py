@@ -187,9 +187,14 @@ def main():
             b = maps[p].power.double()
             keep = b > 1e-6 * b.max()     # the -60 dB floor of the error rule
             dev_db[p] = float((10 * torch.log10(a[keep] / b[keep])).abs().max())
+        ms_mix_n = None
+        if args.streams > 1:
+            ms_mix_n = round(run_steps(args, "f16x3", w, D, params, ap, ap0, users, gpts, H,
+                                       nstreams=args.streams)[0], 5)
         mixed = {"dtype": "f16x3 (FP16 hi/lo x3 MFMA, FP32 accumulate)", "streams": 1,
                  "ms_per_step": round(ms_mix, 5), "maps_launch_ms": round(launch_mix, 5),
                  "speedup_vs_f32_step": round(ms_one / ms_mix, 3),
+                 "ms_per_step_streams": ms_mix_n,
                  "max_db_vs_f32_maps": dev_db}
 
     terms_per_step = 3 * K * M + 2 * N * M
