@@ -25,15 +25,19 @@
 // term (split-precision products: Markidis et al. 2018, Ootomo and Yokota
 // 2022).
 //   FP16 keeps both halves in its normal range by scaling.  h is scaled by
-//   2^14 (|h| <= 1 always, by the near-field clamp).  The weights of each
+//   2^hexp (14 for the default near-field clamp, where |h| <= 1; less for a
+//   smaller d_min, so that |h| 2^hexp <= 2^14).  The weights of each
 //   64-antenna chunk are scaled by a power of two that puts their largest
-//   magnitude in [2^13, 2^14).  The accumulator is rescaled by the exact
-//   ratio when the chunk scale changes, and by the inverse scales at the end.
+//   magnitude in [2^13, 2^14): one scale per chunk in map_x3_wg, one per
+//   chunk and stream in map_x3w_wg.  The accumulator is rescaled by the exact
+//   ratio when a scale changes, and by the inverse scales at the end.
 //   BF16 has the FP32 exponent range and needs no scaling.
 //
 // Output tile D: lane 16g + j holds D[4g + r][j] in register r.  Column
 // layouts are in powermap_common.h.
 #pragma once
+
+#include <type_traits>
 
 #include "powermap_common.h"
 #include "split16.h"
@@ -275,7 +279,6 @@ __device__ __forceinline__ void map_f32_wg(const PmMapDev& a, int64_t wg_first, 
 // split-precision x3 (FP16 / BF16)
 // ---------------------------------------------------------------------------
 
-constexpr float kHScale = 16384.0f;   // 2^14: FP16 range placement of h (|h| <= 1)
 
 // LDS of the x3 map: the B tables of the two 32-antenna steps of a chunk,
 // [step][tile][B1hi, B1lo, B2hi, B2lo][lane] x 16 B, and the antenna
@@ -360,8 +363,8 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
     const int M = a.M;
     const int K = a.K;
     const int64_t base = wg_first + (int64_t)wave * (16 * PT);
-    const float hscale = BF16 ? 1.0f : kHScale;
-    const float amp_s = a.amp_rev * hscale;
+    const int hexp = BF16 ? 0 : a.hexp;   // FP16 range placement of h
+    const float amp_s = ldexpf(a.amp_rev, hexp);
 
     const bool grid = a.P.kind == DMIMO_PTS_GRID;
     const WgGrid wg = grid ? wg_grid(a, wg_first, 16 * PT * WAVES) : WgGrid{};
@@ -497,12 +500,434 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
             x3_steps<NT, PT, BF16, false>(a, T, steps, grp, lane, amp_s, px, py, pz, acc);
     }
     // undo the scales (exact powers of two)
-    const float inv = BF16 ? 1.0f : ldexpf(1.0f, -wexp) / kHScale;
+    const float inv = BF16 ? 1.0f : ldexpf(1.0f, -wexp - hexp);
 #pragma unroll
     for (int t = 0; t < PT; ++t)
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[t][q] *= inv;
     __syncthreads();
+    map_epilogue<NT, PT>(a, acc, base, lane,
+                         reinterpret_cast<float*>(smem) + wave * 16 * PT * ep_stride<NT>());
+}
+
+// ---------------------------------------------------------------------------
+// split-precision x3 for many streams (K > 8): several tiles per wave
+// ---------------------------------------------------------------------------
+//
+// The same products as map_x3_wg, arranged for NT = 2 or 4 output tiles:
+//  * a wave holds PT tiles of 16 points, so each split weight table in LDS
+//    feeds PT tiles, and a workgroup stages one table per chunk for
+//    16 PT WAVES points;
+//  * the weights of the next chunk are loaded into registers while the
+//    current chunk runs, and split into the other of two LDS buffers after
+//    it: one barrier per chunk;
+//  * FP16 weights are scaled per chunk and stream: the eight threads that
+//    stage one stream of a chunk are eight consecutive lanes, which find the
+//    stream's largest magnitude among themselves (no cross-wave step);
+//  * a grid-row workgroup whose chunk lies more than d_min below or beside the
+//    row synthesises without the zero guard and the near-field clamp, which
+//    change no bit there (as in the FP32 body).
+// Accumulation order per output is fixed (chunks, then steps, then the six
+// products in a fixed order), so a point's value does not depend on which
+// workgroup or launch computes it.
+
+// Slot of lane l's 16 bytes in a table row of step s.  The XOR spreads the
+// eight lanes that a 16-byte LDS access serves together over eight distinct
+// bank groups, both for the staging stores (lanes 16 g + k of one stream k,
+// g = 0..3, in both steps) and for the operand loads (eight consecutive lanes).
+__device__ __forceinline__ int x3w_slot(int l, int s) { return l ^ ((2 * (l >> 4) + s) & 7); }
+
+template <int NT>
+struct X3wBuf {
+    u32x4 b[2][NT][4][64];                   // [step][tile][B1hi, B1lo, B2hi, B2lo][x3w_slot(lane)]
+    double x[kChunk], y[kChunk], z[kChunk];  // antennas in wavelengths; grid row: y = C
+    int32_t wexp[8 * NT];                    // FP16: scale exponent of each stream
+    int32_t far;                             // grid row: C >= 1.001 d_min^2 for every antenna
+    int32_t pad[3];
+};
+
+template <int NT, int PT, int WAVES>
+constexpr int x3w_lds_bytes() {
+    constexpr int T = 2 * (int)sizeof(X3wBuf<NT>);
+    return T > ep_bytes<NT, PT, WAVES>() ? T : ep_bytes<NT, PT, WAVES>();
+}
+
+// Registers of one thread's share of the next chunk: the 8 weights of its
+// staging item and, for threads 0..63, one antenna position.
+struct X3wStage {
+    float2 w[8];
+    double ax, ay, az;
+    int wexp;   // FP16: exponent of this thread's stream in the chunk staged last
+    bool set;   // FP16: wexp has been chosen (the stream had a nonzero weight)
+};
+
+// Staging item of thread tid < 64 NT: stream k = tid / 8 and antennas
+// 8 (tid % 8) .. 8 (tid % 8) + 7 of the chunk starting at m0.
+template <int NT>
+__device__ __forceinline__ void x3w_load(const PmMapDev& a, int m0, int tid, X3wStage& st) {
+    const int M = a.M;
+    const int mc = min(kChunk, M - m0);
+    if (tid < 64 * NT) {
+        const int k = tid >> 3;
+        const int a8 = 8 * (tid & 7);
+        const float2* src = a.W + (int64_t)k * M + m0 + a8;
+        if (k < a.K && a8 + 8 <= mc) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) st.w[i] = src[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                st.w[i] = (k < a.K && a8 + i < mc) ? src[i] : make_float2(0.f, 0.f);
+        }
+    }
+    if (tid < kChunk && tid < mc) {
+        const double* q = a.ap + (int64_t)(m0 + tid) * 3;
+        st.ax = q[0];
+        st.ay = q[1];
+        st.az = q[2];
+    }
+}
+
+// Split the staged chunk into buffer T (every thread of the workgroup calls
+// this).  Slots past the last antenna get zero weights and position x = 0,
+// C = 1 (far from any row), or (0, 0, 0) off grid rows.
+template <int NT, bool BF16>
+__device__ __forceinline__ void x3w_write(const PmMapDev& a, X3wBuf<NT>& T, int m0, int tid,
+                                          X3wStage& st, bool row, double ry, double rz,
+                                          double far_c) {
+    const int mc = min(kChunk, a.M - m0);
+    float mx = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fmaxf(fabsf(st.w[i].x), fabsf(st.w[i].y)));
+    // the largest magnitude of the stream: its 8 items are lanes 8j .. 8j + 7
+    // (DPP: swap neighbours, swap pairs, mirror within 8 lanes)
+    mx = fmaxf(mx, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+                       __builtin_bit_cast(int, mx), 0xB1, 0xF, 0xF, false)));   // quad_perm [1,0,3,2]
+    mx = fmaxf(mx, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+                       __builtin_bit_cast(int, mx), 0x4E, 0xF, 0xF, false)));   // quad_perm [2,3,0,1]
+    mx = fmaxf(mx, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+                       __builtin_bit_cast(int, mx), 0x141, 0xF, 0xF, false)));  // row_half_mirror
+    if (tid < 64 * NT) {
+        const int k = tid >> 3;
+        const int g8 = tid & 7;
+        // FP16: the first nonzero chunk of a stream gets the scale 2^(14 - e),
+        // max |w| < 2^e, which puts its largest weight in [2^13, 2^14).  Later
+        // chunks keep the scale while their scaled largest weight stays in
+        // [2^4, 2^15) (FP16 normal, 11 bits for every weight within 2^-18 of
+        // it), so the accumulators rarely need rescaling.  The scale is applied
+        // by ldexp (exact, and no overflow of the factor itself).
+        if (!BF16 && mx > 0.0f) {
+            const int e = ilogbf(mx) + 1;
+            if (!st.set || e + st.wexp > 15 || e + st.wexp < 5) {
+                st.wexp = 14 - e;
+                st.set = true;
+            }
+        }
+        const int ex = BF16 ? 0 : st.wexp;
+        u32x4 rh, rl, ih, il;
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            float r0, r1, q0, q1;
+            rh[i >> 1] = pack_hi<BF16>(ldexpf(st.w[i].x, ex), ldexpf(st.w[i + 1].x, ex), r0, r1);
+            ih[i >> 1] = pack_hi<BF16>(ldexpf(st.w[i].y, ex), ldexpf(st.w[i + 1].y, ex), q0, q1);
+            rl[i >> 1] = pack_lo<BF16>(r0, r1);
+            il[i >> 1] = pack_lo<BF16>(q0, q1);
+        }
+        // hi(-x) = -hi(x) and lo(-x) = -lo(x) (both roundings are symmetric)
+        const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        const int s = g8 >> 2;
+        const int l = x3w_slot(16 * (g8 & 3) + (k & 15), s);
+        const int qr = 2 * (k >> 4);
+        // tile qr: Re z = hr wr - hi wi;  tile qr + 1: Im z = hr wi + hi wr
+        T.b[s][qr][0][l] = rh;
+        T.b[s][qr][1][l] = rl;
+        T.b[s][qr][2][l] = ih ^ sgn;
+        T.b[s][qr][3][l] = il ^ sgn;
+        T.b[s][qr + 1][0][l] = ih;
+        T.b[s][qr + 1][1][l] = il;
+        T.b[s][qr + 1][2][l] = rh;
+        T.b[s][qr + 1][3][l] = rl;
+        if (g8 == 0) T.wexp[k] = st.wexp;
+    }
+    if (tid < kChunk) {
+        const bool live = tid < mc;
+        const double x = live ? st.ax * a.inv_lam : 0.0;
+        T.x[tid] = x;
+        if (row) {
+            double c = 1.0;
+            if (live) {
+                const double dy = ry - st.ay * a.inv_lam, dz = rz - st.az * a.inv_lam;
+                c = fma(dy, dy, dz * dz);
+            }
+            T.y[tid] = c;
+            const bool all_far = __all(c >= far_c);   // wave 0: the 64 slots of the chunk
+            if (tid == 0) T.far = all_far ? 1 : 0;
+        } else {
+            T.y[tid] = live ? st.ay * a.inv_lam : 0.0;
+            T.z[tid] = live ? st.az * a.inv_lam : 0.0;
+        }
+    }
+}
+
+// The 8 terms of one point (antennas xs[i] of this lane's group) as the four
+// split A operands.
+template <bool BF16, bool ROW, bool GUARD>
+__device__ __forceinline__ void x3w_synth(double px, double py, double pz, const double (&xs)[8],
+                                          const double (&ys)[8], const double (&zs)[8], float amp_s,
+                                          float inv_dmin_rev, u32x4& arh, u32x4& arl, u32x4& aih,
+                                          u32x4& ail) {
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        float hr0, hi0, hr1, hi1;
+        if constexpr (ROW) {
+            const double dx0 = px - xs[i], dx1 = px - xs[i + 1];
+            wave_term_rev_d2<GUARD>(fma(dx0, dx0, ys[i]), amp_s, inv_dmin_rev, hr0, hi0);
+            wave_term_rev_d2<GUARD>(fma(dx1, dx1, ys[i + 1]), amp_s, inv_dmin_rev, hr1, hi1);
+        } else {
+            wave_term_rev(px - xs[i], py - ys[i], pz - zs[i], amp_s, inv_dmin_rev, hr0, hi0);
+            wave_term_rev(px - xs[i + 1], py - ys[i + 1], pz - zs[i + 1], amp_s, inv_dmin_rev, hr1,
+                          hi1);
+        }
+        float rr0, rr1, ri0, ri1;
+        arh[i >> 1] = pack_hi<BF16>(hr0, hr1, rr0, rr1);
+        aih[i >> 1] = pack_hi<BF16>(hi0, hi1, ri0, ri1);
+        arl[i >> 1] = pack_lo<BF16>(rr0, rr1);
+        ail[i >> 1] = pack_lo<BF16>(ri0, ri1);
+    }
+}
+
+// Positions of this lane's 8 antennas in step s of the chunk.
+template <int NT, bool ROW>
+__device__ __forceinline__ void x3w_positions(const X3wBuf<NT>& T, int s, int grp, double (&xs)[8],
+                                              double (&ys)[8], double (&zs)[8]) {
+    const int m8 = 32 * s + 8 * grp;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        xs[i] = T.x[m8 + i];
+        ys[i] = T.y[m8 + i];
+        zs[i] = ROW ? 0.0 : T.z[m8 + i];
+    }
+}
+
+#ifdef DMIMO_X3W_PIPE
+// One chunk (two steps of 32 antennas; slots past the last antenna carry zero
+// weights) for the PT tiles of a wave.  The (step, tile) blocks run in order;
+// the terms of the next block are synthesised in program order before the
+// products of the current one, so that the VALU work of one overlaps the
+// matrix-core work of the other.  The B operands of a step are loaded once
+// and serve its PT tiles.
+template <int NT, int PT, bool BF16, bool ROW, bool GUARD>
+__device__ __forceinline__ void x3w_chunk(const X3wBuf<NT>& T, int grp, int lane, float amp_s,
+                                          float inv_dmin_rev, const double (&px)[PT],
+                                          const double (&py)[PT], const double (&pz)[PT],
+                                          f32x4 (&acc)[PT][NT]) {
+    double xs[8], ys[8], zs[8];
+    u32x4 Ac[4], An[4];
+    u32x4 B[NT][4];
+    x3w_positions<NT, ROW>(T, 0, grp, xs, ys, zs);
+    x3w_synth<BF16, ROW, GUARD>(px[0], py[0], pz[0], xs, ys, zs, amp_s, inv_dmin_rev, Ac[0], Ac[1],
+                                Ac[2], Ac[3]);
+#pragma unroll
+    for (int u = 0; u < 2 * PT; ++u) {
+        const int s = u / PT, t = u % PT;
+        if (u + 1 < 2 * PT) {
+            const int s1 = (u + 1) / PT, t1 = (u + 1) % PT;
+            if (s1 != s) x3w_positions<NT, ROW>(T, s1, grp, xs, ys, zs);
+            x3w_synth<BF16, ROW, GUARD>(px[t1], py[t1], pz[t1], xs, ys, zs, amp_s, inv_dmin_rev,
+                                        An[0], An[1], An[2], An[3]);
+        }
+        const int sl = x3w_slot(lane, s);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            if (t == 0) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) B[q][w] = T.b[s][q][w][sl];
+            }
+            f32x4 c = acc[t][q];
+            c = mfma16<BF16>(Ac[0], B[q][0], c);
+            c = mfma16<BF16>(Ac[1], B[q][0], c);
+            c = mfma16<BF16>(Ac[0], B[q][1], c);
+            c = mfma16<BF16>(Ac[2], B[q][2], c);
+            c = mfma16<BF16>(Ac[3], B[q][2], c);
+            c = mfma16<BF16>(Ac[2], B[q][3], c);
+            acc[t][q] = c;
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) Ac[w] = An[w];
+    }
+#ifdef DMIMO_X3W_SCHED
+    // schedule: the first block's synthesis, then each block's products one
+    // at a time between groups of the next block's VALU instructions
+    __builtin_amdgcn_sched_group_barrier(0x002, DMIMO_X3W_SCHED_HEAD, 0);
+#pragma unroll
+    for (int i = 0; i < (2 * PT - 1) * 6 * NT; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, DMIMO_X3W_SCHED, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 6 * NT, 0);
+#endif
+}
+
+#else
+// One chunk (two steps of 32 antennas; slots past the last antenna carry zero
+// weights) for the PT tiles of a wave: per step, the terms of all PT tiles,
+// then the products, with each B operand loaded once for the PT tiles.
+template <int NT, int PT, bool BF16, bool ROW, bool GUARD>
+__device__ __forceinline__ void x3w_chunk(const X3wBuf<NT>& T, int grp, int lane, float amp_s,
+                                          float inv_dmin_rev, const double (&px)[PT],
+                                          const double (&py)[PT], const double (&pz)[PT],
+                                          f32x4 (&acc)[PT][NT]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        double xs[8], ys[8], zs[8];
+        x3w_positions<NT, ROW>(T, s, grp, xs, ys, zs);
+        u32x4 A[PT][4];
+#pragma unroll
+        for (int t = 0; t < PT; ++t)
+            x3w_synth<BF16, ROW, GUARD>(px[t], py[t], pz[t], xs, ys, zs, amp_s, inv_dmin_rev,
+                                        A[t][0], A[t][1], A[t][2], A[t][3]);
+        const int sl = x3w_slot(lane, s);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const u32x4 b1h = T.b[s][q][0][sl], b1l = T.b[s][q][1][sl];
+            const u32x4 b2h = T.b[s][q][2][sl], b2l = T.b[s][q][3][sl];
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
+                f32x4 c = acc[t][q];
+                c = mfma16<BF16>(A[t][0], b1h, c);
+                c = mfma16<BF16>(A[t][1], b1h, c);
+                c = mfma16<BF16>(A[t][0], b1l, c);
+                c = mfma16<BF16>(A[t][2], b2h, c);
+                c = mfma16<BF16>(A[t][3], b2h, c);
+                c = mfma16<BF16>(A[t][2], b2l, c);
+                acc[t][q] = c;
+            }
+        }
+    }
+}
+
+#endif
+
+// One workgroup: points wg_first .. wg_first + 16 PT WAVES - 1.  smem: at
+// least x3w_lds_bytes<NT, PT, WAVES>() bytes, 16-byte aligned.
+template <int NT, int PT, bool BF16, int WAVES>
+__device__ __forceinline__ void map_x3w_wg(const PmMapDev& a, int64_t wg_first, char* smem) {
+    static_assert(NT == 2 || NT == 4, "map_x3w_wg: 16 < K <= 32 or 8 < K <= 16");
+    static_assert(64 * NT <= 64 * WAVES, "map_x3w_wg: one staging item per thread");
+    X3wBuf<NT>* buf = reinterpret_cast<X3wBuf<NT>*>(smem);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int grp = lane >> 4;
+    const int64_t N = a.P.n;
+    const int M = a.M;
+    const int64_t base = wg_first + (int64_t)wave * (16 * PT);
+    const int hexp = BF16 ? 0 : a.hexp;
+    const float amp_s = ldexpf(a.amp_rev, hexp);
+
+    const bool grid = a.P.kind == DMIMO_PTS_GRID;
+    const WgGrid wg = grid ? wg_grid(a, wg_first, 16 * PT * WAVES) : WgGrid{};
+    double px[PT], py[PT], pz[PT];
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+        if (grid) {
+            wg_point_rev(a, wg, wave * (16 * PT) + 16 * t + (lane & 15), px[t], py[t], pz[t]);
+        } else {
+            int64_t n = base + 16 * t + (lane & 15);
+            n = n < N ? n : N - 1;
+            point_rev(a, n, px[t], py[t], pz[t]);
+        }
+    }
+    const bool row = grid && wg.one_row;
+    double ry = 0.0, rz = 0.0;
+    if (row) {
+        double rx;
+        wg_point_rev(a, wg, 0, rx, ry, rz);
+    }
+    const double dmin_rev = 1.0 / (double)a.inv_dmin_rev;
+    const double far_c = 1.001 * dmin_rev * dmin_rev;
+
+    f32x4 acc[PT][NT];
+#pragma unroll
+    for (int t = 0; t < PT; ++t)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int cur[NT / 2];   // FP16: exponent of this lane's column in each 16-stream block
+#pragma unroll
+    for (int b = 0; b < NT / 2; ++b) cur[b] = 0;
+
+    X3wStage st;
+    st.wexp = 0;
+    st.set = false;
+    const int nch = (M + kChunk - 1) / kChunk;
+    // the chunk loop, compiled once for grid-row workgroups and once for the
+    // others (one copy of the accumulators per loop)
+    auto run = [&](auto row_tag) {
+        constexpr bool ROW = decltype(row_tag)::value;
+        x3w_load<NT>(a, 0, tid, st);
+        x3w_write<NT, BF16>(a, buf[0], 0, tid, st, ROW, ry, rz, far_c);
+        if (nch > 1) x3w_load<NT>(a, kChunk, tid, st);
+        __syncthreads();
+        for (int c = 0; c < nch; ++c) {
+            const X3wBuf<NT>& T = buf[c & 1];
+            if constexpr (!BF16) {
+                // the column's stream changed its scale: rescale its sums exactly
+                int ne[NT / 2];
+                bool moved = false;
+#pragma unroll
+                for (int b = 0; b < NT / 2; ++b) {
+                    ne[b] = T.wexp[16 * b + (lane & 15)];
+                    moved = moved || (c > 0 && ne[b] != cur[b]);
+                }
+                if (__builtin_expect(__any(moved), 0)) {
+#pragma unroll
+                    for (int b = 0; b < NT / 2; ++b) {
+                        const int d = c > 0 ? ne[b] - cur[b] : 0;
+#pragma unroll
+                        for (int t = 0; t < PT; ++t)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                acc[t][2 * b][r] = ldexpf(acc[t][2 * b][r], d);
+                                acc[t][2 * b + 1][r] = ldexpf(acc[t][2 * b + 1][r], d);
+                            }
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < NT / 2; ++b) cur[b] = ne[b];
+            }
+            if constexpr (ROW) {
+                if (T.far)
+                    x3w_chunk<NT, PT, BF16, true, false>(T, grp, lane, amp_s, a.inv_dmin_rev, px, py,
+                                                         pz, acc);
+                else
+                    x3w_chunk<NT, PT, BF16, true, true>(T, grp, lane, amp_s, a.inv_dmin_rev, px, py,
+                                                        pz, acc);
+            } else {
+                x3w_chunk<NT, PT, BF16, false, true>(T, grp, lane, amp_s, a.inv_dmin_rev, px, py, pz,
+                                                     acc);
+            }
+            if (c + 1 < nch) {
+                // buffer (c + 1) & 1 was last read in chunk c - 1, before the barrier
+                x3w_write<NT, BF16>(a, buf[(c + 1) & 1], (c + 1) * kChunk, tid, st, ROW, ry, rz,
+                                    far_c);
+                if (c + 2 < nch) x3w_load<NT>(a, (c + 2) * kChunk, tid, st);
+            }
+            __syncthreads();
+        }
+    };
+    if (row)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
+    // undo the scales (exact powers of two)
+    if constexpr (!BF16) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t)
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[t][q][r] = ldexpf(acc[t][q][r], -(cur[q >> 1] + hexp));
+    }
     map_epilogue<NT, PT>(a, acc, base, lane,
                          reinterpret_cast<float*>(smem) + wave * 16 * PT * ep_stride<NT>());
 }

@@ -1,6 +1,8 @@
 // Pieces shared by the matrix-core power-map kernels.
 #pragma once
 
+#include <cmath>
+
 #include "kernels.h"
 
 namespace dmimo {
@@ -15,6 +17,7 @@ struct PmMapDev {
     double inv_lam;      // 1 / lambda: positions are converted to wavelengths
     float amp_rev;       // 1 / (4 pi): amplitude = amp_rev / d_rev
     float inv_dmin_rev;  // lambda / d_min
+    int hexp;            // FP16 split maps: h is scaled by 2^hexp (see fp16_h_exponent)
     const double* ap;    // [M][3] metres
     const float2* W;     // [K][M]
     float sigma2;
@@ -35,6 +38,18 @@ __device__ __forceinline__ PmMapDev map_of(PmMapDev a, int64_t p) {
     return a;
 }
 
+// Exponent e of the power-of-two scale 2^e that the FP16 split maps apply to
+// h.  |h| <= (1 / (4 pi)) (lambda / d_min) by the near-field clamp, and e is
+// the largest exponent <= 14 that keeps that bound times 2^e at or below
+// 2^14 (FP16's largest finite value is 65504): 14 for the default d_min =
+// lambda / (4 pi), less for a smaller d_min.
+inline int fp16_h_exponent(float amp_rev, float inv_dmin_rev) {
+    const double bound = (double)amp_rev * (double)inv_dmin_rev * (1.0 - 1e-6);
+    int e = 14;
+    if (bound > 1.0) e -= (int)std::ceil(std::log2(bound));
+    return e;
+}
+
 inline PmMapDev make_map_dev(const PowermapArgs& a) {
     PmMapDev d;
     d.P = a.P;
@@ -43,6 +58,7 @@ inline PmMapDev make_map_dev(const PowermapArgs& a) {
     d.inv_lam = a.w.inv_lam;
     d.amp_rev = (float)(1.0 / (4.0 * kPi));
     d.inv_dmin_rev = (float)(a.w.inv_dmin / a.w.inv_lam);
+    d.hexp = fp16_h_exponent(d.amp_rev, d.inv_dmin_rev);
     d.ap = a.ap;
     d.W = reinterpret_cast<const float2*>(a.W);
     d.sigma2 = (float)a.sigma2;

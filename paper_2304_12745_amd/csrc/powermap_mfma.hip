@@ -22,6 +22,28 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4)))
                                    s_red);
 }
 
+// The split-precision map for K > 8 (map_x3w_wg): PT tiles of 16 points per
+// wave, WAVES waves per workgroup, at least OCC waves per SIMD.
+#ifndef DMIMO_X3W_PT
+#define DMIMO_X3W_PT 2
+#endif
+#ifndef DMIMO_X3W_WAVES
+#define DMIMO_X3W_WAVES 8
+#endif
+#ifndef DMIMO_X3W_OCC
+#define DMIMO_X3W_OCC 2
+#endif
+constexpr int kX3wPt = DMIMO_X3W_PT;
+constexpr int kX3wWaves = DMIMO_X3W_WAVES;
+
+template <int NT, int PT, bool BF16, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(DMIMO_X3W_OCC)))
+void powermap_x3w_kernel(PmMapDev a) {
+    __shared__ __attribute__((aligned(16))) char smem[x3w_lds_bytes<NT, PT, WAVES>()];
+    map_x3w_wg<NT, PT, BF16, WAVES>(map_of(a, blockIdx.y), (int64_t)blockIdx.x * (WAVES * 16 * PT),
+                                    smem);
+}
+
 #ifndef DMIMO_PM_WAVES
 #define DMIMO_PM_WAVES 8   // wavefronts per workgroup of the map kernels (measured best of 4, 8, 16)
 #endif
@@ -41,6 +63,15 @@ dmimo_status launch_f32(const PmMapDev& d, int maps, hipStream_t s) {
     constexpr int PT = NT == 1 ? 4 : 2;
     return launch_blocks<PT>(
         d, maps, [&](dim3 g) { powermap_mfma_kernel<NT, PT, kWaves><<<g, 64 * kWaves, 0, s>>>(d); });
+}
+
+template <int NT, bool BF16>
+dmimo_status launch_x3w(const PmMapDev& d, int maps, hipStream_t s) {
+    const int64_t blocks = ceil_div(d.P.n, kX3wWaves * 16 * kX3wPt);
+    if (blocks > 0x7fffffff) return fail(DMIMO_E_SHAPE, "powermap: too many points");
+    powermap_x3w_kernel<NT, kX3wPt, BF16, kX3wWaves>
+        <<<dim3((unsigned)blocks, (unsigned)maps), 64 * kX3wWaves, 0, s>>>(d);
+    return check_launch("powermap_x3w");
 }
 
 template <int NT, bool BF16>
@@ -65,12 +96,12 @@ dmimo_status launch_powermap_mfma(const PowermapArgs& a, hipStream_t s) {
     const PmMapDev d = make_map_dev(a);
     if (a.prec == DMIMO_MIX_BF16X3) {
         if (a.K <= 8) return launch_x3<1, true>(d, a.maps, s);
-        if (a.K <= 16) return launch_x3<2, true>(d, a.maps, s);
-        return launch_x3<4, true>(d, a.maps, s);
+        if (a.K <= 16) return launch_x3w<2, true>(d, a.maps, s);
+        return launch_x3w<4, true>(d, a.maps, s);
     }
     if (a.K <= 8) return launch_x3<1, false>(d, a.maps, s);
-    if (a.K <= 16) return launch_x3<2, false>(d, a.maps, s);
-    return launch_x3<4, false>(d, a.maps, s);
+    if (a.K <= 16) return launch_x3w<2, false>(d, a.maps, s);
+    return launch_x3w<4, false>(d, a.maps, s);
 }
 
 }  // namespace dmimo

@@ -58,9 +58,18 @@ struct ServeItem {
     int64_t first;   // first point of the tile
 };
 
+// split-precision modes with more than 8 streams run the many-stream body
+// (map_x3w_wg) with kServeX3wPt tiles per wave
+constexpr int kServeX3wPt = 2;
+
+bool x3w_mode(int mode) {
+    return mode == kF16Nt2 || mode == kF16Nt4 || mode == kBf16Nt2 || mode == kBf16Nt4;
+}
+
 // points of one work item: 16 PT points per wave (one point per lane for VALU)
 int tile_points(int mode) {
     if (mode >= kF32K1) return kServeThreads;
+    if (x3w_mode(mode)) return 16 * kServeX3wPt * kServeWaves;
     return mode < kF16Nt1 ? 16 * 2 * kServeWaves : 16 * kServeWaves;
 }
 
@@ -96,10 +105,26 @@ void serve_kernel(const PmMapDev* __restrict__ slots, const ServeItem* __restric
     }
 }
 
+// The many-stream split-precision modes: the body of the one-shot map kernel
+// (the same bits per point for any workgroup shape), two waves per SIMD.
+template <int NT, bool BF16>
+__global__ __launch_bounds__(kServeThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void serve_x3w_kernel(const PmMapDev* __restrict__ slots, const ServeItem* __restrict__ items,
+                      int n_items) {
+    __shared__ __attribute__((aligned(16))) char smem[x3w_lds_bytes<NT, kServeX3wPt, kServeWaves>()];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const ServeItem w = items[it];
+        const PmMapDev a = slots[w.slot];
+        map_x3w_wg<NT, kServeX3wPt, BF16, kServeWaves>(a, w.first, smem);
+        __syncthreads();   // LDS is reused by the next item
+    }
+}
+
 using ServeKernel = void (*)(const PmMapDev*, const ServeItem*, int);
 const ServeKernel kServeKernels[11] = {serve_kernel<0>, serve_kernel<1>, serve_kernel<2>,
-                                       serve_kernel<3>, serve_kernel<4>, serve_kernel<5>,
-                                       serve_kernel<6>, serve_kernel<7>, serve_kernel<8>,
+                                       serve_kernel<3>, serve_x3w_kernel<2, false>,
+                                       serve_x3w_kernel<4, false>, serve_kernel<6>,
+                                       serve_x3w_kernel<2, true>, serve_x3w_kernel<4, true>,
                                        serve_valu_kernel<1>, serve_valu_kernel<2>};
 
 double now_s() {
@@ -302,6 +327,7 @@ bool ServerImpl::admit_one(Query* q) {
     m.inv_lam = d.w.inv_lam;
     m.amp_rev = (float)(1.0 / (4.0 * kPi));
     m.inv_dmin_rev = (float)(d.w.inv_dmin / d.w.inv_lam);
+    m.hexp = fp16_h_exponent(m.amp_rev, m.inv_dmin_rev);
     m.ap = ap;
     m.W = reinterpret_cast<const float2*>(W);
     m.sigma2 = (float)q->sigma2;

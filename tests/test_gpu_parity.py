@@ -764,6 +764,60 @@ def test_powermap_antennas_in_the_map_plane(D):
     check_db(host(r.sinr), s_ref, MAP_TOL["f32"], what="sinr")
 
 
+# The many-stream split-precision body (K > 8): a near-field clamp d_min ten
+# times below lambda / (4 pi), so that |h| reaches 10 (the FP16 body scales h
+# by 2^10 instead of 2^14), with antennas on grid points (d = 0) and within
+# d_min of the map plane; a 100 x 23 grid, so that some workgroups span two
+# rows (the general path) and the others lie on one row (guarded chunks next
+# to the plane); M = 150 (a ragged third chunk).  Every point against the
+# oracle with the same d_min.
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+@pytest.mark.parametrize("K", [9, 16, 24, 32])
+def test_powermap_many_streams_small_dmin(D, K, prec):
+    say(f"powermap K={K} M=150, d_min = lambda/(40 pi), antennas in the plane, {prec}")
+    rng = np.random.default_rng(300 + K)
+    f = 5.8e9
+    lam = O.wavelength(f)
+    d_min = lam / (40.0 * math.pi)
+    g = WL.Grid(0.0, 0.0, 0.2, 0.2, 1.0, 100, 23)
+    pts = grid_pts(g)
+    M = 150
+    aps = WL.uniform_positions(rng, M, 20, 4.6, 5.0)
+    on = rng.choice(len(pts), 10, replace=False)
+    aps[:10] = pts[on]                                     # on grid points
+    aps[10:20, 2] = 1.0 + rng.uniform(-0.5, 0.5, 10) * d_min   # within d_min of the plane
+    users = WL.uniform_positions(rng, K, 20, 4.6, 1.0)
+    W = c64(O.mr_precoder(O.los_channel(users, aps, f, d_min=d_min), 1.0))
+    r = D.powermap(D.channel_params(f, D.CH_LOS, 0.0, d_min), dev(aps), dev(W),
+                   D.grid_points(g), 1e-12, prec)
+    power = host(r.power)
+    assert np.all(np.isfinite(power)) and np.all(np.isfinite(host(r.sinr)))
+    Hg = O.los_channel(pts, aps, f, d_min=d_min)
+    assert np.abs(Hg).max() > 8.0                          # the clamp bound, 10, is reached
+    Wc = W.astype(np.complex128)
+    check_db(power, O.power_map(Hg, Wc), MAP_TOL[prec], what="power")
+    s_ref, _ = O.sinr_map(Hg, Wc, 1e-12)
+    check_db(host(r.sinr), s_ref, MAP_TOL[prec], what="sinr")
+
+
+# Weights of each stream spanning ten decades from chunk to chunk (M = 320,
+# five chunks): the FP16 stream scales change between chunks and the
+# accumulators are rescaled; K = 20 and 32 on a grid of rows far below the
+# antennas (the guard-free row loop).
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+@pytest.mark.parametrize("K", [20, 32])
+def test_powermap_many_streams_weight_dynamic_range(D, K, prec):
+    say(f"powermap K={K} M=320, weights over 10 decades per stream, {prec}")
+    rng = np.random.default_rng(500 + K)
+    M, f = 320, 5.8e9
+    aps = WL.uniform_positions(rng, M, 30, 30, 5.0)
+    g = WL.Grid(0.0, 0.0, 30.0 / 256, 30.0 / 24, 1.0, 256, 24)
+    mag = 10.0 ** (rng.uniform(-6, 4, size=(K, 1)) + rng.uniform(-3, 3, size=(1, M // 64)).repeat(64, 1))
+    W = c64(WL.complex_normal(rng, (K, M)) * mag)
+    _check_map(D, aps, W, D.grid_points(g), grid_pts(g), f, 1e-12, prec, MAP_TOL[prec],
+               per_stream=True)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 def test_powermap_hall_sampled(D, prec):
     # the full-size hall map (N = 2048^2, M = 1024, K = 32) in one launch,
