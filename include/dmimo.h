@@ -167,6 +167,26 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
                             double* l21, double* sinr, double* rsum, int32_t* info,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* dmimo_beamform for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, bit for bit, with the scratch taken from a
+ * static device array of DMIMO_NOALLOC_SCRATCH_BYTES that each GPU holds from
+ * the first call on it until the process ends.  Nothing is allocated, and no
+ * ws argument is taken.
+ *   Every argument and output as for dmimo_beamform.
+ *   A call whose workspace (dmimo_workspace_size of dmimo_beamform) exceeds
+ *   DMIMO_NOALLOC_SCRATCH_BYTES returns DMIMO_E_WORKSPACE before any launch
+ *   (e.g. FP32 ZF with K = 16, M = 256 fits up to B = 4096).
+ *   All calls on one device share the array: calls that overlap on one device
+ *   (on different streams or host threads) race and must be serialised by the
+ *   caller.  No call depends on what an earlier call left in the array. */
+#define DMIMO_NOALLOC_SCRATCH_BYTES (8 << 20)
+dmimo_status dmimo_beamform_noalloc(int32_t precoder, int32_t B, int32_t K, int32_t M,
+                                    const void* H, const double* gamma_lin, double sigma2,
+                                    double p_total, int32_t prec, void* W, double* p_ant,
+                                    double* l21, double* sinr, double* rsum, int32_t* info,
+                                    void* stream);
+
 /* Several precoders of the same channels in one call, as Sec. VI compares MR
  * and ZF (and the PA-aware precoder) on one deployment: precoder p is
  * dmimo_beamform(precoders[p], ...) with every output at offset p of a

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 #include "dmimo_internal.h"
 #include "kernels.h"
@@ -273,6 +274,86 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, c
         set_error("beamform: workspace needs %zu bytes, got %zu", need, ws ? ws_bytes : 0);
         return DMIMO_E_WORKSPACE;
     }
+    return launch_beamform(beamform_args(precoder, B, K, M, H, gam, sigma2, p_total, prec, W, p_ant,
+                                         l21, sinr, rsum, info, ws),
+                           as_stream(stream));
+}
+
+// ---------------------------------------------------------------------------
+// dmimo_beamform_noalloc: the scratch of dmimo_beamform in a static device array
+// ---------------------------------------------------------------------------
+//
+// Each GPU that runs the library holds its own copy of `scratch` until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it only stands for the symbol): its device address is looked up once
+// per device with hipGetSymbolAddress, with that device current, and that
+// address is what the kernels receive.  Every call on a device shares the
+// array, so calls that overlap on one device (different streams, or threads)
+// race; the kernels write every byte of the scratch they read, so no call
+// depends on what an earlier one left there.
+
+static __device__ __align__(256) char scratch[DMIMO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that `stream` belongs to (the
+// current device for the NULL stream).
+dmimo_status scratch_address(hipStream_t stream, void** out) {
+    int dev = 0;
+    hipError_t e = stream ? hipStreamGetDevice(stream, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("beamform_noalloc: device of the stream: %s", hipGetErrorString(e));
+        return DMIMO_E_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(DMIMO_E_UNSUPPORTED, "beamform_noalloc: device index");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        if ((e = hipGetDevice(&cur)) == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess || !p) {
+            set_error("beamform_noalloc: scratch address: %s", hipGetErrorString(e));
+            return DMIMO_E_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return DMIMO_OK;
+}
+
+}  // namespace
+
+dmimo_status dmimo_beamform_noalloc(int32_t precoder, int32_t B, int32_t K, int32_t M,
+                                    const void* H, const double* gamma_lin, double sigma2,
+                                    double p_total, int32_t prec, void* W, double* p_ant,
+                                    double* l21, double* sinr, double* rsum, int32_t* info,
+                                    void* stream) {
+    clear_error();
+    double gam[DMIMO_K_MAX];
+    dmimo_status st = check_beamform(precoder, B, K, M, sigma2, p_total, prec,
+                                     sinr ? sinr : rsum, gamma_lin, gam);
+    if (st) return st;
+    const size_t need = dmimo_workspace_size(
+        precoder == DMIMO_ZF ? DMIMO_CALL_BEAMFORM_ZF : DMIMO_CALL_BEAMFORM_MR, B, K, M, 0, prec);
+    if (need > (size_t)DMIMO_NOALLOC_SCRATCH_BYTES) {
+        set_error("beamform_noalloc: the call needs %zu bytes of scratch, more than the %d bytes "
+                  "of the static array (use dmimo_beamform with a workspace)",
+                  need, DMIMO_NOALLOC_SCRATCH_BYTES);
+        return DMIMO_E_WORKSPACE;
+    }
+    if (B == 0) return DMIMO_OK;
+    if (!H || !W) return fail(DMIMO_E_ARG, "beamform_noalloc: NULL H or W");
+    void* ws = nullptr;
+    if (need > 0 && (st = scratch_address(as_stream(stream), &ws))) return st;
     return launch_beamform(beamform_args(precoder, B, K, M, H, gam, sigma2, p_total, prec, W, p_ant,
                                          l21, sinr, rsum, info, ws),
                            as_stream(stream));

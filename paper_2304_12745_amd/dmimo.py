@@ -57,6 +57,8 @@ _SIGS = {
     "dmimo_gram": [_i32, _i32, _i32, _vp, _i32, _vp, _vp],
     "dmimo_beamform": [_i32, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _vp, _vp,
                        _vp, _vp, _vp, _sz, _vp],
+    "dmimo_beamform_noalloc": [_i32, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _vp,
+                               _vp, _vp, _vp, _vp],
     "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
                        ctypes.POINTER(Points), _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "dmimo_beamform_multi": [_i32, _vp, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp,
@@ -268,6 +270,31 @@ def beamform(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f3
                                 _ptr(out.rsum), _ptr(out.info), _ptr(ws),
                                 ws.numel() if ws is not None else 0, _stream(stream)),
            "dmimo_beamform")
+    return out
+
+
+# bytes of the static scratch array of dmimo_beamform_noalloc (DMIMO_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 8 << 20
+
+
+def beamform_noalloc(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f32",
+                     out: Optional[BeamformResult] = None, stream=None) -> BeamformResult:
+    """dmimo_beamform_noalloc: dmimo_beamform with the scratch in the library's
+    static device array (no workspace argument, nothing allocated by the
+    call).  ``out`` (from beamform_outputs) reuses preallocated outputs."""
+    prec = _prec(prec)
+    pc = PRECODERS[precoder] if isinstance(precoder, str) else int(precoder)
+    B, K, M = H.shape
+    if out is None:
+        out = beamform_outputs(B, K, M, prec, H.device, True, pc)
+    g = None
+    if gamma_lin is not None:
+        g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+    _check(lib().dmimo_beamform_noalloc(pc, B, K, M, _ptr(H), g, float(sigma2), float(p_total),
+                                        prec, _ptr(out.W), _ptr(out.p_ant), _ptr(out.l21),
+                                        _ptr(out.sinr), _ptr(out.rsum), _ptr(out.info),
+                                        _stream(stream)),
+           "dmimo_beamform_noalloc")
     return out
 
 
