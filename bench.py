@@ -1,32 +1,48 @@
 #!/usr/bin/env python3
 """Benchmark of the distributed-MIMO hot path on one MI355X.
 
-Workload ("room"): M = 64 APs on a jittered 8x8 ceiling grid (pitch 2.5 m,
-z = 4 m) of a 20x20x4 m room, 3.5 GHz, K = 8 users at z = 1.2 m, noise -90 dBm.
-One step is one pass of the whole path, with inputs already resident in HBM:
+Headline workload ("hall", the largest single-GPU configuration): M = 1024
+APs on a regular 32x32 ceiling grid (pitch 1.5625 m, z = 5 m) of a 50x50x5 m
+hall, 5.8 GHz, K = 32 users at z = 1 m, ZF at 1 W, noise -90 dBm, power + SINR
+map on a 2048x2048 grid at z = 1 m.  One step is one pass of the whole path,
+with inputs already resident in HBM:
 
-  1. dmimo_beamform_users  user channels H (K x M, complex64, synthesised in
-                           the launch and written out), and MR and ZF of them
-                           at 1 W (+ p_m, L2,1, SINR_k, R_sum) in one launch;
-                           ZF with its FP64 Gram and inverse
-  2. dmimo_powermap_batch  MR and ZF power + SINR + best-stream maps, 512 x 512
-                           grid at z = 1.2 m, both maps in one launch
+  1. dmimo_beamform_users  the users' LoS channels H (K x M) and their ZF
+                           precoder at 1 W with p_m, L2,1, SINR_k and R_sum
+                           (channel kernel, then the wide ZF path: per-tile
+                           Gram shares, FP64 Gauss-Jordan inverse, W)
+  2. dmimo_powermap        power + SINR + best-stream map over the 2048^2 grid,
+                           the channel synthesised in the kernel (FP64
+                           distance and phase) and contracted with W
 
-value = channel terms h[n,m] synthesised and consumed per second, over the
-whole step (K M for the channels and for each precoder, N M for each map), in
-G h/s.  The timed steps rotate over two HIP streams (--streams): each step is
-an independent pass with its own outputs, so one stream's precoder launch and
-its map launch's ramp and drain overlap the other stream's map.  The JSON
-line's ``one_stream`` gives the same steps on a single stream, and the
-roofline's map launch duration is measured on a single stream.
+The headline precision is the configuration's: FP16 hi/lo split products on
+the matrix cores with FP32 accumulation (``f16x3``).  The same step in plain
+FP32 and in BF16x3 is timed beside it (``fp32``, ``bf16x3``), with the
+speed-up of the mixed path.
+
+value = channel terms h[n,m] synthesised and consumed per second over the
+whole step (K M for the channels, K M for the precoder, N M for the map), in
+G h/s.
 
 The JSON line also carries:
-* ``roofline`` for the dominant kernel (the FP32 power map).  It is bound by
-  plain VALU arithmetic; the algorithmic cost and the peak are stated below.
-* ``cpu_baseline``: the FP64 oracle timed on a bounded sample of the same step.
-* ``err_db``: the error of the GPU maps against the oracle on that sample.
+* ``roofline`` for the dominant kernel (the map).  Its launch duration is the
+  mean of a dedicated pass of HIP-event pairs on the launching stream (at
+  least 20 launches).  The kernel is bound by its VALU work (synthesis and
+  hi/lo split); the matrix-core fraction is reported beside it.
+* ``err_db``: every result of the GPU chain against the FP64 oracle chain
+  (oracle users -> oracle ZF -> oracle map) in dB, for each precision: the
+  map on sampled grid rows, and the per-user SINR_k.
+* ``cpu_baseline``: the FP64 oracle timed on the host's cores (all of them,
+  one process per core, and one core alone) on a bounded sample of the same
+  step: the users' channel and ZF plus map rows.
+* Secondary configurations: ``room`` (the 512x512 MR + ZF room step),
+  ``focus`` (the FP64 MR focusing map), ``batched`` (Rician Gram + ZF over
+  many deployments), ``paper`` (the paper's ZF sum rate), ``serving``
+  (Poisson queries, p50/p99), ``pgd`` and ``pa`` (the paper's solver), and
+  ``channel`` (the channel materialised in HBM), each with its dB errors.
 
-Only the cpu_baseline leg imports the oracle.
+Only the CPU-baseline and error legs import the oracle; they run before the
+first GPU call (the oracle values) and after the timed regions.
 """
 from __future__ import annotations
 
@@ -41,27 +57,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # ---------------------------------------------------------------------------
-# roofline model of the power-map kernel (VALU issue slots)
+# roofline model of the power-map kernels (VALU issue slots)
 # ---------------------------------------------------------------------------
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 lane-slots/s.
-# FP64 add/mul/FMA and unpacked FP32 ops issue at that full rate.  The
-# transcendental ops (rsq, sin, cos) take 4 slots each.
+# FP64 add/mul/FMA, conversions and unpacked FP32 ops issue at that rate; the
+# transcendentals (rsq, sin, cos) at half of it (2 slots, measured).
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
-# Algorithmic slots per term for FP64 distance/phase + FP32 synthesis:
-#   3 sub + 3 (mul, 2 FMA) for d^2                             6
-#   sqrt: cvt, rsq(4), cvt, 4 FP64 Newton ops                  10
-#   revolutions: mul, floor, FMA (fract), cvt                   4
-#   sin(4) + cos(4)                                             8
-#   amplitude min + mul, h = amp * (c, -s): 2 mul                4
-# = 32 slots.  With K >= 3 the K complex MACs (8K real flops per term) run on
-# FP32 MFMA (157.3 TFLOP/s dense) and overlap the VALU; the kernel is bound by
-# whichever of the two pipes has the larger fraction.
-SYNTH_SLOTS = 32
+# Algorithmic slots per term for FP64 distance/phase + FP32 synthesis of a
+# point in general position:
+#   d^2: 3 sub + mul + 2 FMA                                      6
+#   d = sqrt(d^2): cvt, rsq (2), cvt, 2 mul, 2 FMA (one Newton)   8
+#   phase: fract, cvt                                             2
+#   sin (2) + cos (2)                                             4
+#   amplitude and h = amp (cos, -sin): 3 mul                      3
+# = 23 slots.  The split-precision maps add the hi/lo split of h: two
+# packed conversions and two mixed-precision residuals per term, 4 slots.
+# The K-stream contraction runs on the matrix cores (FP32, or FP16/BF16 x3).
+SYNTH_SLOTS = 23
+SPLIT_SLOTS = 4
 MFMA_F32_PEAK = 157.3e12
+MFMA_F16_PEAK = 2.5e15
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
 
 
-def alg_slots_per_term(K: int) -> int:
+def alg_slots_per_term(K: int, prec: str = "f32") -> int:
+    if prec in ("f16x3", "bf16x3"):
+        return SYNTH_SLOTS + SPLIT_SLOTS
+    # FP32: K <= 2 maps run the contraction on the VALU (4K FMA per term)
     return SYNTH_SLOTS if K >= 3 else SYNTH_SLOTS + 4 * K
+
+
+def mfma_flops_per_term(K: int, prec: str) -> int:
+    # 8K real flops per term (K complex MACs); the split products run three
+    return 8 * K * (3 if prec in ("f16x3", "bf16x3") else 1)
 
 
 def _src_hash(files):
@@ -72,7 +100,7 @@ def _src_hash(files):
     return h.hexdigest()[:16]
 
 
-# every file the map kernels are compiled from (the traffic summary is only
+# every file the map kernels are compiled from (a traffic summary is only
 # valid for these exact sources)
 POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
                     "paper_2304_12745_amd/csrc/powermap_mfma.hip",
@@ -82,16 +110,17 @@ POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
                     "paper_2304_12745_amd/csrc/split16.h",
                     "paper_2304_12745_amd/csrc/kernels.h",
                     "paper_2304_12745_amd/csrc/dmimo_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_hall_traffic.json")
+ROOM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
 
 
-def load_traffic(kernel_hash: str):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary.
+def load_traffic(kernel_hash: str, path: str = None):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary.
 
     None if there is none, or if it was taken on other kernel sources.
     """
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -100,37 +129,323 @@ def load_traffic(kernel_hash: str):
     return t.get("bytes_per_launch")
 
 
+def host_info():
+    """Host CPU model and core count (where the oracle baseline runs)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
 def parse_args():
     p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=500)
-    p.add_argument("--warmup", type=int, default=2000,
-                   help="untimed steps first (enough to bring the GPU clocks up)")
-    p.add_argument("--event-every", type=int, default=10,
-                   help="record the map event pair on every n-th timed step (each pair "
-                        "puts two markers in the queue, about 7 us per step)")
-    p.add_argument("--nx", type=int, default=512)
-    p.add_argument("--streams", type=int, default=2,
-                   help="HIP streams the timed steps rotate over (independent steps, each "
-                        "stream with its own outputs); 1 = every step on one stream")
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--ramp-seconds", type=float, default=0.3,
+                   help="untimed map launches before the first warm-up step (brings the GPU "
+                        "clocks up; not counted as warm-up steps)")
+    p.add_argument("--event-launches", type=int, default=30,
+                   help="map launches in the dedicated HIP-event pass of the roofline (>= 20)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
-                   help="budget of the oracle CPU baseline (0 disables it)")
+                   help="wall budget of the all-core oracle baseline (the one-core leg takes "
+                        "half of it); 0 disables both")
+    p.add_argument("--cpu-workers", type=int, default=16,
+                   help="at most this many oracle processes (the GPU box's CPU share is 16)")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--serve-seconds", type=float, default=5.0,
+    p.add_argument("--serve-seconds", type=float, default=30.0,
                    help="measured window of the serving phase (0 disables it)")
-    p.add_argument("--serve-warmup", type=float, default=1.0)
+    p.add_argument("--serve-warmup", type=float, default=5.0)
     p.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (1/s)")
     p.add_argument("--serve-prec", default="f32", choices=["f32", "f16x3", "bf16x3"])
-    p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision step")
+    p.add_argument("--serve-sweep", action="store_true",
+                   help="also serve at 500, 1000, 2000 and 4000 queries/s (3 s each)")
+    p.add_argument("--room-steps", type=int, default=500)
+    p.add_argument("--room-warmup", type=int, default=2000)
+    p.add_argument("--room-streams", type=int, default=2)
+    p.add_argument("--event-every", type=int, default=10,
+                   help="room step: record the map event pair on every n-th timed step")
+    p.add_argument("--nx", type=int, default=512, help="room grid side")
+    p.add_argument("--no-room", action="store_true")
+    p.add_argument("--no-twins", action="store_true", help="skip the FP32 and BF16x3 hall steps")
     p.add_argument("--no-pgd", action="store_true", help="skip the PGD / unfolded-PGD phase")
     p.add_argument("--no-pa", action="store_true", help="skip the PA-aware precoder phase")
     p.add_argument("--no-channel", action="store_true",
                    help="skip the materialised-channel bandwidth phase")
     p.add_argument("--no-batched", action="store_true",
-                   help="skip the batched Gram + ZF sweep over B")
-    p.add_argument("--serve-sweep", action="store_true",
-                   help="also serve at 500, 1000, 2000 and 4000 queries/s (3 s each)")
+                   help="skip the batched Gram + ZF phase")
+    p.add_argument("--only-hall", action="store_true",
+                   help="the hall steps and their roofline only (profiling runs)")
     return p.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# oracle legs (CPU; imported only here)
+# ---------------------------------------------------------------------------
+
+HALL_ERR_ROWS = (0, 301, 602, 1023, 1024, 1445, 1746, 2047)
+
+
+def _hall_oracle_rows(rows):
+    """Oracle chain of the hall step for the given grid rows: the users'
+    channel and ZF at 1 W, then power and SINR maps on those rows.  Returns
+    (terms, power [rows][nx], sinr [rows][nx], user SINR [K])."""
+    import numpy as np
+    from oracle import dmimo_oracle as O
+    from paper_2304_12745_amd import workloads as WL
+    w = WL.hall_workload()
+    g = w.grid
+    aps = w.ap_xyz[0]
+    Hu = O.los_channel(w.user_xyz[0], aps, w.freq_hz)
+    Wz, _ = O.zf_precoder(Hu, None, w.sigma2, w.p_total)
+    su = O.user_sinr(Hu, Wz, w.sigma2)
+    O.antenna_power(Wz)
+    O.l21_norm(Wz)
+    terms = 2 * w.K * w.M
+    pw, sn = [], []
+    xs = g.x0 + (np.arange(g.nx) + 0.5) * g.dx
+    for j in rows:
+        y = g.y0 + (j + 0.5) * g.dy
+        pts = np.stack([xs, np.full(g.nx, y), np.full(g.nx, g.z)], axis=1)
+        Hg = O.los_channel(pts, aps, w.freq_hz)
+        pw.append(O.power_map(Hg, Wz))
+        sn.append(O.sinr_map(Hg, Wz, w.sigma2)[0])
+        terms += g.nx * w.M
+    return terms, np.array(pw), np.array(sn), su
+
+
+def _oracle_worker(args):
+    """One oracle process: rows start, start + stride, ... until the deadline
+    (wall clock).  One numpy/BLAS thread."""
+    start, stride, deadline = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        terms, n, j = 0, 0, start
+        while time.time() < deadline or n == 0:
+            t, _, _, _ = _hall_oracle_rows([j % 2048])
+            terms += t
+            n += 1
+            j += stride
+    return terms, n
+
+
+def cpu_baseline_hall(budget_s: float, max_workers: int):
+    """The FP64 oracle on the hall step, timed on all host cores (one process
+    each, rows dealt round-robin) and on one core, before any GPU call.  Also
+    returns the oracle values that the error report compares with."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    info = host_info()
+    # the error rows first (one core, untimed)
+    with threadpool_limits(limits=1):
+        _, ref_p, ref_s, ref_u = _hall_oracle_rows(HALL_ERR_ROWS)
+    ref = {"power": ref_p, "sinr": ref_s, "user_sinr": ref_u}
+    if budget_s <= 0:
+        return None, ref
+    workers = max(1, min(max_workers, info["nproc"] or 1))
+    ctx = mp.get_context("fork")       # no GPU has been touched in this process yet
+    t0 = time.time()
+    deadline = t0 + budget_s
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_worker, [(i * 7, workers * 7 + 1, deadline) for i in range(workers)])
+    el_all = time.time() - t0
+    terms_all = sum(r[0] for r in res)
+    rows_all = sum(r[1] for r in res)
+    # one core
+    one_budget = budget_s / 2
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        terms1, n1, j = 0, 0, 3
+        while time.perf_counter() - t0 < one_budget or n1 == 0:
+            t, _, _, _ = _hall_oracle_rows([j % 2048])
+            terms1 += t
+            n1 += 1
+            j += 97
+        el1 = time.perf_counter() - t0
+    full = 2 * 32 * 1024 + 2048 * 2048 * 1024
+    v_all = terms_all / el_all / 1e9
+    v1 = terms1 / el1 / 1e9
+    cpu = {
+        "value": round(v_all, 6),
+        "unit": "G h/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": (f"hall step, oracle chain (users' channel + ZF + power and SINR map rows), "
+                   f"{rows_all} grid rows of 2048 points x 1024 APs x 32 streams on {workers} "
+                   f"processes (one BLAS thread each) in {el_all:.1f} s; work per row is "
+                   f"uniform, so the rate extrapolates linearly to the full map: "
+                   f"{full / (v_all * 1e9):.0f} s per step"),
+        "one_core": {"value": round(v1, 6), "unit": "G h/s",
+                     "sample": f"{n1} grid rows in {el1:.1f} s"},
+        "host": info,
+    }
+    return cpu, ref
+
+
+def db_report(y, ref, tol, floor_rel=1e-6):
+    from oracle import dberror
+    s = dberror.summary(y, ref, tol, floor_rel)
+    return {"max_db": s["max_db"], "p99_db": s["p99_db"], "n": s["n"],
+            "n_below_floor": s["n_below_floor"], f"n_over_{tol}dB": s["n_fail"]}
+
+
+def plain_db(y, ref):
+    import numpy as np
+    e = np.abs(10.0 * np.log10(np.asarray(y, np.float64) / np.asarray(ref, np.float64))).ravel()
+    return {"max_db": float(e.max()), "p99_db": float(np.percentile(e, 99)), "n": int(e.size)}
+
+
+# ---------------------------------------------------------------------------
+# the hall step
+# ---------------------------------------------------------------------------
+
+class HallStep:
+    """The hall step at one precision, with its outputs preallocated."""
+
+    def __init__(self, D, WL, torch, prec):
+        self.D, self.torch, self.prec = D, torch, prec
+        w = self.w = WL.hall_workload()
+        self.K, self.M, self.N = w.K, w.M, w.grid.n
+        self.params = D.channel_params(w.freq_hz)
+        self.ap = torch.from_numpy(w.ap_xyz).cuda()            # [1][M][3]
+        self.ap0 = self.ap[0].contiguous()
+        self.users = torch.from_numpy(w.user_xyz).cuda()      # [1][K][3]
+        self.gpts = D.grid_points(w.grid)
+        self.pre = D.beamform_users(self.params, self.ap, self.users, ("zf",), None, w.sigma2,
+                                    w.p_total, prec)
+        self.W = self.pre.W[0, 0]                              # [K][M], contiguous
+        N = self.N
+        self.maps = D.MapResult(torch.empty(N, device="cuda"), torch.empty(N, device="cuda"),
+                                torch.empty(N, dtype=torch.int32, device="cuda"), None)
+        self.terms = 2 * self.K * self.M + N * self.M
+
+    def precoder(self):
+        w = self.w
+        self.D.beamform_users(self.params, self.ap, self.users, ("zf",), None, w.sigma2,
+                              w.p_total, self.prec, out=self.pre)
+
+    def map(self):
+        self.D.powermap(self.params, self.ap0, self.W, self.gpts, self.w.sigma2, self.prec,
+                        out=self.maps)
+
+    def step(self):
+        self.precoder()
+        self.map()
+
+    def timed(self, warmup, steps):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def map_events(self, launches):
+        """Mean duration of the map launch: one HIP-event pair around each of
+        `launches` back-to-back launches on the launching stream (torch's
+        current stream, which the binding passes to the library)."""
+        torch = self.torch
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]
+        self.map()
+        torch.cuda.synchronize()
+        for i in range(launches):
+            ev[2 * i].record()
+            self.map()
+            ev[2 * i + 1].record()
+        torch.cuda.synchronize()
+        ts = sorted(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(launches))
+        return sum(ts) / launches, ts[0], ts[len(ts) // 2]
+
+    def ramp(self, seconds):
+        torch = self.torch
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            for _ in range(10):
+                self.map()
+            torch.cuda.synchronize()
+
+    def sampled(self):
+        """Map rows HALL_ERR_ROWS and the users' SINR, on the host."""
+        import numpy as np
+        torch = self.torch
+        torch.cuda.synchronize()
+        nx = self.w.grid.nx
+        p = self.maps.power.view(-1, nx)[list(HALL_ERR_ROWS)].double().cpu().numpy()
+        s = self.maps.sinr.view(-1, nx)[list(HALL_ERR_ROWS)].double().cpu().numpy()
+        u = self.pre.sinr[0, 0].cpu().numpy()
+        return {"power": p, "sinr": s, "user_sinr": np.asarray(u), "info": int(self.pre.info[0, 0])}
+
+
+def hall_phase(args, D, WL, torch):
+    """The headline (FP16x3) and its FP32 and BF16x3 twins."""
+    out = {}
+    head = HallStep(D, WL, torch, "f16x3")
+    head.ramp(args.ramp_seconds)
+    ms = head.timed(args.warmup, args.steps)
+    launch, lmin, lmed = head.map_events(max(20, args.event_launches))
+    out["f16x3"] = {"ms_per_step": ms, "map_launch_ms": launch, "map_launch_min_ms": lmin,
+                    "map_launch_median_ms": lmed, "sample": head.sampled(), "step": head}
+    if not args.no_twins:
+        for prec in ("f32", "bf16x3"):
+            tw = HallStep(D, WL, torch, prec)
+            ms = tw.timed(args.warmup, args.steps)
+            launch, lmin, lmed = tw.map_events(max(20, args.event_launches))
+            out[prec] = {"ms_per_step": ms, "map_launch_ms": launch, "map_launch_min_ms": lmin,
+                         "map_launch_median_ms": lmed, "sample": tw.sampled()}
+            del tw
+            torch.cuda.empty_cache()
+    return out
+
+
+def hall_roofline(K, N, M, prec, launch_ms, khash, traffic):
+    terms = N * M
+    slots = alg_slots_per_term(K, prec)
+    achieved = slots * terms / (launch_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_SLOTS / 1e12
+    mf = mfma_flops_per_term(K, prec) * terms
+    mpeak = MFMA_F16_PEAK if prec in ("f16x3", "bf16x3") else MFMA_F32_PEAK
+    t_valu = slots * terms / VALU_PEAK_SLOTS
+    t_mfma = mf / mpeak
+    kern = {"f16x3": "powermap_x3w_kernel<4, 2, false, 8>",
+            "bf16x3": "powermap_x3w_kernel<4, 2, true, 8>",
+            "f32": "powermap_mfma_kernel<4, 2, 8>"}[prec]
+    return {
+        "bound": "alu",
+        "kernel": f"{kern}, the 2048 x 2048 hall map (K = 32, M = 1024)",
+        "achieved": round(achieved, 3),
+        "peak": round(peak, 3),
+        "unit": "T VALU lane-slots/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": traffic,
+        "launch_ms": round(launch_ms, 5),
+        "alg_slots_per_term": slots,
+        "terms_per_launch": terms,
+        "mfma": {"achieved": round(mf / (launch_ms * 1e-3) / 1e12, 3),
+                 "peak": round(mpeak / 1e12, 1), "unit": "TFLOP/s",
+                 "frac": round(mf / (launch_ms * 1e-3) / mpeak, 4),
+                 "flops_per_term": mfma_flops_per_term(K, prec)},
+        # the FP16/BF16 matrix cores overlap the VALU (the floor is the larger
+        # of the two times); FP32 MFMA does not (the floor is their sum)
+        "floor_ms": round((max(t_valu, t_mfma) if prec != "f32" else t_valu + t_mfma) * 1e3, 4),
+        "frac_of_floor": round((max(t_valu, t_mfma) if prec != "f32" else t_valu + t_mfma) * 1e3
+                               / launch_ms, 4),
+        "source_hash": khash,
+    }
 
 
 def main():
@@ -145,143 +460,280 @@ def main():
     import numpy as np
     import torch
 
+    # counting devices does not initialise the GPU, so the oracle processes
+    # below can still be forked from this one
+    if torch.cuda.device_count() < 1:
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
     from paper_2304_12745_amd import dmimo as D
     from paper_2304_12745_amd import workloads as WL
+
+    cpu, ref = None, None
+    if not args.no_cpu:
+        cpu, ref = cpu_baseline_hall(args.cpu_seconds, args.cpu_workers)
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     D.lib()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    w = WL.room_workload(nx=args.nx, ny=args.nx)
-    K, M, N = w.K, w.M, w.grid.n
-    params = D.channel_params(w.freq_hz)
-    ap = torch.from_numpy(w.ap_xyz).to(dev)            # [1][M][3]
-    ap0 = ap[0].contiguous()
-    users = torch.from_numpy(w.user_xyz).to(dev)       # [1][K][3]
-    gpts = D.grid_points(w.grid)
-    H = torch.empty((1, K, M), dtype=torch.complex64, device=dev)
+    torch.cuda.set_device(0)
 
     # a plain copy of known size, for scaling the HBM counters of a profiled run
-    cp_src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    cp_src = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
     cp_dst = torch.empty_like(cp_src)
     cp_dst.copy_(cp_src)
 
-    # one stream: the map launch's own duration (HIP events) for the roofline
-    ms_one, map_launch_ms, maps, bf = run_steps(args, "f32", w, D, params, ap, ap0, users,
-                                                gpts, H)
-    ms_per_step = ms_one
-    if args.streams > 1:
-        # the headline: steps in flight on args.streams streams
-        ms_per_step = run_steps(args, "f32", w, D, params, ap, ap0, users, gpts, H,
-                                nstreams=args.streams)[0]
-    mixed = None
-    if not args.no_mixed:
-        ms_mix, launch_mix, maps_mix, _ = run_steps(args, "f16x3", w, D, params, ap, ap0, users,
-                                                    gpts, H)
-        dev_db = {}
-        for p in ("mr", "zf"):
-            a = maps_mix[p].power.double()
-            b = maps[p].power.double()
-            keep = b > 1e-6 * b.max()     # the -60 dB floor of the error rule
-            dev_db[p] = float((10 * torch.log10(a[keep] / b[keep])).abs().max())
-        ms_mix_n = None
-        if args.streams > 1:
-            ms_mix_n = round(run_steps(args, "f16x3", w, D, params, ap, ap0, users, gpts, H,
-                                       nstreams=args.streams)[0], 5)
-        mixed = {"dtype": "f16x3 (FP16 hi/lo x3 MFMA, FP32 accumulate)", "streams": 1,
-                 "ms_per_step": round(ms_mix, 5), "maps_launch_ms": round(launch_mix, 5),
-                 "speedup_vs_f32_step": round(ms_one / ms_mix, 3),
-                 "ms_per_step_streams": ms_mix_n,
-                 "max_db_vs_f32_maps": dev_db}
-
-    terms_per_step = 3 * K * M + 2 * N * M
-    value = terms_per_step / (ms_per_step * 1e-3) / 1e9
-    terms_per_launch = 2 * N * M          # both maps in one launch
-    alg = alg_slots_per_term(K) * terms_per_launch
-    achieved = alg / (map_launch_ms * 1e-3) / 1e12
-    peak = VALU_PEAK_SLOTS / 1e12
-    mfma_tflops = 8 * K * terms_per_launch / (map_launch_ms * 1e-3) / 1e12
+    hall = hall_phase(args, D, WL, torch)
+    head = hall["f16x3"]
+    hs = head.pop("step")
+    K, M, N = hs.K, hs.M, hs.N
+    terms = hs.terms
+    value = terms / (head["ms_per_step"] * 1e-3) / 1e9
     khash = _src_hash(POWERMAP_SOURCES)
     traffic = load_traffic(khash)
 
     out = {
-        "metric": "channel-term evals/sec (G h[n,m]/s)",
+        "metric": "channel-term evals/sec (G h[n,m]/s) + p99 query latency, mixed vs FP32",
         "value": round(value, 3),
         "unit": "G h/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "streams": args.streams,
-        "one_stream": {"ms_per_step": round(ms_one, 5),
-                       "value": round(terms_per_step / (ms_one * 1e-3) / 1e9, 3)},
+        "ms_per_step": round(head["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16x3",
         "data": "synthetic",
         "config": {
-            "workload": f"room: M={M} APs jittered 8x8 ceiling grid 20x20x4 m, K={K} users, "
-                        f"3.5 GHz, MR+ZF at 1 W, noise -90 dBm, {w.grid.nx}x{w.grid.ny} power+SINR "
-                        "maps at z=1.2 m; FP64 distance/phase, FP32 synthesis and contraction",
-            "M": M, "K": K, "N": N, "terms_per_step": terms_per_step,
+            "workload": "hall: M=1024 APs on a regular 32x32 ceiling grid (pitch 1.5625 m, z=5 m) "
+                        "of a 50x50x5 m hall, 5.8 GHz, K=32 users at z=1 m, ZF at 1 W, noise "
+                        "-90 dBm, 2048x2048 power+SINR map at z=1 m; FP64 distance/phase, FP32 "
+                        "synthesis, FP16 hi/lo x3 MFMA contraction with FP32 accumulation",
+            "M": M, "K": K, "N": N, "terms_per_step": terms,
+            "step": "dmimo_beamform_users (users' LoS channels + ZF, wide path) + dmimo_powermap",
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "powermap_mfma_kernel<1,4,8>, grid 512 x 2 (MR and ZF maps in one launch)",
-            "achieved": round(achieved, 3),
-            "peak": round(peak, 3),
-            "unit": "T VALU lane-slots/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": traffic,
-            "launch_ms": round(map_launch_ms, 5),
-            "event_samples": len(range(0, args.steps, max(1, args.event_every))),
-            "alg_slots_per_term": alg_slots_per_term(K),
-            "mfma_f32": {"achieved": round(mfma_tflops, 3), "peak": MFMA_F32_PEAK / 1e12,
-                         "unit": "TFLOP/s", "frac": round(mfma_tflops * 1e12 / MFMA_F32_PEAK, 4),
-                         "flops_per_term": 8 * K},
-            # the matrix unit and the VALU do not co-issue on this kernel
-            # (SQ_VALU_MFMA_COEXEC_CYCLES = 0), so its floor is the sum of the
-            # synthesis at the VALU peak and the contraction at the MFMA peak
-            "serial_valu_mfma": {
-                "floor_ms": round((alg / VALU_PEAK_SLOTS + 8 * K * terms_per_launch / MFMA_F32_PEAK)
-                                  * 1e3, 5),
-                "frac": round((alg / VALU_PEAK_SLOTS + 8 * K * terms_per_launch / MFMA_F32_PEAK) * 1e3
-                              / map_launch_ms, 4)},
-            "terms_per_launch": terms_per_launch,
-            "source_hash": khash,
-        },
+        "roofline": hall_roofline(K, N, M, "f16x3", head["map_launch_ms"], khash, traffic),
     }
+    out["roofline"]["event_samples"] = max(20, args.event_launches)
+    out["roofline"]["launch_min_ms"] = round(head["map_launch_min_ms"], 5)
+    out["roofline"]["launch_median_ms"] = round(head["map_launch_median_ms"], 5)
 
-    if mixed is not None:
-        mixed["value"] = round(terms_per_step / (mixed["ms_per_step"] * 1e-3) / 1e9, 3)
-        out["mixed"] = mixed
-    if not args.no_channel:
-        out["channel"] = channel_phase(D, WL, torch, params, ap, gpts, N)
-    if not args.no_batched:
-        out["batched"] = batched_phase(D, torch)
-    if args.serve_seconds > 0:
-        out["serving"] = serving_phase(args, D, WL, torch)
-    if args.serve_sweep:
-        sweep = []
-        for rate in (500.0, 1000.0, 2000.0, 4000.0):
-            a2 = argparse.Namespace(**vars(args))
-            a2.serve_rate, a2.serve_seconds = rate, 3.0
-            r = serving_phase(a2, D, WL, torch)
-            sweep.append({k: r[k] for k in ("rate_qps", "queries", "p50_ms", "p99_ms", "max_ms",
-                                            "sustained_Gh_per_s", "offered_Gh_per_s")})
-        out["serving_sweep"] = sweep
-    if not args.no_pgd:
-        out["pgd"] = pgd_phase(args, D, WL, torch)
-    if not args.no_pa:
-        out["pa"] = pa_phase(w, D, WL, torch, params, ap0, gpts)
-    if not args.no_cpu and args.cpu_seconds > 0:
-        out["cpu_baseline"], out["err_db"] = cpu_baseline(w, bf, maps, args.cpu_seconds)
+    # the twins: the same step in FP32 and in BF16x3
+    for prec in ("f32", "bf16x3"):
+        if prec not in hall:
+            continue
+        h = hall[prec]
+        out["fp32" if prec == "f32" else prec] = {
+            "ms_per_step": round(h["ms_per_step"], 5),
+            "value": round(terms / (h["ms_per_step"] * 1e-3) / 1e9, 3),
+            "map_launch_ms": round(h["map_launch_ms"], 5),
+            "roofline": hall_roofline(K, N, M, prec, h["map_launch_ms"], khash, None),
+        }
+    if "f32" in hall:
+        out["mixed_vs_fp32"] = {
+            "speedup_step": round(hall["f32"]["ms_per_step"] / head["ms_per_step"], 3),
+            "speedup_map_launch": round(hall["f32"]["map_launch_ms"] / head["map_launch_ms"], 3)}
+
+    # every result of the GPU chain against the oracle chain, per precision
+    if ref is not None:
+        err = {}
+        tol = {"f16x3": 0.1, "bf16x3": 0.1, "f32": 0.01}
+        for prec in ("f16x3", "f32", "bf16x3"):
+            if prec not in hall:
+                continue
+            smp = hall[prec]["sample"]
+            err[prec] = {"power": db_report(smp["power"], ref["power"], tol[prec]),
+                         "sinr": db_report(smp["sinr"], ref["sinr"], tol[prec]),
+                         "user_sinr": plain_db(smp["user_sinr"], ref["user_sinr"]),
+                         "zf_info": smp["info"]}
+        err["compared"] = (f"GPU chain (users' channel -> ZF -> map) vs the FP64 oracle chain, "
+                           f"grid rows {list(HALL_ERR_ROWS)} ({len(HALL_ERR_ROWS) * 2048} points) "
+                           f"and the 32 users' SINR_k; tolerance 0.1 dB mixed, 0.01 dB FP32, "
+                           f"floor rule at -60 dB below the sample's peak")
+        out["err_db"] = err
+    for prec in hall:
+        hall[prec].pop("sample", None)
+    del hs
+    torch.cuda.empty_cache()
+
+    if not args.only_hall:
+        if not args.no_room:
+            out["room"] = room_phase(args, D, WL, torch)
+        out["focus"] = focus_phase(D, WL, torch)
+        out["paper"] = paper_phase(D, WL, torch)
+        if not args.no_channel:
+            out["channel"] = channel_phase(D, WL, torch)
+        if not args.no_batched:
+            out["batched"] = batched_phase(D, WL, torch)
+        if args.serve_seconds > 0:
+            out["serving"] = serving_phase(args, D, WL, torch)
+            out["p99_query_ms"] = out["serving"]["p99_ms"]
+        if args.serve_sweep:
+            sweep = []
+            for rate in (500.0, 1000.0, 2000.0, 4000.0):
+                a2 = argparse.Namespace(**vars(args))
+                a2.serve_rate, a2.serve_seconds, a2.serve_warmup = rate, 3.0, 1.0
+                r = serving_phase(a2, D, WL, torch)
+                sweep.append({k: r[k] for k in ("rate_qps", "queries", "p50_ms", "p99_ms", "max_ms",
+                                                "sustained_Gh_per_s", "offered_Gh_per_s")})
+            out["serving_sweep"] = sweep
+        if not args.no_pgd:
+            out["pgd"] = pgd_phase(args, D, WL, torch)
+        if not args.no_pa:
+            out["pa"] = pa_phase(WL.room_workload(nx=args.nx, ny=args.nx), D, WL, torch)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
 
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# secondary configurations
+# ---------------------------------------------------------------------------
+
+def room_phase(args, D, WL, torch):
+    """The room step (M = 64, K = 8, MR + ZF, two 512x512 power + SINR +
+    best-stream maps), FP32 and FP16x3, on one stream and on several; its map
+    launch duration from HIP events; the GPU chain against the oracle chain on
+    sampled rows."""
+    w = WL.room_workload(nx=args.nx, ny=args.nx)
+    K, M, N = w.K, w.M, w.grid.n
+    params = D.channel_params(w.freq_hz)
+    ap = torch.from_numpy(w.ap_xyz).cuda()
+    ap0 = ap[0].contiguous()
+    users = torch.from_numpy(w.user_xyz).cuda()
+    gpts = D.grid_points(w.grid)
+    H = torch.empty((1, K, M), dtype=torch.complex64, device="cuda")
+    ra = argparse.Namespace(steps=args.room_steps, warmup=args.room_warmup,
+                            event_every=args.event_every)
+    ms_one, launch, maps, _ = run_steps(ra, "f32", w, D, params, ap, ap0, users, gpts, H)
+    ms_n = run_steps(ra, "f32", w, D, params, ap, ap0, users, gpts, H,
+                     nstreams=args.room_streams)[0] if args.room_streams > 1 else ms_one
+    ms_mix, launch_mix, maps_mix, _ = run_steps(ra, "f16x3", w, D, params, ap, ap0, users, gpts, H)
+    terms = 3 * K * M + 2 * N * M
+    khash = _src_hash(POWERMAP_SOURCES)
+    slots = alg_slots_per_term(K)
+    res = {
+        "workload": f"room: M={M} APs jittered 8x8 ceiling grid 20x20x4 m, K={K} users, 3.5 GHz, "
+                    f"MR+ZF at 1 W, noise -90 dBm, {w.grid.nx}x{w.grid.ny} power+SINR+best-stream "
+                    "maps at z=1.2 m (both maps in one launch)",
+        "terms_per_step": terms,
+        "f32": {"ms_per_step_one_stream": round(ms_one, 5),
+                "value_one_stream": round(terms / (ms_one * 1e-3) / 1e9, 3),
+                "streams": args.room_streams, "ms_per_step": round(ms_n, 5),
+                "value": round(terms / (ms_n * 1e-3) / 1e9, 3),
+                "maps_launch_ms": round(launch, 5)},
+        "f16x3": {"ms_per_step_one_stream": round(ms_mix, 5),
+                  "value_one_stream": round(terms / (ms_mix * 1e-3) / 1e9, 3),
+                  "maps_launch_ms": round(launch_mix, 5)},
+        "roofline": {"bound": "alu", "kernel": "powermap_mfma_kernel<1, 4, 8>, grid 512 x 2",
+                     "alg_slots_per_term": slots,
+                     "frac": round(slots * 2 * N * M / (launch * 1e-3) / VALU_PEAK_SLOTS, 4),
+                     "mfma_f32_frac": round(8 * K * 2 * N * M / (launch * 1e-3) / MFMA_F32_PEAK, 4),
+                     "launch_ms": round(launch, 5),
+                     "traffic": load_traffic(khash, ROOM_TRAFFIC_FILE), "source_hash": khash},
+    }
+    res["err_db"] = room_errors(w, maps, maps_mix)
+    return res
+
+
+def room_errors(w, maps, maps_mix, rows=(0, 1, 137, 255, 256, 511)):
+    """The GPU maps of the room step (GPU H -> GPU W -> GPU map) against the
+    oracle chain on sampled rows, FP32 and FP16x3."""
+    import numpy as np
+    from oracle import dmimo_oracle as O
+    g = w.grid
+    aps = w.ap_xyz[0]
+    Hu = O.los_channel(w.user_xyz[0], aps, w.freq_hz)
+    Wp = {"mr": O.mr_precoder(Hu, w.p_total), "zf": O.zf_precoder(Hu, None, w.sigma2, w.p_total)[0]}
+    xs = g.x0 + (np.arange(g.nx) + 0.5) * g.dx
+    pts = np.concatenate([np.stack([xs, np.full(g.nx, g.y0 + (j + 0.5) * g.dy),
+                                    np.full(g.nx, g.z)], axis=1) for j in rows])
+    Hg = O.los_channel(pts, aps, w.freq_hz)
+    out = {}
+    for tag, mp, tol in (("f32", maps, 0.01), ("f16x3", maps_mix, 0.1)):
+        for p in ("mr", "zf"):
+            pw = mp[p].power.view(g.ny, g.nx)[list(rows)].double().cpu().numpy().ravel()
+            sn = mp[p].sinr.view(g.ny, g.nx)[list(rows)].double().cpu().numpy().ravel()
+            out[f"{tag}_{p}"] = {"power": db_report(pw, O.power_map(Hg, Wp[p]), tol),
+                                 "sinr": db_report(sn, O.sinr_map(Hg, Wp[p], w.sigma2)[0], tol)}
+    out["compared"] = f"GPU chain vs oracle chain, grid rows {list(rows)}"
+    return out
+
+
+def focus_phase(D, WL, torch):
+    """The FP64 MR focusing map (M = 16 APs, 920 MHz, 64x64 grid): the focal
+    point's channel, MR at 1 W and the map, all in FP64; every point against
+    the oracle, and the focal-point closed form y = P sum_m |h_m|^2."""
+    import numpy as np
+    from oracle import dmimo_oracle as O
+    w = WL.focus_workload()
+    params = D.channel_params(w.freq_hz)
+    ap = torch.from_numpy(w.ap_xyz).cuda()
+    foc = torch.from_numpy(w.focal_xyz[None]).cuda()          # [1][1][3]
+    gpts = D.grid_points(w.grid)
+
+    def run():
+        Hf = D.channel(params, ap, D.list_points(foc, 1), prec="f64")
+        r = D.beamform(Hf, "mr", None, w.sigma2, w.p_total, "f64")
+        return D.powermap(params, ap[0].contiguous(), r.W[0], gpts, w.sigma2, "f64")
+    m = run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        m = run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    aps = w.ap_xyz[0]
+    Hf = O.los_channel(w.focal_xyz, aps, w.freq_hz)
+    Wm = O.mr_precoder(Hf, w.p_total)
+    Hg = O.los_channel(O.grid_points(*[getattr(w.grid, k) for k in ("x0", "y0", "dx", "dy", "z",
+                                                                  "nx", "ny")]), aps, w.freq_hz)
+    y = m.power.cpu().numpy()
+    s = m.sinr.cpu().numpy()
+    return {"workload": "focus: M=16 APs on the ceiling (z=3 m) of a 10x10x3 m room, 920 MHz, "
+                        "MR at 1 W focused on one point at z=1 m, 64x64 map at z=1 m, FP64",
+            "ms_per_call_chain": round(ms, 4),
+            "terms": int(w.grid.n * w.M + 2 * w.M),
+            "err_db": {"power": db_report(y, O.power_map(Hg, Wm), 1e-9),
+                       "snr": db_report(s, O.sinr_map(Hg, Wm, w.sigma2)[0], 1e-9),
+                       "focal_closed_form_db": float(abs(10 * np.log10(
+                           y.max() / (w.p_total * np.sum(np.abs(Hf) ** 2)))))}}
+
+
+def paper_phase(D, WL, torch):
+    """The paper's ZF on its own workload (5000 Rayleigh channels, K = 8,
+    M = 64, gamma 10 dB, sigma 1; Sec. VI-B): every SINR_k must equal the
+    target and R_sum = 8 log2 11 = 27.68 bit/symbol.  GPU against the oracle
+    and against that closed form, and the MR sum rate against the oracle."""
+    import numpy as np
+    from oracle import dmimo_oracle as O
+    w = WL.paper_workload(seed=0, B=5000)
+    H = torch.from_numpy(w.H.astype(np.complex64)).cuda()
+    zf = D.beamform(H, "zf", w.gamma_lin, w.sigma2, 0.0, "f32")
+    mr = D.beamform(H, "mr", None, w.sigma2, 0.0, "f32")
+    torch.cuda.synchronize()
+    Hc = w.H.astype(np.complex64).astype(np.complex128)
+    idx = np.arange(0, 5000, 50)
+    Wz, _ = O.zf_precoder(Hc[idx], w.gamma_lin, w.sigma2, 0.0)
+    sz = O.user_sinr(Hc[idx], Wz, w.sigma2)
+    Wm = O.mr_precoder(Hc[idx], 0.0)
+    sm = O.user_sinr(Hc[idx], Wm, w.sigma2)
+    g_sinr = zf.sinr.cpu().numpy()
+    rs = zf.rsum.cpu().numpy()
+    target = 8 * np.log2(11.0)
+    return {"workload": "paper: 5000 Rayleigh channels CN(0,1), K=8, M=64, gamma 10 dB, sigma 1; "
+                        "ZF with the constraint of eq. (optim1), MR = H^*",
+            "zf_rsum_mean": float(rs.mean()), "zf_rsum_paper": round(target, 4),
+            "zf_rsum_max_abs_err": float(np.abs(rs - target).max()),
+            "err_db": {"zf_user_sinr_vs_oracle": plain_db(g_sinr[idx], sz),
+                       "zf_user_sinr_vs_target": plain_db(g_sinr, np.full(g_sinr.shape, 10.0)),
+                       "mr_user_sinr_vs_oracle": plain_db(mr.sinr.cpu().numpy()[idx], sm),
+                       "compared": "100 sampled channels vs the oracle; all 5000 vs the 10 dB target"}}
 
 
 def run_steps(args, prec, w, D, params, ap, ap0, users, gpts, H, nstreams=1):
@@ -387,7 +839,7 @@ def run_streams(args, prec, w, D, params, ap, ap0, users, gpts, nstreams):
 HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
 
 
-def channel_phase(D, WL, torch, params, ap, gpts, N):
+def channel_phase(D, WL, torch):
     """dmimo_channel materialising H in HBM, an HBM-write-bound kernel: the
     room grid (512 x 512 points x 64 APs) in complex64 and complex128, and the
     hall grid (2048 x 2048 points x 1024 APs, 34.4 GB) in complex64.  Kernel
@@ -409,11 +861,15 @@ def channel_phase(D, WL, torch, params, ap, gpts, N):
         nbytes = n * m * (16 if prec == "f64" else 8)
         return {"ms": round(ms, 4), "G_h_per_s": round(n * m / ms / 1e6, 1),
                 "GB_per_s": round(nbytes / ms / 1e6, 1), "hbm_frac": round(nbytes / (ms * 1e-3) / HBM_PEAK, 3)}
-    M = ap.shape[1]
+    w = WL.room_workload()
+    params = D.channel_params(w.freq_hz)
+    ap = torch.from_numpy(w.ap_xyz).cuda()
+    gpts = D.grid_points(w.grid)
+    N, M = w.grid.n, w.M
     out = {"room_f32": run(params, ap, gpts, N, M, "f32", 50),
            "room_f64": run(params, ap, gpts, N, M, "f64", 50)}
     hw = WL.hall_workload()
-    hap = torch.from_numpy(hw.ap_xyz).to(ap.device)
+    hap = torch.from_numpy(hw.ap_xyz).cuda()
     out["hall_f32"] = run(D.channel_params(hw.freq_hz), hap, D.grid_points(hw.grid), hw.grid.n,
                           hw.M, "f32", 5)
     out["workload"] = ("room: 512 x 512 grid x 64 APs (16.8 M terms); hall: 2048 x 2048 grid x "
@@ -421,43 +877,89 @@ def channel_phase(D, WL, torch, params, ap, gpts, N):
     return out
 
 
-def batched_phase(D, torch):
-    """Batched Gram + ZF (dmimo_beamform at 1 W, -90 dBm) on B deployments of
-    K = 16 users and M = 256 antennas, B = 2^10 .. 2^17, with the FP32 and
-    the FP16x3 Gram.  The cost does not depend on the channel values, so H is
-    CN(0,1), drawn on the device by torch with a fixed seed.  Units: B K M
-    terms per call; time from HIP events around back-to-back calls."""
+def batched_phase(D, WL, torch):
+    """Batched mixed-precision ZF (B deployments of K = 16 users and M = 256
+    antennas, 5.8 GHz).
+
+    * ``rician``: the configuration as defined: 1024 rooms, Rician channels
+      (K-factor 6 dB, CN(0,1) NLoS draws from the seed) synthesised by
+      dmimo_channel from the positions and the NLoS array, then dmimo_beamform
+      ZF at 1 W with the FP16x3 (and FP32) Gram, FP64 inverse, per-user SINR;
+      per-user SINR_k against the oracle chain in dB on sampled deployments.
+    * ``sweep``: Gram + ZF alone for B = 2^10 .. 2^17 with the FP32 and the
+      FP16x3 Gram; H is CN(0,1), drawn on the device with a fixed seed (the
+      cost does not depend on the channel values).
+    Times from HIP events around back-to-back calls."""
+    import numpy as np
+    from oracle import dmimo_oracle as O
     K, M = 16, 256
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    w = WL.batched_workload()
+    B = w.B
+    params = D.channel_params(w.freq_hz, D.CH_RICIAN, w.kappa_lin)
+    ap = torch.from_numpy(w.ap_xyz).cuda()
+    users = torch.from_numpy(w.user_xyz).cuda()
+    nlos = torch.from_numpy(w.nlos).cuda()
+    pts = D.list_points(users, K)
+    H = D.channel(params, ap, pts, nlos=nlos, prec="f32")
+    ric = {}
+    idx = np.arange(0, B, 32)
+    Ho = np.stack([O.rician_channel(w.user_xyz[b], w.ap_xyz[b], w.freq_hz, w.kappa_lin,
+                                    w.nlos[b].astype(np.complex128)) for b in idx])
+    Wo, _ = O.zf_precoder(Ho, None, w.sigma2, w.p_total)
+    so = O.user_sinr(Ho, Wo, w.sigma2)
+    for prec in ("f16x3", "f32"):
+        r = D.beamform(H, "zf", None, w.sigma2, w.p_total, prec)
+        ms_bf = timed(lambda: D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=r), 20)
+        ms_ch = timed(lambda: D.channel(params, ap, pts, nlos=nlos, prec="f32", out=H), 20)
+        sg = r.sinr.cpu().numpy()[idx]
+        ric[prec] = {"channel_ms": round(ms_ch, 4), "gram_zf_ms": round(ms_bf, 4),
+                     "ms": round(ms_ch + ms_bf, 4),
+                     "G_h_per_s": round(2 * B * K * M / ((ms_ch + ms_bf) * 1e-3) / 1e9, 2),
+                     "failed_deployments": int((r.info != 0).sum().item()),
+                     "err_db_user_sinr": plain_db(sg, so)}
+    ric["workload"] = ("1024 rooms 20x20x4 m, 16x16 jittered ceiling APs, 16 users at 1.2 m, "
+                       "5.8 GHz, Rician K-factor 6 dB with CN(0,1) NLoS draws, ZF at 1 W, "
+                       "-90 dBm; dmimo_channel (Rician) then dmimo_beamform")
+    ric["compared"] = f"per-user SINR_k of {len(idx)} sampled deployments vs the oracle chain"
+    del H, nlos
+    torch.cuda.empty_cache()
+
     gen = torch.Generator(device="cuda")
     gen.manual_seed(3)
     bmax = 1 << 17
-    H = torch.complex(torch.randn(bmax, K, M, generator=gen, device="cuda"),
-                      torch.randn(bmax, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
+    Hs = torch.complex(torch.randn(bmax, K, M, generator=gen, device="cuda"),
+                       torch.randn(bmax, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
     sweep = []
     for prec in ("f32", "f16x3"):
         for e in (10, 12, 14, 16, 17):
-            B = 1 << e
-            Hb = H[:B]
+            Bs = 1 << e
+            Hb = Hs[:Bs]
             r = D.beamform(Hb, "zf", None, 1e-12, 1.0, prec)
-            reps = 20 if B <= 1 << 14 else 5
-            for _ in range(2):
-                D.beamform(Hb, "zf", None, 1e-12, 1.0, prec, out=r)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(reps):
-                D.beamform(Hb, "zf", None, 1e-12, 1.0, prec, out=r)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            sweep.append({"B": B, "prec": prec, "ms": round(ms, 4),
-                          "deployments_per_s": round(B / ms * 1e3, 1),
-                          "G_h_per_s": round(B * K * M / ms / 1e6, 2)})
+            ms = timed(lambda: D.beamform(Hb, "zf", None, 1e-12, 1.0, prec, out=r),
+                       20 if Bs <= 1 << 14 else 5)
+            sweep.append({"B": Bs, "prec": prec, "ms": round(ms, 4),
+                          "deployments_per_s": round(Bs / ms * 1e3, 1),
+                          "G_h_per_s": round(Bs * K * M / ms / 1e6, 2),
+                          "hbm_frac_h_read_w_write": round(16 * Bs * K * M / (ms * 1e-3) / HBM_PEAK, 4)})
             del r
-    del H
+    del Hs
     torch.cuda.empty_cache()
-    return {"workload": "batched ZF: B deployments x K=16 users x M=256 antennas, H ~ CN(0,1) "
-                        "(device draws), total power 1 W, noise -90 dBm; Gram + inverse + W + epilogues",
+    return {"rician": ric,
+            "sweep_workload": "Gram + ZF alone: B deployments x K=16 users x M=256 antennas, "
+                              "H ~ CN(0,1) (device draws), total power 1 W, noise -90 dBm",
             "sweep": sweep}
 
 
@@ -649,7 +1151,7 @@ def pgd_phase(args, D, WL, torch):
     return res
 
 
-def pa_phase(w, D, WL, torch, params, ap0, gpts):
+def pa_phase(w, D, WL, torch):
     """The PA-consumption-aware precoder (eq. optim1 by normalised PGD, lambda =
     1/15, 5000 iterations) on the benchmark room: the step's K = 8 users, SINR
     targets 10 dB, noise -90 dBm.  Reports its PCG against ZF with the same
@@ -659,6 +1161,9 @@ def pa_phase(w, D, WL, torch, params, ap0, gpts):
     import numpy as np
 
     K, M, N = w.K, w.M, w.grid.n
+    params = D.channel_params(w.freq_hz)
+    gpts = D.grid_points(w.grid)
+    ap0 = torch.from_numpy(w.ap_xyz[0]).cuda().contiguous()
     gamma = np.full(K, 10.0)
     it = 5000
     lam = torch.full((it,), 1.0 / 15.0, dtype=torch.float64, device="cuda")
@@ -818,76 +1323,6 @@ def pa_hall(D, WL, torch, lam, er, timed):
             "map_2048x2048_ms": round(ms_map, 3),
             "map_terms": N * M}
 
-
-def cpu_baseline(w, bf, maps, budget_s):
-    """Oracle timed on a bounded sample of the step, single-threaded.
-
-    The sample is the user-side calls (channel, MR and ZF precoders with
-    their SINR and L2,1 epilogues) plus power and SINR maps of both precoders
-    on 16 random grid rows, repeated until the budget is spent.
-
-    Also reports the dB error of the GPU chain (GPU H -> GPU W -> GPU map)
-    against the oracle chain (oracle H -> oracle W -> oracle map) on the first
-    sampled rows.  No GPU output enters the oracle.
-    """
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    from oracle import dberror
-    from oracle import dmimo_oracle as O
-
-    g = w.grid
-    nx = g.nx
-    rows_per_rep = 16
-    pts_all = O.grid_points(g.x0, g.y0, g.dx, g.dy, g.z, g.nx, g.ny)
-    aps = w.ap_xyz[0]
-    K, M = w.K, w.M
-    gpu = {p: (maps[p].power.cpu().numpy(), maps[p].sinr.cpu().numpy()) for p in maps}
-    pairs = {"power": [], "sinr": []}
-    terms = 0
-    reps = 0
-    rng = np.random.default_rng(0)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < budget_s:
-            Hu = O.los_channel(w.user_xyz[0], aps, w.freq_hz)
-            Wmr = O.mr_precoder(Hu, w.p_total)
-            Wzf, _ = O.zf_precoder(Hu, None, w.sigma2, w.p_total)
-            for Wp in (Wmr, Wzf):
-                O.user_sinr(Hu, Wp, w.sigma2)
-                O.antenna_power(Wp)
-                O.l21_norm(Wp)
-            terms += 3 * K * M
-            j0 = int(rng.integers(0, g.ny - rows_per_rep + 1))
-            sl = slice(j0 * nx, (j0 + rows_per_rep) * nx)
-            Hg = O.los_channel(pts_all[sl], aps, w.freq_hz)
-            for name, Wp in (("mr", Wmr), ("zf", Wzf)):
-                y = O.power_map(Hg, Wp)
-                s, _ = O.sinr_map(Hg, Wp, w.sigma2)
-                terms += (sl.stop - sl.start) * M
-                if reps < 8:
-                    pairs["power"].append((gpu[name][0][sl], y))
-                    pairs["sinr"].append((gpu[name][1][sl], s))
-            reps += 1
-        elapsed = time.perf_counter() - t0
-    err = {}
-    for k, pr in pairs.items():
-        y = np.concatenate([p[0] for p in pr])
-        r = np.concatenate([p[1] for p in pr])
-        sm = dberror.summary(y, r, 0.01)
-        err[k] = {"max_db": sm["max_db"], "p99_db": sm["p99_db"], "n": sm["n"],
-                  "n_below_floor": sm["n_below_floor"], "n_over_0.01dB": sm["n_fail"]}
-    err["compared"] = "GPU chain vs oracle chain (users -> precoder -> map), both precoders"
-    cpu = {
-        "value": round(terms / elapsed / 1e9, 6),
-        "unit": "G h/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"{reps} reps of the step's user-side calls plus power+SINR maps of MR and ZF "
-                  f"on {rows_per_rep} random grid rows ({rows_per_rep * nx} points each): "
-                  f"{terms} terms in {elapsed:.1f} s",
-    }
-    return cpu, err
 
 
 if __name__ == "__main__":

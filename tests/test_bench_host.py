@@ -62,7 +62,25 @@ def test_source_hash_covers_every_listed_file():
 
 
 def test_algorithmic_slots_per_term():
-    # the synthesis count, plus the VALU contraction of the K <= 2 kernel
-    assert bench.alg_slots_per_term(8) == bench.SYNTH_SLOTS == 32
-    assert bench.alg_slots_per_term(1) == 36
-    assert bench.alg_slots_per_term(2) == 40
+    # the synthesis count, plus the VALU contraction of the K <= 2 FP32 kernel,
+    # plus the hi/lo split of the split-precision maps
+    assert bench.alg_slots_per_term(8) == bench.SYNTH_SLOTS == 23
+    assert bench.alg_slots_per_term(1) == 27
+    assert bench.alg_slots_per_term(2) == 31
+    assert bench.alg_slots_per_term(32, "f16x3") == bench.alg_slots_per_term(8, "bf16x3") == 27
+    assert bench.mfma_flops_per_term(32, "f16x3") == 768
+    assert bench.mfma_flops_per_term(32, "f32") == 256
+
+
+def test_hall_roofline_fields():
+    r = bench.hall_roofline(32, 2048 * 2048, 1024, "f16x3", 5.0, "abc", None)
+    assert r["bound"] == "alu" and r["unit"] == "T VALU lane-slots/s"
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    # 27 slots x 4.29e9 terms in 5 ms
+    assert abs(r["achieved"] - 27 * 2048 * 2048 * 1024 / 5e-3 / 1e12) < 1e-2
+    assert r["floor_ms"] > 0 and r["mfma"]["flops_per_term"] == 768
+
+
+def test_host_info():
+    h = bench.host_info()
+    assert h["nproc"] >= 1
