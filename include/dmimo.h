@@ -415,7 +415,13 @@ dmimo_status dmimo_ufpgd_train(int32_t n_channels, int32_t K, int32_t M, const v
  * -------------------------------------------------------------------------*/
 typedef struct dmimo_server dmimo_server;
 
-enum { DMIMO_Q_QUEUED = 0, DMIMO_Q_RUNNING = 1, DMIMO_Q_DONE = 2, DMIMO_Q_FAILED = 3 };
+/* Query states.  FAILED: a ZF query whose pivot test failed (two users at the
+ * same place, or nearly collinear channels; dmimo_server_query_info gives the
+ * pivot), a launch that failed, or a query that cannot be admitted even with
+ * no other query running.  CANCELLED: dmimo_server_cancel before admission.
+ * TIMED_OUT: waited for admission longer than the server's queue time-out. */
+enum { DMIMO_Q_QUEUED = 0, DMIMO_Q_RUNNING = 1, DMIMO_Q_DONE = 2, DMIMO_Q_FAILED = 3,
+       DMIMO_Q_CANCELLED = 4, DMIMO_Q_TIMED_OUT = 5 };
 
 /* Create a server on `device` with an arena of hbm_budget_bytes (>= 1 MiB)
  * and at most max_inflight (1..4096) admitted queries. */
@@ -425,7 +431,10 @@ dmimo_status dmimo_server_create(int32_t device, size_t hbm_budget_bytes, int32_
  * DMIMO_E_NOMEM if the geometry does not fit the budget. */
 dmimo_status dmimo_server_add_deployment(dmimo_server* srv, const dmimo_channel_params* params,
                                          int32_t M, const double* ap_xyz_host, int32_t* dep_id);
-/* Queue a power-map query; returns at once with a ticket.
+/* Queue a power-map query; returns at once with a ticket.  Queries are
+ * admitted in arrival order; query scratch comes from the bottom of the
+ * arena and resident data (geometry, the DMIMO_PA schedule) from its top, so
+ * resident uploads never fragment the space queries draw from.
  *   user_xyz_host  host FP64 [K][3] (copied); 1 <= K <= 32, K <= M for ZF.
  *   pts            GRID, or LIST of device points that outlive the query.
  *   prec           DMIMO_F32, DMIMO_MIX_F16X3 or DMIMO_MIX_BF16X3.
@@ -452,6 +461,18 @@ dmimo_status dmimo_server_wait(dmimo_server* srv, uint64_t ticket, double timeou
 dmimo_status dmimo_server_set_pa_schedule(dmimo_server* srv, int32_t layers,
                                           const double* lambdas, const double* eta_rel,
                                           double gamma_lin);
+/* Withdraw a query that has not been admitted yet: it ends in
+ * DMIMO_Q_CANCELLED and its outputs are never written.  DMIMO_E_BUSY if it was
+ * admitted already (admitted work runs to completion) or is finished. */
+dmimo_status dmimo_server_cancel(dmimo_server* srv, uint64_t ticket);
+/* Queued queries that wait longer than `seconds` for admission end in
+ * DMIMO_Q_TIMED_OUT (their outputs are never written); 0 (the default) waits
+ * forever.  Applies to queries already queued. */
+dmimo_status dmimo_server_set_queue_timeout(dmimo_server* srv, double seconds);
+/* The precoder's info word of a finished query: 0, or for a ZF query that
+ * ended DMIMO_Q_FAILED the failed pivot j > 0 (as info[b] of dmimo_beamform).
+ * 0 while the query is not finished. */
+dmimo_status dmimo_server_query_info(dmimo_server* srv, uint64_t ticket, int32_t* info);
 /* Forget a finished ticket (DMIMO_E_BUSY if it is not finished). */
 dmimo_status dmimo_server_release(dmimo_server* srv, uint64_t ticket);
 /* Counters: queries completed, channel terms completed, launches issued,

@@ -38,6 +38,7 @@
 
 #include "kernels.h"
 #include "powermap_body.h"
+#include "server_arena.h"
 
 namespace dmimo {
 
@@ -133,57 +134,14 @@ double now_s() {
     return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// First-fit allocator over one device buffer (offsets only).
-class Arena {
-  public:
-    void init(size_t size) {
-        free_.clear();
-        free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = align256(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t roff = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[roff] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align256(bytes);
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<size_t, size_t> free_;
-};
-
 struct Deployment {
     WaveConst w;
     int M;
     size_t off;   // arena offset of FP64 [M][3]
 };
 
-enum QState : int32_t { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+enum QState : int32_t { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3, kCancelled = 4,
+                         kTimedOut = 5 };
 
 struct Query {
     uint64_t ticket = 0;
@@ -206,6 +164,7 @@ struct Query {
     std::atomic<int32_t> state{kQueued};
     double t_submit = 0, t_done = 0;
     int64_t terms = 0;
+    int32_t info = 0;    // ZF: the failed pivot (copied from the device at retirement)
 };
 
 }  // namespace
@@ -222,7 +181,9 @@ struct ServerImpl {
     PmMapDev* d_slots = nullptr;
     PmMapDev* h_slots = nullptr;
     double* h_users = nullptr;
+    int32_t* h_info = nullptr;   // pinned: each slot's precoder info word, copied back
     std::vector<int> free_slots;
+    double queue_timeout = 0.0;   // seconds a query may wait for admission; 0 = no limit
     // work lists (double buffered)
     int item_cap = 0;
     ServeItem* h_items[2] = {nullptr, nullptr};
@@ -251,7 +212,8 @@ struct ServerImpl {
     std::atomic<int64_t> n_done{0}, terms_done{0};
 
     void loop();
-    bool admit_one(Query* q);
+    // 1 = admitted (or failed at once), 0 = not now, -1 = can never be admitted
+    int admit_one(Query* q);
     void retire_ticks(bool block);
     void finish(Query* q, bool ok);
 };
@@ -262,7 +224,7 @@ static bool hip_ok(hipError_t e, ServerImpl* s, const char* what) {
     return false;
 }
 
-bool ServerImpl::admit_one(Query* q) {
+int ServerImpl::admit_one(Query* q) {
     const Deployment& d = deps[q->dep];
     const int K = q->K;
     const size_t M = (size_t)d.M;
@@ -271,11 +233,14 @@ bool ServerImpl::admit_one(Query* q) {
     const size_t w_b = align256((size_t)K * M * 8);
     const size_t g_b = align256(beamform_workspace_bytes(q->precoder, 1, K, M, q->prec));
     const size_t pa_b = q->precoder == DMIMO_PA ? align256(2 * sizeof(double)) : 0;
-    q->bytes = users_b + h_b + w_b + g_b + pa_b;
-    if (in_use + q->footprint > budget) return false;
-    if (free_slots.empty()) return false;
+    const size_t info_b = 256;
+    q->bytes = users_b + h_b + w_b + g_b + pa_b + info_b;
+    if (in_use + q->footprint > budget) return active.empty() ? -1 : 0;
+    if (free_slots.empty()) return 0;
     size_t off;
-    if (!arena.alloc(q->bytes, &off)) return false;
+    // with no query running, the space below the resident data is one block:
+    // a query that does not fit then never will
+    if (!arena.alloc_low(q->bytes, &off)) return active.empty() ? -1 : 0;
     q->off = off;
     q->slot = free_slots.back();
     free_slots.pop_back();
@@ -285,6 +250,8 @@ bool ServerImpl::admit_one(Query* q) {
     void* H = base + users_b;
     void* W = base + users_b + h_b;
     void* G = base + users_b + h_b + w_b;
+    int32_t* d_info = reinterpret_cast<int32_t*>(base + users_b + h_b + w_b + g_b + pa_b);
+    h_info[q->slot] = 0;
     // user positions: pinned staging of this slot -> device
     double* stage = h_users + (size_t)q->slot * DMIMO_K_MAX * 3;
     std::memcpy(stage, q->users, sizeof(double) * 3 * K);
@@ -316,8 +283,11 @@ bool ServerImpl::admit_one(Query* q) {
         ba.prec = q->prec;
         ba.W = W;
         ba.ws = G;
+        ba.info = d_info;   // a failed ZF pivot fails the query (read back at retirement)
         const int pc = q->precoder;
         ok = ok && launch_beamform_users(ba, 1, &pc, d.w, ap, d_users, stream) == DMIMO_OK;
+        ok = ok && hip_ok(hipMemcpyAsync(h_info + q->slot, d_info, sizeof(int32_t),
+                                         hipMemcpyDeviceToHost, stream), this, "info copy");
     }
     // map descriptor of the slot
     PmMapDev& m = h_slots[q->slot];
@@ -383,7 +353,10 @@ void ServerImpl::retire_ticks(bool block) {
         for (auto it = active.begin(); it != active.end();) {
             Query* q = *it;
             if (q->next_item == q->n_items && q->last_tick <= t) {
-                finish(q, true);
+                // the tick ran after the precoder on the same stream, so the
+                // precoder's info word has been copied back
+                q->info = h_info[q->slot];
+                finish(q, q->info == 0);
                 it = active.erase(it);
             } else {
                 ++it;
@@ -400,10 +373,23 @@ void ServerImpl::loop() {
         {
             std::unique_lock<std::mutex> lk(mu);
             bool admitted = false;
+            const double now = now_s();
             while (!pending.empty()) {
                 Query* q = pending.front();
-                if (!admit_one(q)) break;
+                if (queue_timeout > 0.0 && now - q->t_submit > queue_timeout) {
+                    pending.pop_front();
+                    q->t_done = now;
+                    q->state.store(kTimedOut);
+                    admitted = true;
+                    continue;
+                }
+                const int r = admit_one(q);
+                if (r == 0) break;
                 pending.pop_front();
+                if (r < 0) {   // nothing is running and it still does not fit
+                    q->t_done = now;
+                    q->state.store(kFailed);
+                }
                 admitted = true;
             }
             if (admitted) cv.notify_all();
@@ -506,7 +492,8 @@ dmimo_status dmimo_server_create(int32_t device, size_t hbm_budget_bytes, int32_
               hip_ok(hipMalloc(&S.d_slots, sizeof(PmMapDev) * max_inflight), &S, "slots") &&
               hip_ok(hipHostMalloc(&S.h_slots, sizeof(PmMapDev) * max_inflight), &S, "pinned slots") &&
               hip_ok(hipHostMalloc(&S.h_users, sizeof(double) * DMIMO_K_MAX * 3 * max_inflight), &S,
-                     "pinned users");
+                     "pinned users") &&
+              hip_ok(hipHostMalloc(&S.h_info, sizeof(int32_t) * max_inflight), &S, "pinned info");
     for (int i = 0; ok && i < 2; ++i)
         ok = hip_ok(hipHostMalloc(&S.h_items[i], sizeof(ServeItem) * S.item_cap), &S, "pinned items") &&
              hip_ok(hipMalloc(&S.d_items[i], sizeof(ServeItem) * S.item_cap), &S, "items") &&
@@ -542,8 +529,10 @@ dmimo_status dmimo_server_add_deployment(dmimo_server* srv, const dmimo_channel_
     std::lock_guard<std::mutex> lk(S.mu);
     const size_t bytes = (size_t)M * 3 * sizeof(double);
     size_t off;
-    if (S.in_use + align256(bytes) > S.budget || !S.arena.alloc(bytes, &off))
-        return fail(DMIMO_E_NOMEM, "add_deployment: geometry does not fit the budget");
+    // resident data comes from the top of the arena, query scratch from the bottom
+    if (S.in_use + align256(bytes) > S.budget || !S.arena.alloc_high(bytes, &off))
+        return fail(DMIMO_E_NOMEM, "add_deployment: geometry does not fit the budget (or the "
+                                   "space not used by running queries)");
     S.in_use += align256(bytes);
     S.geom_bytes += align256(bytes);
     if (hipMemcpy(S.arena_base + off, ap_xyz_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -649,7 +638,7 @@ dmimo_status dmimo_server_set_pa_schedule(dmimo_server* srv, int32_t layers,
     if (S.pa_layers >= 0) return fail(DMIMO_E_BUSY, "set_pa_schedule: already set");
     const size_t bytes = sizeof(double) * 2 * (size_t)std::max(layers, 1);
     size_t off;
-    if (S.in_use + align256(bytes) > S.budget || !S.arena.alloc(bytes, &off))
+    if (S.in_use + align256(bytes) > S.budget || !S.arena.alloc_high(bytes, &off))
         return fail(DMIMO_E_NOMEM, "set_pa_schedule: schedule does not fit the budget");
     double* dev = reinterpret_cast<double*>(S.arena_base + off);
     if (layers > 0 &&
@@ -694,6 +683,48 @@ dmimo_status dmimo_server_wait(dmimo_server* srv, uint64_t ticket, double timeou
                        std::chrono::microseconds((int64_t)(std::max(0.0, timeout_s) * 1e6));
     S.cv.wait_until(lk, until, [q] { return q->state.load() >= kDone; });
     *state = q->state.load();
+    return DMIMO_OK;
+}
+
+dmimo_status dmimo_server_cancel(dmimo_server* srv, uint64_t ticket) {
+    clear_error();
+    if (!srv) return fail(DMIMO_E_ARG, "cancel: NULL server");
+    ServerImpl& S = srv->impl;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        auto it = S.all.find(ticket);
+        if (it == S.all.end()) return fail(DMIMO_E_NOTFOUND, "cancel: unknown ticket");
+        Query* q = it->second;
+        auto pos = std::find(S.pending.begin(), S.pending.end(), q);
+        if (pos == S.pending.end())
+            return fail(DMIMO_E_BUSY, "cancel: the query was admitted already (or is finished)");
+        S.pending.erase(pos);
+        q->t_done = now_s();
+        q->state.store(kCancelled);
+    }
+    S.cv.notify_all();
+    return DMIMO_OK;
+}
+
+dmimo_status dmimo_server_set_queue_timeout(dmimo_server* srv, double seconds) {
+    clear_error();
+    if (!srv) return fail(DMIMO_E_ARG, "set_queue_timeout: NULL server");
+    if (!(seconds >= 0.0) || !std::isfinite(seconds))
+        return fail(DMIMO_E_ARG, "set_queue_timeout: seconds must be >= 0");
+    ServerImpl& S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.queue_timeout = seconds;
+    return DMIMO_OK;
+}
+
+dmimo_status dmimo_server_query_info(dmimo_server* srv, uint64_t ticket, int32_t* info) {
+    clear_error();
+    if (!srv || !info) return fail(DMIMO_E_ARG, "query_info: NULL argument");
+    ServerImpl& S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(ticket);
+    if (it == S.all.end()) return fail(DMIMO_E_NOTFOUND, "query_info: unknown ticket");
+    *info = it->second->state.load() >= kDone ? it->second->info : 0;
     return DMIMO_OK;
 }
 
@@ -743,6 +774,7 @@ dmimo_status dmimo_server_destroy(dmimo_server* srv) {
         if (S.h_items[i]) hipHostFree(S.h_items[i]);
     }
     if (S.h_users) hipHostFree(S.h_users);
+    if (S.h_info) hipHostFree(S.h_info);
     if (S.h_slots) hipHostFree(S.h_slots);
     if (S.d_slots) hipFree(S.d_slots);
     if (S.arena_base) hipFree(S.arena_base);

@@ -88,6 +88,9 @@ _SIGS = {
                           ctypes.POINTER(_f64)],
     "dmimo_server_wait": [_vp, ctypes.c_uint64, _f64, ctypes.POINTER(_i32)],
     "dmimo_server_release": [_vp, ctypes.c_uint64],
+    "dmimo_server_cancel": [_vp, ctypes.c_uint64],
+    "dmimo_server_set_queue_timeout": [_vp, _f64],
+    "dmimo_server_query_info": [_vp, ctypes.c_uint64, ctypes.POINTER(_i32)],
     "dmimo_server_set_pa_schedule": [_vp, _i32, _vp, _vp, _f64],
     "dmimo_server_stats": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i32),
@@ -640,7 +643,7 @@ def ufpgd_train(H, state: UfpgdState, idx, gamma_lin=None, sigma2=1.0, lam_c=LAM
 # serving
 # ---------------------------------------------------------------------------
 
-Q_QUEUED, Q_RUNNING, Q_DONE, Q_FAILED = 0, 1, 2, 3
+Q_QUEUED, Q_RUNNING, Q_DONE, Q_FAILED, Q_CANCELLED, Q_TIMED_OUT = 0, 1, 2, 3, 4, 5
 
 
 class Server:
@@ -704,6 +707,21 @@ class Server:
     def release(self, ticket: int):
         _check(lib().dmimo_server_release(self._h, ctypes.c_uint64(ticket)), "dmimo_server_release")
         self._keep.pop(ticket, None)
+
+    def cancel(self, ticket: int):
+        """Withdraw a query not admitted yet (DmimoError with DMIMO_E_BUSY otherwise)."""
+        _check(lib().dmimo_server_cancel(self._h, ctypes.c_uint64(ticket)), "dmimo_server_cancel")
+
+    def set_queue_timeout(self, seconds: float):
+        _check(lib().dmimo_server_set_queue_timeout(self._h, float(seconds)),
+               "dmimo_server_set_queue_timeout")
+
+    def query_info(self, ticket: int) -> int:
+        """The precoder's info word of a finished query (ZF: the failed pivot, or 0)."""
+        v = _i32()
+        _check(lib().dmimo_server_query_info(self._h, ctypes.c_uint64(ticket), ctypes.byref(v)),
+               "dmimo_server_query_info")
+        return v.value
 
     def stats(self) -> dict:
         c, tm, tk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -226,3 +226,140 @@ def test_pa_queries_equal_one_shot_and_mix(D):
                 np.testing.assert_array_equal(power.cpu().numpy(), alone[i // 2][0])
                 np.testing.assert_array_equal(sinr.cpu().numpy(), alone[i // 2][1])
             srv.release(t)
+
+
+# ---------------------------------------------------------------------------
+# failure paths: singular ZF, full queue, cancel, queue time-out, resident
+# uploads between running queries
+# ---------------------------------------------------------------------------
+
+def _big_query(D, srv, dep, rng, side=1024, K=16, prec="f32"):
+    users = WL.uniform_positions(rng, K, 20.0, 20.0, 1.2)
+    g = WL.Grid(0.0, 0.0, 20.0 / side, 20.0 / side, 1.2, side, side)
+    power = torch.full((g.n,), -1.0, device="cuda")
+    t = srv.submit(dep, users, "zf", D.grid_points(g), 1e-12, 1.0, prec, power)
+    return t, power
+
+
+def _drain(srv, tickets, timeout=60.0):
+    states = []
+    for t in tickets:
+        states.append(srv.wait(t, timeout))
+    return states
+
+
+def test_zf_query_with_duplicate_users_fails(D):
+    # two users at one place make G singular: the query ends FAILED with the
+    # pivot as its info word, and a regular query beside it is unaffected
+    say("serving: ZF with duplicated users -> FAILED, neighbour DONE")
+    rng = np.random.default_rng(21)
+    aps = _room(rng, 64, 3.5e9)
+    with D.Server(256 << 20, 8) as srv:
+        dep = srv.add_deployment(D.channel_params(3.5e9), aps)
+        g = WL.Grid(0.0, 0.0, 20 / 64, 20 / 64, 1.2, 64, 64)
+        users = WL.uniform_positions(rng, 4, 20, 20, 1.2)
+        bad = users.copy()
+        bad[2] = bad[0]
+        outs = []
+        for u in (bad, users):
+            p = torch.full((g.n,), -1.0, device="cuda")
+            outs.append((srv.submit(dep, u, "zf", D.grid_points(g), 1e-12, 1.0, "f32", p), p))
+        st = _drain(srv, [t for t, _ in outs])
+        assert st == [D.Q_FAILED, D.Q_DONE]
+        assert srv.query_info(outs[0][0]) == 3 and srv.query_info(outs[1][0]) == 0
+        torch.cuda.synchronize()
+        assert torch.all(outs[1][1] > 0)
+        # the one-shot call reports the same pivot
+        Hu = O.los_channel(bad, aps, 3.5e9).astype(np.complex64)
+        r = D.beamform(torch.from_numpy(Hu[None]).cuda(), "zf", None, 1e-12, 1.0, "f32")
+        assert int(r.info[0]) == 3
+
+
+def test_full_pending_queue_is_busy(D):
+    # one admitted query at a time and a pending queue of 64: a burst of large
+    # queries gets DMIMO_E_BUSY once 64 wait; every accepted query completes
+    say("serving: pending queue full -> DMIMO_E_BUSY")
+    rng = np.random.default_rng(22)
+    with D.Server(1 << 30, 1) as srv:
+        dep = srv.add_deployment(D.channel_params(5.8e9), _room(rng, 512, 5.8e9))
+        tickets, busy = [], 0
+        for _ in range(80):
+            try:
+                tickets.append(_big_query(D, srv, dep, rng)[0])
+            except D.DmimoError as e:
+                assert e.status == 7
+                busy += 1
+        say(f"    accepted {len(tickets)}, busy {busy}")
+        assert busy > 0
+        assert all(s == D.Q_DONE for s in _drain(srv, tickets, 120.0))
+
+
+def test_cancel_a_queued_query(D):
+    say("serving: cancel before admission")
+    rng = np.random.default_rng(23)
+    with D.Server(1 << 30, 1) as srv:
+        dep = srv.add_deployment(D.channel_params(5.8e9), _room(rng, 512, 5.8e9))
+        t0, p0 = _big_query(D, srv, dep, rng, side=2048)
+        t1, p1 = _big_query(D, srv, dep, rng)
+        t2, p2 = _big_query(D, srv, dep, rng)
+        srv.cancel(t1)
+        st = _drain(srv, [t0, t1, t2], 120.0)
+        assert st == [D.Q_DONE, D.Q_CANCELLED, D.Q_DONE]
+        torch.cuda.synchronize()
+        assert torch.all(p1 == -1.0)                  # never written
+        assert torch.all(p0 > 0) and torch.all(p2 > 0)
+        with pytest.raises(D.DmimoError) as e:        # admitted and finished: not cancellable
+            srv.cancel(t0)
+        assert e.value.status == 7
+
+
+def test_queue_timeout(D):
+    # a 1 ms admission time-out with one query admitted at a time: the
+    # queries behind a long one time out, their outputs untouched
+    say("serving: queue time-out")
+    rng = np.random.default_rng(24)
+    with D.Server(1 << 30, 1) as srv:
+        dep = srv.add_deployment(D.channel_params(5.8e9), _room(rng, 512, 5.8e9))
+        srv.set_queue_timeout(1e-3)
+        qs = [_big_query(D, srv, dep, rng, side=2048)] + [_big_query(D, srv, dep, rng)
+                                                           for _ in range(5)]
+        st = _drain(srv, [t for t, _ in qs], 120.0)
+        say(f"    states {st}")
+        assert st[0] == D.Q_DONE
+        assert D.Q_TIMED_OUT in st[1:]
+        torch.cuda.synchronize()
+        for s, (_, p) in zip(st, qs):
+            if s == D.Q_TIMED_OUT:
+                assert torch.all(p == -1.0)
+            else:
+                assert s == D.Q_DONE and torch.all(p > 0)
+
+
+def test_geometry_uploaded_between_running_queries(D):
+    # Resident uploads come from the top of the arena.  Two large ZF queries
+    # (K = 32, M = 4096: a few MiB of scratch each) run while deployments are
+    # added; the arena is sized so that, had the geometry been placed between
+    # their blocks, no free block would hold the third, larger query once they
+    # finish.  It must be admitted and complete.
+    say("serving: add_deployment between running queries, then a larger query")
+    rng = np.random.default_rng(25)
+    M = 4096
+    sA = D.workspace_size(D.CALL_BEAMFORM_ZF, 1, 24, M, 0, "f32") + 2 * 24 * M * 8
+    sC = D.workspace_size(D.CALL_BEAMFORM_ZF, 1, 32, M, 0, "f32") + 2 * 32 * M * 8
+    geo = (M * 24 + 255) // 256 * 256
+    side = 256
+    maps = side * side * 4
+    budget = 2 * (sA + 2048) + 3 * geo + sA // 2 + 2 * maps + (1 << 20)
+    assert sC > sA and sC + maps + 3 * geo < budget
+    aps = [_room(rng, M, 5.8e9) for _ in range(3)]
+    with D.Server(budget, 4) as srv:
+        dep = srv.add_deployment(D.channel_params(5.8e9), aps[0])
+        ta, pa = _big_query(D, srv, dep, rng, side=side, K=24)
+        srv.add_deployment(D.channel_params(5.8e9), aps[1])
+        tb, pb = _big_query(D, srv, dep, rng, side=side, K=24)
+        srv.add_deployment(D.channel_params(5.8e9), aps[2])
+        tc, pc = _big_query(D, srv, dep, rng, side=side, K=32)
+        st = _drain(srv, [ta, tb, tc], 60.0)
+        assert st == [D.Q_DONE] * 3, st
+        torch.cuda.synchronize()
+        assert torch.all(pc > 0)
