@@ -167,6 +167,34 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
                             double* l21, double* sinr, double* rsum, int32_t* info,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* The batched workload of many small deployments (independent rooms), fused
+ * into one launch: for each deployment b, the users' channels
+ * H[b] = dmimo_channel(params, ap_xyz[b], users user_xyz[b], nlos[b]) (LoS, or
+ * Rician with CN(0,1) draws; the same H bits as dmimo_channel), the precoder
+ * of dmimo_beamform (MR or ZF, with its scaling rules) and the epilogues,
+ * with the channel kept on chip.  K x K Gram on the matrix cores (DMIMO_F32:
+ * FP32 products; MIX modes: FP16 / BF16 hi/lo split products, FP32
+ * accumulation), inverse in FP64 (Gauss-Jordan, the pivot test of
+ * dmimo_beamform), G^-1 H by FP32 matrix-core products.  SINR_k uses the gains
+ * A = H W^T, which for ZF equal G G^-1 D_c and for MR c G (Sec. II-A; exact
+ * identities of W = conj(G^-1 H) D_c and G = H H^H), formed in FP64.
+ *   precoder   DMIMO_MR or DMIMO_ZF.
+ *   params     LoS or Rician; nlos: device complex64 [B][K][M] for Rician,
+ *              NULL for LoS.
+ *   B, K, M    1 <= K <= 16, K <= M for ZF, M <= 256 (larger deployments:
+ *              dmimo_channel then dmimo_beamform; DMIMO_E_UNSUPPORTED here).
+ *   ap_xyz     device FP64 [B][M][3]; user_xyz device FP64 [B][K][3].
+ *   prec       DMIMO_F32, DMIMO_MIX_F16X3 or DMIMO_MIX_BF16X3.
+ *   H, W       device complex64 [B][K][M] outputs, each may be NULL (not written).
+ *   p_ant, l21, sinr, rsum, info  as for dmimo_beamform, each may be NULL.
+ * No workspace.  gamma_lin, sigma2, p_total as for dmimo_beamform. */
+dmimo_status dmimo_beamform_batched(int32_t precoder, const dmimo_channel_params* params,
+                                    int32_t B, int32_t K, int32_t M, const double* ap_xyz,
+                                    const double* user_xyz, const void* nlos,
+                                    const double* gamma_lin, double sigma2, double p_total,
+                                    int32_t prec, void* H, void* W, double* p_ant, double* l21,
+                                    double* sinr, double* rsum, int32_t* info, void* stream);
+
 /* dmimo_beamform for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same kernels and results, bit for bit, with the scratch taken from a

@@ -279,6 +279,34 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M, c
                            as_stream(stream));
 }
 
+dmimo_status dmimo_beamform_batched(int32_t precoder, const dmimo_channel_params* params,
+                                    int32_t B, int32_t K, int32_t M, const double* ap_xyz,
+                                    const double* user_xyz, const void* nlos,
+                                    const double* gamma_lin, double sigma2, double p_total,
+                                    int32_t prec, void* H, void* W, double* p_ant, double* l21,
+                                    double* sinr, double* rsum, int32_t* info, void* stream) {
+    clear_error();
+    WaveConst w;
+    dmimo_status st = make_wave_const(params, &w);
+    if (st) return st;
+    if (precoder != DMIMO_MR && precoder != DMIMO_ZF)
+        return fail(DMIMO_E_UNSUPPORTED, "beamform_batched: MR or ZF");
+    if ((params->model == DMIMO_CH_RICIAN) != (nlos != nullptr))
+        return fail(DMIMO_E_ARG, "beamform_batched: nlos is required for Rician and only for it");
+    double gam[DMIMO_K_MAX];
+    st = check_beamform(precoder, B, K, M, sigma2, p_total, prec, sinr ? sinr : rsum, gamma_lin, gam);
+    if (st) return st;
+    if (prec == DMIMO_F64) return fail(DMIMO_E_UNSUPPORTED, "beamform_batched: FP32 or MIX precision");
+    if (K > 16 || M > 256)
+        return fail(DMIMO_E_UNSUPPORTED, "beamform_batched: K <= 16 and M <= 256 "
+                                         "(dmimo_channel + dmimo_beamform serve larger deployments)");
+    if (B == 0) return DMIMO_OK;
+    if (!ap_xyz || !user_xyz) return fail(DMIMO_E_ARG, "beamform_batched: NULL positions");
+    return launch_beamform_batched(beamform_args(precoder, B, K, M, nullptr, gam, sigma2, p_total,
+                                                 prec, W, p_ant, l21, sinr, rsum, info, nullptr),
+                                   w, ap_xyz, user_xyz, nlos, H, as_stream(stream));
+}
+
 // ---------------------------------------------------------------------------
 // dmimo_beamform_noalloc: the scratch of dmimo_beamform in a static device array
 // ---------------------------------------------------------------------------

@@ -49,6 +49,13 @@ size_t beamform_multi_workspace_bytes(int P, const int* precoders, int64_t B, in
 dmimo_status launch_beamform_users(const BeamformArgs& a, int P, const int* precoders,
                                    const WaveConst& w, const double* ap_xyz, const double* user_xyz,
                                    hipStream_t s);
+// The users' channels (LoS, or Rician with nlos [B][K][M]), MR or ZF and the
+// epilogues of many small deployments in one launch (K <= 16, M <= 256;
+// FP32 or MIX precision): H ([B][K][M], optional) and a.W optional, no
+// workspace.
+dmimo_status launch_beamform_batched(const BeamformArgs& a, const WaveConst& w,
+                                     const double* ap_xyz, const double* user_xyz,
+                                     const void* nlos, void* H, hipStream_t s);
 
 // `maps` precoders over the same antennas and points, one launch: W
 // [maps][K][M], every output [maps][N] ([maps][N][K] per stream); map p is

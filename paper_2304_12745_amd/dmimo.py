@@ -57,6 +57,8 @@ _SIGS = {
     "dmimo_gram": [_i32, _i32, _i32, _vp, _i32, _vp, _vp],
     "dmimo_beamform": [_i32, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _vp, _vp,
                        _vp, _vp, _vp, _sz, _vp],
+    "dmimo_beamform_batched": [_i32, ctypes.POINTER(ChannelParams), _i32, _i32, _i32, _vp, _vp, _vp,
+                               _vp, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dmimo_beamform_noalloc": [_i32, _i32, _i32, _i32, _vp, _vp, _f64, _f64, _i32, _vp, _vp, _vp,
                                _vp, _vp, _vp, _vp],
     "dmimo_powermap": [ctypes.POINTER(ChannelParams), _i32, _vp, _i32, _vp,
@@ -273,6 +275,45 @@ def beamform(H, precoder="zf", gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f3
                                 _ptr(out.rsum), _ptr(out.info), _ptr(ws),
                                 ws.numel() if ws is not None else 0, _stream(stream)),
            "dmimo_beamform")
+    return out
+
+
+def beamform_batched(params: ChannelParams, ap_xyz, user_xyz, nlos=None, precoder="zf",
+                     gamma_lin=None, sigma2=1.0, p_total=0.0, prec="f32", want_H=False,
+                     want_W=True, out: Optional[BeamformResult] = None,
+                     stream=None) -> BeamformResult:
+    """dmimo_beamform_batched: the users' channels (LoS, or Rician with
+    ``nlos`` complex64 [B][K][M]) and their MR / ZF precoder with epilogues,
+    for many small deployments in one launch (K <= 16, M <= 256).
+    ap_xyz float64 [B][M][3], user_xyz float64 [B][K][3].  H (``out.H``) and
+    W are written when asked for."""
+    import torch
+    prec = _prec(prec)
+    pc = PRECODERS[precoder] if isinstance(precoder, str) else int(precoder)
+    B, M = ap_xyz.shape[0], ap_xyz.shape[1]
+    K = user_xyz.shape[1]
+    if tuple(user_xyz.shape) != (B, K, 3) or tuple(ap_xyz.shape) != (B, M, 3):
+        raise ValueError("beamform_batched: ap_xyz [B][M][3] and user_xyz [B][K][3]")
+    if not (ap_xyz.is_contiguous() and user_xyz.is_contiguous()):
+        raise ValueError("beamform_batched: contiguous coordinates required")
+    dev = ap_xyz.device
+    if out is None:
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = BeamformResult(
+            torch.empty((B, K, M), dtype=torch.complex64, device=dev) if want_W else None,
+            torch.empty((B, M), **f64), torch.empty((B,), **f64), torch.empty((B, K), **f64),
+            torch.empty((B,), **f64), torch.empty((B,), dtype=torch.int32, device=dev))
+        out.H = torch.empty((B, K, M), dtype=torch.complex64, device=dev) if want_H else None
+    g = None
+    if gamma_lin is not None:
+        g = (ctypes.c_double * K)(*[float(x) for x in gamma_lin])
+    _check(lib().dmimo_beamform_batched(pc, ctypes.byref(params), B, K, M, _ptr(ap_xyz),
+                                        _ptr(user_xyz), _ptr(nlos), g, float(sigma2),
+                                        float(p_total), prec, _ptr(getattr(out, "H", None)),
+                                        _ptr(out.W), _ptr(out.p_ant), _ptr(out.l21),
+                                        _ptr(out.sinr), _ptr(out.rsum), _ptr(out.info),
+                                        _stream(stream)),
+           "dmimo_beamform_batched")
     return out
 
 

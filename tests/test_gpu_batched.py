@@ -1,0 +1,189 @@
+"""GPU parity of dmimo_beamform_batched against the FP64 oracle.
+
+The fused call synthesises the users' channels (LoS or Rician), forms the
+Gram on the matrix cores, inverts it in FP64 and writes W, p_m, ||W||_{2,1},
+SINR_k and the sum rate, for many small deployments in one launch.
+
+* H equals dmimo_channel's output bit for bit (the same term arithmetic).
+* W against the oracle chain (oracle channel -> oracle precoder): relative
+  Frobenius error per deployment <= 1e-4 (FP32 Gram: FP32 sums of <= 256
+  products times cond(G) <= 100), 1e-3 for the split FP16/BF16 Gram.
+* SINR_k in dB: 0.01 dB (FP32), 0.1 dB (MIX); p_m, ||W||_{2,1}, R_sum: 1e-4
+  relative (1e-3 MIX).
+* A singular deployment (two users at one place) fails with the pivot of
+  dmimo_beamform and zero outputs, and the others are unaffected.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dmimo_oracle as O  # noqa: E402
+from paper_2304_12745_amd import workloads as WL  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+W_TOL = {"f32": 1e-4, "f16x3": 1e-3, "bf16x3": 1e-3}
+DB_TOL = {"f32": 0.01, "f16x3": 0.1, "bf16x3": 0.1}
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2304_12745_amd import dmimo
+    dmimo.lib()
+    return dmimo
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rooms(rng, B, K, M, side=20.0):
+    aps = np.stack([WL.uniform_positions(rng, M, side, side, 4.0) for _ in range(B)])
+    users = np.stack([WL.uniform_positions(rng, K, side, side, 1.2) for _ in range(B)])
+    return aps, users
+
+
+def _oracle(aps, users, nlos, f, kappa, precoder, sigma2, p_total, gamma):
+    B = aps.shape[0]
+    if nlos is None:
+        H = np.stack([O.los_channel(users[b], aps[b], f) for b in range(B)])
+    else:
+        H = np.stack([O.rician_channel(users[b], aps[b], f, kappa, nlos[b].astype(np.complex128))
+                      for b in range(B)])
+    if precoder == "zf":
+        W, sing = O.zf_precoder(H, gamma, sigma2, p_total)
+    else:
+        W, sing = O.mr_precoder(H, p_total), np.zeros(B, bool)
+    return H, W, sing
+
+
+def _check(D, prec, r, H_or, W_or, sigma2, ok):
+    W = r.W.cpu().numpy().astype(np.complex128)
+    for b in np.nonzero(ok)[0]:
+        e = np.linalg.norm(W[b] - W_or[b]) / np.linalg.norm(W_or[b])
+        assert e <= W_TOL[prec], (b, e)
+    s_or = O.user_sinr(H_or, W_or, sigma2)
+    s = r.sinr.cpu().numpy()
+    ddb = np.abs(10 * np.log10(s[ok] / s_or[ok]))
+    say(f"    SINR max {ddb.max():.2e} dB, W ok")
+    assert ddb.max() <= DB_TOL[prec]
+    rel = 1e-4 if prec == "f32" else 1e-3
+    np.testing.assert_allclose(r.p_ant.cpu().numpy()[ok], O.antenna_power(W_or)[ok], rtol=rel,
+                               atol=rel * O.antenna_power(W_or)[ok].max())
+    np.testing.assert_allclose(r.l21.cpu().numpy()[ok], O.l21_norm(W_or)[ok], rtol=rel)
+    np.testing.assert_allclose(r.rsum.cpu().numpy()[ok], O.sum_rate(s_or)[ok], rtol=rel)
+
+
+CASES = [  # B, K, M, model, precoder, prec, p_total
+    (16, 16, 256, "rician", "zf", "f32", 1.0),
+    (16, 16, 256, "rician", "zf", "f16x3", 1.0),
+    (16, 16, 256, "rician", "zf", "bf16x3", 1.0),
+    (9, 16, 256, "los", "zf", "f16x3", 1.0),
+    (7, 5, 37, "rician", "zf", "f32", 1.0),
+    (7, 5, 37, "los", "mr", "bf16x3", 1.0),
+    (5, 9, 100, "rician", "zf", "f16x3", 0.0),
+    (4, 1, 1, "los", "zf", "f32", 1.0),
+    (4, 16, 16, "rician", "zf", "f32", 1.0),
+    (6, 12, 200, "los", "mr", "f32", 0.0),
+    (3, 8, 64, "rician", "mr", "f16x3", 1.0),
+]
+
+
+@pytest.mark.parametrize("B,K,M,model,precoder,prec,p_total", CASES)
+def test_batched_against_oracle(D, B, K, M, model, precoder, prec, p_total):
+    say(f"beamform_batched B={B} K={K} M={M} {model} {precoder} {prec} p_total={p_total}")
+    rng = np.random.default_rng(B * 1000 + K * 10 + M)
+    f, kappa, sigma2 = 5.8e9, 10 ** 0.6, 1e-12
+    aps, users = _rooms(rng, B, K, M)
+    nlos = WL.complex_normal(rng, (B, K, M), np.complex64) if model == "rician" else None
+    gamma = 10 ** (rng.uniform(0, 2, K)) if p_total <= 0 else None
+    params = D.channel_params(f, D.CH_RICIAN if nlos is not None else D.CH_LOS,
+                              kappa if nlos is not None else 0.0)
+    apd, ud = torch.from_numpy(aps).cuda(), torch.from_numpy(users).cuda()
+    nd = torch.from_numpy(nlos).cuda() if nlos is not None else None
+    r = D.beamform_batched(params, apd, ud, nd, precoder, gamma, sigma2, p_total, prec, want_H=True)
+    # H: the channel kernel's bits
+    Hc = D.channel(params, apd, D.list_points(ud, K), nlos=nd, prec="f32")
+    torch.cuda.synchronize()
+    assert torch.equal(r.H, Hc)
+    assert int(r.info.abs().sum()) == 0
+    H_or, W_or, sing = _oracle(aps, users, nlos, f, kappa, precoder, sigma2, p_total, gamma)
+    assert not sing.any()
+    _check(D, prec, r, H_or, W_or, sigma2, np.ones(B, bool))
+    # the same call without H and W writes the same epilogues
+    r2 = D.beamform_batched(params, apd, ud, nd, precoder, gamma, sigma2, p_total, prec,
+                            want_W=False)
+    torch.cuda.synchronize()
+    for n in ("p_ant", "l21", "sinr", "rsum", "info"):
+        assert torch.equal(getattr(r, n), getattr(r2, n)), n
+
+
+def test_batched_singular_deployment_is_isolated(D):
+    say("beamform_batched: duplicated users in deployment 2 -> pivot, zeros; others ok")
+    rng = np.random.default_rng(77)
+    B, K, M, f = 5, 8, 128, 5.8e9
+    aps, users = _rooms(rng, B, K, M)
+    users[2, 5] = users[2, 1]
+    params = D.channel_params(f)
+    apd, ud = torch.from_numpy(aps).cuda(), torch.from_numpy(users).cuda()
+    for prec in ("f32", "f16x3", "bf16x3"):
+        r = D.beamform_batched(params, apd, ud, None, "zf", None, 1e-12, 1.0, prec, want_H=True)
+        ref = D.beamform(r.H, "zf", None, 1e-12, 1.0, prec)
+        torch.cuda.synchronize()
+        info = r.info.cpu().numpy()
+        assert info[2] > 0 and info[[0, 1, 3, 4]].tolist() == [0, 0, 0, 0]
+        assert info[2] == int(ref.info[2])
+        assert not torch.any(r.W[2]) and float(r.rsum[2]) == 0.0 and float(r.l21[2]) == 0.0
+        H_or, W_or, sing = _oracle(aps, users, None, f, 0, "zf", 1e-12, 1.0, None)
+        assert sing[2] and not sing[[0, 1, 3, 4]].any()
+        _check(D, prec, r, H_or, W_or, 1e-12, ~sing)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
+def test_batched_workload_sampled(D, prec):
+    # the batched configuration: 1024 Rician rooms (K = 16, M = 256, 5.8 GHz,
+    # K-factor 6 dB), ZF at 1 W; 64 sampled deployments against the oracle,
+    # all of them against the two-call path (dmimo_channel + dmimo_beamform)
+    say(f"beamform_batched: 1024 Rician rooms, {prec}")
+    w = WL.batched_workload()
+    params = D.channel_params(w.freq_hz, D.CH_RICIAN, w.kappa_lin)
+    apd, ud = torch.from_numpy(w.ap_xyz).cuda(), torch.from_numpy(w.user_xyz).cuda()
+    nd = torch.from_numpy(w.nlos).cuda()
+    r = D.beamform_batched(params, apd, ud, nd, "zf", None, w.sigma2, w.p_total, prec, want_H=True)
+    two = D.beamform(r.H, "zf", None, w.sigma2, w.p_total, prec)
+    torch.cuda.synchronize()
+    assert int(r.info.abs().sum()) == 0 and int(two.info.abs().sum()) == 0
+    d = np.abs(10 * np.log10(r.sinr.cpu().numpy() / two.sinr.cpu().numpy()))
+    say(f"    vs two-call path: SINR max {d.max():.2e} dB")
+    assert d.max() < DB_TOL[prec]
+    idx = np.arange(0, w.B, 16)
+    Ho = np.stack([O.rician_channel(w.user_xyz[b], w.ap_xyz[b], w.freq_hz, w.kappa_lin,
+                                    w.nlos[b].astype(np.complex128)) for b in idx])
+    Wo, sing = O.zf_precoder(Ho, None, w.sigma2, w.p_total)
+    assert not sing.any()
+
+    class Sub:
+        pass
+    sub = Sub()
+    for n in ("W", "p_ant", "l21", "sinr", "rsum"):
+        setattr(sub, n, getattr(r, n)[idx])
+    _check(D, prec, sub, Ho, Wo, w.sigma2, np.ones(len(idx), bool))
+
+
+def test_batched_validation(D):
+    params = D.channel_params(5.8e9)
+    z = torch.zeros((2, 17, 3), dtype=torch.float64, device="cuda")
+    a = torch.zeros((2, 300, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(D.DmimoError) as e:
+        D.beamform_batched(params, a, z, None, "zf")
+    assert e.value.status in (2, 6)
+    ric = D.channel_params(5.8e9, D.CH_RICIAN, 4.0)
+    with pytest.raises(D.DmimoError) as e:
+        D.beamform_batched(ric, a[:, :64].contiguous(), z[:, :8].contiguous(), None, "zf")
+    assert e.value.status == 1
