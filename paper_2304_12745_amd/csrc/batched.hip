@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 #include "split16.h"
@@ -67,16 +68,17 @@ struct BbShared {
     float2 h[kBbK][kBbP];                    // the channel, FP32
     union {
         float part[4][2][kBbK][kBbK + 1];    // per-wave Gram partials (Gr, Gi)
-        double2 A[kBbK][kBbK + 1];           // the gains, at the end
+        double2 prow[kBbK][kBbK];            // Gauss-Jordan: row r as it enters step r
     } u;
-    double2 g0[kBbK][kBbK + 1];              // G (FP64)
-    double2 gi[kBbK][kBbK + 1];              // G^-1
+    double2 g0[kBbK][kBbK + 1];              // G (FP64), zero outside K x K
+    double2 gi[kBbK][kBbK + 1];              // G^-1, zero outside K x K
     double user[kBbK][3];
-    double d0[kBbK];
-    double c[kBbK];                          // scale of W's row k
+    double c[kBbK];                          // scale of W's row k, zero for k >= K
     double cpaper[kBbK];                     // the row scales of ZF at p_total <= 0
+    double rate[kBbK];                       // log2(1 + SINR_k)
     double red[4];
     float hmax[4];
+    int aexp;                                // MIX: power-of-two scale of G^-1
     int fail;
 };
 
@@ -84,42 +86,76 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Gauss-Jordan elimination without pivoting of the K x K matrix g in LDS, in
-// place, by one wave with no barrier: lane l holds row l / 4 and columns
-// 4 (l % 4) .. 4 (l % 4) + 3.  In every step each lane reads the pivot, its
-// row's pivot-column entry and the pivot row's entries of its columns before
-// any lane writes (a wave's LDS accesses run in program order).  The pivot of
-// step p is the diagonal entry of the Schur complement (L_pp^2 of the
-// Cholesky factor); one not above tol * d0[p] stops the elimination.
-// Returns 0 or the failed step p + 1 (the same in every lane).
-__device__ int bb_invert_wave(double2 (*g)[kBbK + 1], const double* d0, int K, double tol,
-                              int lane) {
-    const int r = lane >> 2, c0 = 4 * (lane & 3);
-    for (int p = 0; p < K; ++p) {
-        const double piv = g[p][p].x;
-        if (!(piv > tol * d0[p])) return p + 1;
-        const double inv = 1.0 / piv;
-        const double2 gip = g[r][p];
-        double2 prow[4], mine[4];
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// every lane of a quad takes the value of quad lane Q (DPP quad_perm)
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), Q * 0x55, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), Q * 0x55, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double quad_bcast(double x, int q) {
+    switch (q) {
+        case 0: return quad_bcast<0>(x);
+        case 1: return quad_bcast<1>(x);
+        case 2: return quad_bcast<2>(x);
+        default: return quad_bcast<3>(x);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Gauss-Jordan elimination without pivoting of a 16 x 16 Hermitian positive
+// definite matrix held by one wave in registers: lane l holds row l / 4,
+// columns 4 (l % 4) .. + 3 in v.  Step p reads the pivot from its lane
+// (readlane), gives every lane the pivot-column entry of its row by a
+// broadcast within the quad that holds the row (DPP), and the pivot row's
+// entries of its columns through LDS (prow), where the lanes of row p + 1
+// leave that row after step p.  The pivot of step p is the diagonal entry of
+// the Schur complement (L_pp^2 of the Cholesky factor); one not above
+// tol * dg[p] (dg[p] in lane p) stops the elimination.  Returns 0 or the
+// failed step p + 1, the same in every lane.
+__device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[kBbK], double dg,
+                                               double tol, int lane) {
+    const int r = lane >> 2, q = lane & 3;
+    if (r == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) prow[0][4 * q + e] = v[e];
+    }
+#pragma unroll
+    for (int p = 0; p < kBbK; ++p) {
+        const double piv = readlane_d(v[p & 3].x, 4 * p + (p >> 2));
+        const double dp = readlane_d(dg, p);
+        if (!(piv > tol * dp)) return p + 1;
+        // 1 / piv: hardware reciprocal and two Newton steps (within an ulp)
+        double inv = __builtin_amdgcn_rcp(piv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        double2 pr[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pr[e] = prow[p][4 * q + e];
+        const double2 gip = make_double2(quad_bcast(v[p & 3].x, p >> 2), quad_bcast(v[p & 3].y, p >> 2));
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            prow[e] = g[p][c0 + e];
-            mine[e] = g[r][c0 + e];
+            const bool jp = 4 * q + e == p;
+            const double2 rv = jp ? make_double2(inv, 0.0) : make_double2(pr[e].x * inv, pr[e].y * inv);
+            const double2 x = jp ? make_double2(0.0, 0.0) : v[e];
+            const double2 nv = make_double2(fma(-gip.x, rv.x, fma(gip.y, rv.y, x.x)),
+                                            fma(-gip.x, rv.y, fma(-gip.y, rv.x, x.y)));
+            v[e] = r == p ? rv : nv;
         }
+        if (p + 1 < kBbK && r == p + 1) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = c0 + e;
-            const double2 rv = j == p ? make_double2(inv, 0.0)
-                                      : make_double2(prow[e].x * inv, prow[e].y * inv);
-            double2 nv;
-            if (r == p) {
-                nv = rv;
-            } else {
-                const double2 x = j == p ? make_double2(0.0, 0.0) : mine[e];
-                nv = make_double2(fma(-gip.x, rv.x, fma(gip.y, rv.y, x.x)),
-                                  fma(-gip.x, rv.y, fma(-gip.y, rv.x, x.y)));
-            }
-            if (r < K && j < K) g[r][j] = nv;
+            for (int e = 0; e < 4; ++e) prow[p + 1][4 * q + e] = v[e];
         }
     }
     return 0;
@@ -189,8 +225,7 @@ struct BbIn {
     float2 g[kBbK];
 };
 
-__device__ __forceinline__ void bb_fetch(const BbDev& a, int64_t b, int tid, BbIn& in) {
-    const int K = a.K, M = a.M;
+__device__ __forceinline__ void bb_fetch(const BbDev& a, int64_t b, int tid, BbIn& in, int K, int M) {
     // clamped indices: every lane loads a valid address, unused values are never read
     const int m = tid < M ? tid : M - 1;
     const double* q = a.ap + (b * M + m) * 3;
@@ -205,65 +240,79 @@ __device__ __forceinline__ void bb_fetch(const BbDev& a, int64_t b, int tid, BbI
     if (tid < 3 * K) in.u = a.users[b * K * 3 + tid];
 }
 
-// 1. the users' channels of deployment b, from the inputs in registers
-template <int MODE>
-__device__ __forceinline__ void bb_deployment(const BbDev& a, int64_t b, BbShared& S, const BbIn& in) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int K = a.K, M = a.M;
+// 1. the users' channels of deployment b, from the inputs in registers:
+// rows i < K only (rows K .. 15 of H in LDS stay zero from the start of the
+// kernel); lanes m >= M compute antenna M - 1's terms (clamped inputs) and
+// write them to the pad column, which nothing reads, so H's columns M .. 255
+// stay zero as well.  Returns the lane's largest |Re h|, |Im h| (MIX).
+template <int MODE, bool RICIAN, bool WANT_H>
+__device__ __forceinline__ float bb_synth_rows(const BbDev& a, int64_t b, BbShared& S, const BbIn& in,
+                                               int K, int M, int tid) {
     const bool live = tid < M;
-    const double ax = in.ax, ay = in.ay, az = in.az;
-    const bool rician = a.nlos != nullptr;
-    float2* const Hb = a.H ? a.H + b * K * M + tid : nullptr;
+    const int col = live ? tid : kBbP - 1;
+    float2* const Hb = WANT_H ? a.H + b * K * M + tid : nullptr;
+    const float a_los = (float)a.w.a_los, a_nlos = (float)a.w.a_nlos;
     float mx = 0.0f;
-    // all 16 rows are computed (rows k >= K from user 0's position) and the
-    // unused ones zeroed: no per-row lane masks
 #pragma unroll
     for (int i = 0; i < kBbK; ++i) {
-        const int iu = i < K ? i : 0;
-        const TermF32 t = wave_term_f32(S.user[iu][0] - ax, S.user[iu][1] - ay, S.user[iu][2] - az,
+        if (i >= K) continue;   // uniform; the loop stays fully unrolled
+        const TermF32 t = wave_term_f32(S.user[i][0] - in.ax, S.user[i][1] - in.ay, S.user[i][2] - in.az,
                                         a.w.inv_lam, (float)a.w.amp_c, (float)a.w.inv_dmin);
         float2 h;
-        if (rician) {
+        if constexpr (RICIAN) {
             const float2 g = in.g[i];
-            h.x = t.amp * fmaf((float)a.w.a_los, t.c, (float)a.w.a_nlos * g.x);
-            h.y = t.amp * fmaf(-(float)a.w.a_los, t.s, (float)a.w.a_nlos * g.y);
+            h.x = t.amp * fmaf(a_los, t.c, a_nlos * g.x);
+            h.y = t.amp * fmaf(-a_los, t.s, a_nlos * g.y);
         } else {
             h.x = t.amp * t.c;
             h.y = -t.amp * t.s;
         }
-        const bool use = live && i < K;
-        h = use ? h : make_float2(0.f, 0.f);
-        if (Hb && use) Hb[i * M] = h;
-        if (MODE == 1) mx = fmaxf(mx, fmaxf(fabsf(h.x), fabsf(h.y)));
-        S.h[i][tid] = h;    // zero rows and columns pad H to 16 x 256
+        if constexpr (WANT_H) {
+            if (live) Hb[i * M] = h;
+        }
+        if constexpr (MODE != 0) mx = fmaxf(mx, fmaxf(fabsf(h.x), fabsf(h.y)));
+        S.h[i][col] = h;
     }
-    if constexpr (MODE == 1) {
+    return mx;
+}
+
+template <int MODE>
+__device__ __forceinline__ void bb_deployment(const BbDev& a, int64_t b, BbShared& S, const BbIn& in,
+                                              int K, int M, int tid) {
+    float mx;
+    if (a.nlos) {
+        mx = a.H ? bb_synth_rows<MODE, true, true>(a, b, S, in, K, M, tid)
+                 : bb_synth_rows<MODE, true, false>(a, b, S, in, K, M, tid);
+    } else {
+        mx = a.H ? bb_synth_rows<MODE, false, true>(a, b, S, in, K, M, tid)
+                 : bb_synth_rows<MODE, false, false>(a, b, S, in, K, M, tid);
+    }
+    if constexpr (MODE != 0) {
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-        if (lane == 0) S.hmax[wave] = mx;
+        if ((tid & 63) == 0) S.hmax[tid >> 6] = mx;
     }
-    (void)lane;
-    (void)wave;
     (void)mx;
 }
 
-// 2 - 5: the Gram, the precoder and the epilogues of deployment b
+// 2 - 5: the Gram, the precoder and the epilogues of deployment b; the next
+// deployment's users (in.u, if `more`) go to LDS before the last barrier
 template <int MODE>
-__device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, const BbIn& in,
+                                        bool more, int K, int M, int tid) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int K = a.K, M = a.M;
+    const bool zf = a.precoder == DMIMO_ZF;
     __syncthreads();
-    int hexp = 0;
-    if constexpr (MODE == 1) {
-        // FP16: largest |h| of the deployment scaled into [2^13, 2^14)
+    // MIX: largest |h| of the deployment scaled into [2^13, 2^14) for the
+    // FP16 products (the Gram in FP16 mode, X = G^-1 H in both)
+    int xexp = 0;
+    if constexpr (MODE != 0) {
         const float m4 = fmaxf(fmaxf(S.hmax[0], S.hmax[1]), fmaxf(S.hmax[2], S.hmax[3]));
-        hexp = m4 > 0.0f ? 14 - (ilogbf(m4) + 1) : 0;
+        xexp = m4 > 0.0f ? 14 - (ilogbf(m4) + 1) : 0;
     }
+    const int hexp = MODE == 1 ? xexp : 0;
 
-    // 2. the Gram, per wave, then added in wave order in FP64
+    // 2. the Gram, per wave
     if (64 * wave < M) {
         bb_gram<MODE>(S, wave, lane, hexp);
     } else {
@@ -274,145 +323,224 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S) 
         }
     }
     __syncthreads();
-    {
-        const int i = tid >> 4, j = tid & 15;
-        const int ii = i <= j ? i : j, jj = i <= j ? j : i;   // upper triangle, mirrored
-        double gr = 0.0, gim = 0.0;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            gr += (double)S.u.part[w][0][ii][jj];
-            gim += (double)S.u.part[w][1][ii][jj];
-        }
-        if (MODE == 1) {
-            gr = ldexp(gr, -2 * hexp);
-            gim = ldexp(gim, -2 * hexp);
-        }
-        if (i == j) gim = 0.0;
-        if (i > j) gim = -gim;
-        const double2 v = make_double2(gr, gim);
-        S.g0[i][j] = v;
-        S.gi[i][j] = v;
-        if (i == j) S.d0[i] = gr;
-    }
-    __syncthreads();
 
-    // 3. ZF: the inverse (wave 0); the scale of every row of W
-    const bool zf = a.precoder == DMIMO_ZF;
-    if (zf && wave == 0) {
-        const int f = bb_invert_wave(S.gi, S.d0, K, a.pivot_tol, lane);
-        if (lane == 0) S.fail = f;
+    // 3. wave 0: the partials added in wave order in FP64 (upper triangle,
+    //    mirrored: G exactly Hermitian), G^-1 (ZF), the scale of every row of W
+    if (wave == 0) {
+        const int r = lane >> 2, q = lane & 3;
+        double2 v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * q + e;
+            const int ii = r <= j ? r : j, jj = r <= j ? j : r;
+            double gr = 0.0, gim = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                gr += (double)S.u.part[w][0][ii][jj];
+                gim += (double)S.u.part[w][1][ii][jj];
+            }
+            if (MODE == 1) {
+                gr = ldexp(gr, -2 * hexp);
+                gim = ldexp(gim, -2 * hexp);
+            }
+            gim = r == j ? 0.0 : (r > j ? -gim : gim);
+            v[e] = make_double2(gr, gim);
+            S.g0[r][j] = v[e];
+        }
+        int fail = 0, aexp = 0;
+        double t = 0.0;
+        if (zf) {
+            // padded to 16 x 16 with the identity outside K x K
+            const double dg = (lane & 15) < K ? S.g0[lane & 15][lane & 15].x : 1.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = 4 * q + e;
+                if (r >= K || j >= K) v[e] = make_double2(r == j ? 1.0 : 0.0, 0.0);
+            }
+            fail = bb_gauss_jordan(v, S.u.prow, dg, a.pivot_tol, lane);
+            double mx = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = 4 * q + e;
+                const double2 x = r < K && j < K ? v[e] : make_double2(0.0, 0.0);
+                S.gi[r][j] = x;
+                if (j == r) t = x.x;
+                mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
+            }
+            if (MODE != 0) {
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+                aexp = mx > 0.0 ? 14 - (ilogb(mx) + 1) : 0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * q + e == r) t = v[e].x;
+        }
+        const double tr = wave_sum(t);   // tr(G^-1) (ZF) or tr(G) (MR)
+        if (lane < kBbK) {
+            double c;
+            if (a.p_total > 0.0)
+                c = tr > 0.0 ? sqrt(a.p_total / tr) : 0.0;
+            else
+                c = zf ? S.cpaper[lane] : 1.0;
+            S.c[lane] = fail || lane >= K ? 0.0 : c;
+        }
+        if (lane == 0) {
+            S.fail = fail;
+            S.aexp = aexp;
+        }
     }
     __syncthreads();
     const int fail = S.fail;
-    if (tid < K) {
-        double c;
-        if (a.p_total > 0.0) {
-            double tr = 0.0;
-            for (int k = 0; k < K; ++k) tr += zf ? S.gi[k][k].x : S.g0[k][k].x;
-            c = tr > 0.0 ? sqrt(a.p_total / tr) : 0.0;
-        } else {
-            c = zf ? S.cpaper[tid] : 1.0;
-        }
-        S.c[tid] = fail ? 0.0 : c;
-    }
-    __syncthreads();
 
-    // 4. X = G^-1 H (or H), W = c conj(X), p_m; wave w takes antenna tiles
-    //    4 w .. 4 w + 3 of 16 antennas
+    // 4. X = G^-1 H (or H), W = c conj(X), p_m (FP32 sum of the 16 |w_km|^2);
+    //    wave w takes antenna tiles 4 w .. 4 w + 3 of 16 antennas.  A failed
+    //    deployment has c = 0, hence W = 0 (X is finite).
     double l21_part = 0.0;
     {
-        const int kq = lane >> 4, col = lane & 15;    // operand lane (k', i) / output lane (g, c)
-        float ar[4], ai[4];
-        if (zf) {
+        const int g = lane >> 4, col = lane & 15;    // operand lane (g, i) / output lane (g, c)
+        float2* const Wt = a.W ? a.W + (b * K + 4 * g) * M + col : nullptr;
+        double* const Pt = a.p_ant ? a.p_ant + b * M + col : nullptr;
+        auto tiles = [&](auto zf_c) {
+            constexpr bool ZF = decltype(zf_c)::value;
+            float ar[4], ai[4];
+            u32x4 arh, arl, aih, ail;
+            int xs = 0;                              // X is 2^xs times G^-1 H
+            if constexpr (ZF) {
+                if constexpr (MODE == 0) {
+                    // 16x16x4: lane (k', i) holds G^-1[i][4 t + k']
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const double2 v = S.gi[col][4 * t + kq];
-                const bool in = col < K && 4 * t + kq < K;
-                ar[t] = in ? (float)v.x : 0.0f;
-                ai[t] = in ? (float)v.y : 0.0f;
-            }
-        }
-        float cs[4];
+                    for (int t = 0; t < 4; ++t) {
+                        const double2 v = S.gi[col][4 * t + g];
+                        ar[t] = (float)v.x;
+                        ai[t] = (float)v.y;
+                    }
+                } else {
+                    // 16x16x32 over [re; im] of 16 users: lane (g, i) holds
+                    // [Gr | -Gi][i][8 g ..] (Xr) and [Gi | Gr][i][8 g ..] (Xi),
+                    // scaled by 2^aexp and split in FP16 hi/lo
+                    const int aexp = S.aexp;
+                    const int l0 = 8 * (g & 1);
+                    const bool lower = g < 2;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cs[r] = 4 * kq + r < K ? (float)S.c[4 * kq + r] : 0.0f;
-        for (int n = 4 * wave; n < 4 * wave + 4 && 16 * n < M; ++n) {
-            const int m0 = 16 * n;
-            f32x4 xr = {0.f, 0.f, 0.f, 0.f}, xi = {0.f, 0.f, 0.f, 0.f};
-            if (zf) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float2 hv = S.h[4 * t + kq][m0 + col];
-                    xr = mfma4(ar[t], hv.x, xr);
-                    xr = mfma4(-ai[t], hv.y, xr);
-                    xi = mfma4(ar[t], hv.y, xi);
-                    xi = mfma4(ai[t], hv.x, xi);
+                    for (int e = 0; e < 8; e += 2) {
+                        const double2 v0 = S.gi[col][l0 + e], v1 = S.gi[col][l0 + e + 1];
+                        const float r0 = (float)ldexp(lower ? v0.x : -v0.y, aexp);
+                        const float r1 = (float)ldexp(lower ? v1.x : -v1.y, aexp);
+                        const float i0 = (float)ldexp(lower ? v0.y : v0.x, aexp);
+                        const float i1 = (float)ldexp(lower ? v1.y : v1.x, aexp);
+                        float q0, q1;
+                        arh[e >> 1] = pack_hi<false>(r0, r1, q0, q1);
+                        arl[e >> 1] = pack_lo<false>(q0, q1);
+                        aih[e >> 1] = pack_hi<false>(i0, i1, q0, q1);
+                        ail[e >> 1] = pack_lo<false>(q0, q1);
+                    }
+                    xs = aexp + xexp;
                 }
-            } else {
+            }
+            float cs[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cs[r] = ldexpf((float)S.c[4 * g + r], -xs);
+            for (int n = 4 * wave; n < 4 * wave + 4 && 16 * n < M; ++n) {
+                const int m0 = 16 * n;
+                f32x4 xr = {0.f, 0.f, 0.f, 0.f}, xi = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (!ZF) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float2 hv = S.h[4 * g + r][m0 + col];
+                        xr[r] = hv.x;
+                        xi[r] = hv.y;
+                    }
+                } else if constexpr (MODE == 0) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float2 hv = S.h[4 * t + g][m0 + col];
+                        xr = mfma4(ar[t], hv.x, xr);
+                        xr = mfma4(-ai[t], hv.y, xr);
+                        xi = mfma4(ar[t], hv.y, xi);
+                        xi = mfma4(ai[t], hv.x, xi);
+                    }
+                } else {
+                    // lane (g, j): [Hr; Hi][8 g .. 8 g + 7][m0 + j], hi/lo split
+                    const float* hp = &S.h[8 * (g & 1)][m0 + col].x + (g < 2 ? 0 : 1);
+                    u32x4 bh, bl;
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+                        float q0, q1;
+                        bh[e >> 1] = pack_hi<false>(ldexpf(hp[e * 2 * kBbP], xexp),
+                                                    ldexpf(hp[(e + 1) * 2 * kBbP], xexp), q0, q1);
+                        bl[e >> 1] = pack_lo<false>(q0, q1);
+                    }
+                    xr = mfma16<false>(arh, bh, xr);
+                    xr = mfma16<false>(arl, bh, xr);
+                    xr = mfma16<false>(arh, bl, xr);
+                    xi = mfma16<false>(aih, bh, xi);
+                    xi = mfma16<false>(ail, bh, xi);
+                    xi = mfma16<false>(aih, bl, xi);
+                }
+                // lane (g, c) holds X[4 g + r][m0 + c]
+                const bool in = m0 + col < M;
+                float pm = 0.0f;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float2 hv = S.h[4 * kq + r][m0 + col];
-                    xr[r] = hv.x;
-                    xi[r] = hv.y;
+                    const float2 wv = make_float2(cs[r] * xr[r], -cs[r] * xi[r]);
+                    if (Wt && in && 4 * g + r < K) Wt[r * M + m0] = wv;
+                    pm = fmaf(wv.x, wv.x, fmaf(wv.y, wv.y, pm));
+                }
+                pm += __shfl_xor(pm, 16, 64);
+                pm += __shfl_xor(pm, 32, 64);
+                if (g == 0 && in) {
+                    if (Pt) Pt[m0] = (double)pm;
+                    l21_part += (double)__builtin_amdgcn_sqrtf(pm);   // hardware sqrt, within an ulp
                 }
             }
-            // lane (g, c) holds X[4 g + r][m0 + c]
-            const int m = m0 + col;
-            double pm = 0.0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int k = 4 * kq + r;
-                const float wr = cs[r] * xr[r], wi = -cs[r] * xi[r];
-                if (a.W && k < K && m < M) a.W[(b * K + k) * M + m] = make_float2(wr, wi);
-                pm += (double)wr * (double)wr + (double)wi * (double)wi;
-            }
-            pm += __shfl_xor(pm, 16, 64);
-            pm += __shfl_xor(pm, 32, 64);
-            if (m < M) {
-                if (a.p_ant && kq == 0) a.p_ant[b * M + m] = pm;
-                if (kq == 0) l21_part += sqrt(pm);
-            }
-        }
+        };
+        if (zf)
+            tiles(std::true_type{});
+        else
+            tiles(std::false_type{});
     }
     for (int off = 8; off > 0; off >>= 1) l21_part += __shfl_xor(l21_part, off, 64);
     if (lane == 0) S.red[wave] = l21_part;
 
-    // 5. gains A = G G^-1 D_c (ZF) or c G (MR), SINR_k, sum rate
+    // 5. gains A = G G^-1 D_c (ZF) or G D_c (MR), FP64, thread (k, j) on
+    //    A[k][j]; SINR_k = |A_kk|^2 / (sum_{j != k} |A_kj|^2 + sigma^2)
     {
         const int k = tid >> 4, j = tid & 15;
         double2 acc = make_double2(0.0, 0.0);
-        if (k < K && j < K && !fail) {
-            if (zf) {
-                for (int l = 0; l < K; ++l) {
-                    const double2 x = S.g0[k][l], y = S.gi[l][j];
-                    acc.x = fma(x.x, y.x, fma(-x.y, y.y, acc.x));
-                    acc.y = fma(x.x, y.y, fma(x.y, y.x, acc.y));
-                }
-            } else {
-                acc = S.g0[k][j];
+        if (zf) {
+#pragma unroll
+            for (int l = 0; l < kBbK; ++l) {
+                const double2 x = S.g0[k][l], y = S.gi[l][j];
+                acc.x = fma(x.x, y.x, fma(-x.y, y.y, acc.x));
+                acc.y = fma(x.x, y.y, fma(x.y, y.x, acc.y));
             }
-            acc.x *= S.c[j];
-            acc.y *= S.c[j];
+        } else {
+            acc = S.g0[k][j];
         }
-        __syncthreads();   // the Gram partials are dead; A reuses their bytes
-        S.u.A[k][j] = acc;
-    }
-    __syncthreads();
-    if (tid < K) {
-        double sig = 0.0, intf = 0.0;
-        for (int j = 0; j < K; ++j) {
-            const double2 v = S.u.A[tid][j];
-            const double p = v.x * v.x + v.y * v.y;
-            if (j == tid) sig = p;
-            else intf += p;
+        const double cj = S.c[j];
+        acc.x *= cj;
+        acc.y *= cj;
+        const double pw = acc.x * acc.x + acc.y * acc.y;
+        double sig = j == k ? pw : 0.0, itf = j == k ? 0.0 : pw;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            sig += __shfl_xor(sig, off, 64);
+            itf += __shfl_xor(itf, off, 64);
         }
-        const double s = fail ? 0.0 : sig / (intf + a.sigma2);
-        if (a.sinr) a.sinr[b * K + tid] = s;
-        S.d0[tid] = log2(1.0 + s);
+        if (j == 0 && k < K) {
+            const double s = fail ? 0.0 : sig / (itf + a.sigma2);
+            if (a.sinr) a.sinr[b * K + k] = s;
+            S.rate[k] = log2(1.0 + s);
+        }
     }
+    if (more && tid < 3 * K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     __syncthreads();
     if (tid == 0) {
         double rs = 0.0;
-        for (int k = 0; k < K; ++k) rs += S.d0[k];
+#pragma unroll
+        for (int k = 0; k < kBbK; ++k) rs += k < K ? S.rate[k] : 0.0;
         if (a.rsum) a.rsum[b] = fail ? 0.0 : rs;
         if (a.l21) a.l21[b] = fail ? 0.0 : ((S.red[0] + S.red[1]) + S.red[2]) + S.red[3];
         if (a.info) a.info[b] = fail;
@@ -421,23 +549,30 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S) 
 
 // Persistent: workgroup w takes deployments w, w + gridDim.x, ...; the next
 // deployment's inputs are loaded into registers while the current one runs.
+// Four barriers per deployment: H in LDS, the Gram partials, G^-1 and the
+// scales, the epilogues (which also publish the next deployment's users).
 template <int MODE>
 __global__ __launch_bounds__(kBbThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void beamform_batched_kernel(BbDev a) {
     __shared__ BbShared S;
     const int tid = threadIdx.x;
-    const int K = a.K;
     BbIn in;
     if (tid < kBbK) S.cpaper[tid] = a.cpaper[tid];
-    if ((int64_t)blockIdx.x < a.B) bb_fetch(a, blockIdx.x, tid, in);
+#pragma unroll
+    for (int i = 0; i < kBbK; ++i) S.h[i][tid] = make_float2(0.0f, 0.0f);
+    bb_fetch(a, blockIdx.x, tid, in, a.K, a.M);   // the grid has at most B workgroups
+    if (tid < 3 * a.K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
+    __syncthreads();
     for (int64_t b = blockIdx.x; b < a.B; b += gridDim.x) {
-        if (tid < 3 * K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
-        if (tid == 0) S.fail = 0;
-        __syncthreads();
-        bb_deployment<MODE>(a, b, S, in);
-        if (b + gridDim.x < a.B) bb_fetch(a, b + gridDim.x, tid, in);   // in flight meanwhile
-        bb_rest<MODE>(a, b, S);
-        __syncthreads();   // LDS is rewritten for the next deployment
+        // K, M and the thread index made opaque in every iteration: what is
+        // derived from them is formed where it is used instead of held in
+        // registers across the loop
+        int K = a.K, M = a.M, t = tid;
+        asm volatile("" : "+s"(K), "+s"(M), "+v"(t));
+        bb_deployment<MODE>(a, b, S, in, K, M, t);
+        const bool more = b + gridDim.x < a.B;
+        if (more) bb_fetch(a, b + gridDim.x, t, in, K, M);   // in flight meanwhile
+        bb_rest<MODE>(a, b, S, in, more, K, M, t);
     }
 }
 
