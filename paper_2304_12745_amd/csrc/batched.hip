@@ -86,6 +86,15 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// x summed over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the same bits in
+// all four): the row swaps of v_permlane16_swap / v_permlane32_swap
+__device__ __forceinline__ float sum_rows4(float x) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+
 __device__ __forceinline__ double readlane_d(double x, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
@@ -121,11 +130,11 @@ __device__ __forceinline__ double wave_sum(double x) {
 // broadcast within the quad that holds the row (DPP), and the pivot row's
 // entries of its columns through LDS (prow), where the lanes of row p + 1
 // leave that row after step p.  The pivot of step p is the diagonal entry of
-// the Schur complement (L_pp^2 of the Cholesky factor); one not above
-// tol * dg[p] (dg[p] in lane p) stops the elimination.  Returns 0 or the
-// failed step p + 1, the same in every lane.
-__device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[kBbK], double dg,
-                                               double tol, int lane) {
+// the Schur complement (L_pp^2 of the Cholesky factor); one not above th[p]
+// (held by lane p) stops the elimination.  Returns 0 or the failed step
+// p + 1, the same in every lane (v is then not used).
+__device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[kBbK], double th,
+                                               int lane) {
     const int r = lane >> 2, q = lane & 3;
     if (r == 0) {
 #pragma unroll
@@ -134,8 +143,7 @@ __device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[
 #pragma unroll
     for (int p = 0; p < kBbK; ++p) {
         const double piv = readlane_d(v[p & 3].x, 4 * p + (p >> 2));
-        const double dp = readlane_d(dg, p);
-        if (!(piv > tol * dp)) return p + 1;
+        if (!(piv > readlane_d(th, p))) return p + 1;
         // 1 / piv: hardware reciprocal and two Newton steps (within an ulp)
         double inv = __builtin_amdgcn_rcp(piv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
@@ -225,6 +233,14 @@ struct BbIn {
     float2 g[kBbK];
 };
 
+// Marks the inputs as read here: the compiler waits for their loads at this
+// point and at no later one.
+__device__ __forceinline__ void bb_settle(BbIn& in) {
+    asm volatile("" : "+v"(in.ax), "+v"(in.ay), "+v"(in.az), "+v"(in.u));
+#pragma unroll
+    for (int i = 0; i < kBbK; ++i) asm volatile("" : "+v"(in.g[i].x), "+v"(in.g[i].y));
+}
+
 __device__ __forceinline__ void bb_fetch(const BbDev& a, int64_t b, int tid, BbIn& in, int K, int M) {
     // clamped indices: every lane loads a valid address, unused values are never read
     const int m = tid < M ? tid : M - 1;
@@ -297,7 +313,7 @@ __device__ __forceinline__ void bb_deployment(const BbDev& a, int64_t b, BbShare
 // 2 - 5: the Gram, the precoder and the epilogues of deployment b; the next
 // deployment's users (in.u, if `more`) go to LDS before the last barrier
 template <int MODE>
-__device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, const BbIn& in,
+__device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, BbIn& in,
                                         bool more, int K, int M, int tid) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -327,6 +343,9 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
     // 3. wave 0: the partials added in wave order in FP64 (upper triangle,
     //    mirrored: G exactly Hermitian), G^-1 (ZF), the scale of every row of W
     if (wave == 0) {
+        // the other waves wait for this one: it issues ahead of the waves of
+        // the other workgroups on its SIMD until the scales are out
+        __builtin_amdgcn_s_setprio(3);
         const int r = lane >> 2, q = lane & 3;
         double2 v[4];
 #pragma unroll
@@ -351,18 +370,18 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
         double t = 0.0;
         if (zf) {
             // padded to 16 x 16 with the identity outside K x K
-            const double dg = (lane & 15) < K ? S.g0[lane & 15][lane & 15].x : 1.0;
+            const double th = (lane & 15) < K ? a.pivot_tol * S.g0[lane & 15][lane & 15].x : 0.5;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = 4 * q + e;
                 if (r >= K || j >= K) v[e] = make_double2(r == j ? 1.0 : 0.0, 0.0);
             }
-            fail = bb_gauss_jordan(v, S.u.prow, dg, a.pivot_tol, lane);
+            fail = bb_gauss_jordan(v, S.u.prow, th, lane);
             double mx = 0.0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = 4 * q + e;
-                const double2 x = r < K && j < K ? v[e] : make_double2(0.0, 0.0);
+                const double2 x = r < K && j < K && !fail ? v[e] : make_double2(0.0, 0.0);
                 S.gi[r][j] = x;
                 if (j == r) t = x.x;
                 mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
@@ -390,9 +409,15 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
             S.fail = fail;
             S.aexp = aexp;
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
     const int fail = S.fail;
+    // The next deployment's inputs, loaded since the synthesis, are waited
+    // for here, before this deployment's stores: the loads and the stores
+    // share one counter, and a wait for a load behind pending stores would
+    // be a wait for the stores as well.
+    bb_settle(in);
 
     // 4. X = G^-1 H (or H), W = c conj(X), p_m (FP32 sum of the 16 |w_km|^2);
     //    wave w takes antenna tiles 4 w .. 4 w + 3 of 16 antennas.  A failed
@@ -442,8 +467,10 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
             float cs[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) cs[r] = ldexpf((float)S.c[4 * g + r], -xs);
-            for (int n = 4 * wave; n < 4 * wave + 4 && 16 * n < M; ++n) {
-                const int m0 = 16 * n;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int m0 = 64 * wave + 16 * t;
+                if (m0 >= M) break;
                 f32x4 xr = {0.f, 0.f, 0.f, 0.f}, xi = {0.f, 0.f, 0.f, 0.f};
                 if constexpr (!ZF) {
 #pragma unroll
@@ -488,8 +515,7 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
                     if (Wt && in && 4 * g + r < K) Wt[r * M + m0] = wv;
                     pm = fmaf(wv.x, wv.x, fmaf(wv.y, wv.y, pm));
                 }
-                pm += __shfl_xor(pm, 16, 64);
-                pm += __shfl_xor(pm, 32, 64);
+                pm = sum_rows4(pm);
                 if (g == 0 && in) {
                     if (Pt) Pt[m0] = (double)pm;
                     l21_part += (double)__builtin_amdgcn_sqrtf(pm);   // hardware sqrt, within an ulp
@@ -561,6 +587,7 @@ void beamform_batched_kernel(BbDev a) {
 #pragma unroll
     for (int i = 0; i < kBbK; ++i) S.h[i][tid] = make_float2(0.0f, 0.0f);
     bb_fetch(a, blockIdx.x, tid, in, a.K, a.M);   // the grid has at most B workgroups
+    bb_settle(in);
     if (tid < 3 * a.K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     __syncthreads();
     for (int64_t b = blockIdx.x; b < a.B; b += gridDim.x) {
