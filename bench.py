@@ -186,6 +186,8 @@ def parse_args():
                    help="skip the batched Gram + ZF phase")
     p.add_argument("--only-hall", action="store_true",
                    help="the hall steps and their roofline only (profiling runs)")
+    p.add_argument("--only-batched", action="store_true",
+                   help="the batched phase only, printed as its own JSON line (profiling runs)")
     return p.parse_args()
 
 
@@ -484,6 +486,10 @@ def main():
     cp_dst = torch.empty_like(cp_src)
     cp_dst.copy_(cp_src)
 
+    if args.only_batched:
+        print(json.dumps({"batched": batched_phase(D, WL, torch, args.event_launches)}), flush=True)
+        return
+
     hall = hall_phase(args, D, WL, torch)
     head = hall["f16x3"]
     hs = head.pop("step")
@@ -566,7 +572,7 @@ def main():
         if not args.no_channel:
             out["channel"] = channel_phase(D, WL, torch)
         if not args.no_batched:
-            out["batched"] = batched_phase(D, WL, torch)
+            out["batched"] = batched_phase(D, WL, torch, args.event_launches)
         if args.serve_seconds > 0:
             out["serving"] = serving_phase(args, D, WL, torch)
             out["p99_query_ms"] = out["serving"]["p99_ms"]
@@ -882,19 +888,38 @@ def channel_phase(D, WL, torch):
     return out
 
 
-def batched_phase(D, WL, torch):
-    """Batched mixed-precision ZF (B deployments of K = 16 users and M = 256
-    antennas, 5.8 GHz).
+# every file the fused batched kernel is compiled from
+BATCHED_SOURCES = ["paper_2304_12745_amd/csrc/batched.hip",
+                   "paper_2304_12745_amd/csrc/split16.h",
+                   "paper_2304_12745_amd/csrc/kernels.h",
+                   "paper_2304_12745_amd/csrc/dmimo_internal.h"]
+BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_rician_traffic.json")
 
-    * ``rician``: the configuration as defined: 1024 rooms, Rician channels
-      (K-factor 6 dB, CN(0,1) NLoS draws from the seed) synthesised by
-      dmimo_channel from the positions and the NLoS array, then dmimo_beamform
-      ZF at 1 W with the FP16x3 (and FP32) Gram, FP64 inverse, per-user SINR;
-      per-user SINR_k against the oracle chain in dB on sampled deployments.
-    * ``sweep``: Gram + ZF alone for B = 2^10 .. 2^17 with the FP32 and the
-      FP16x3 Gram; H is CN(0,1), drawn on the device with a fixed seed (the
-      cost does not depend on the channel values).
-    Times from HIP events around back-to-back calls."""
+
+def batched_bytes(B, K, M, want_W=True):
+    """Algorithmic HBM bytes of one fused batched launch: the NLoS draws, the
+    antenna and user positions read once, W, p_m, SINR_k, R_sum, l21 and
+    info written once."""
+    per = K * M * 8 + M * 24 + K * 24 + (K * M * 8 if want_W else 0) + M * 8 + K * 8 + 8 + 8 + 4
+    return B * per
+
+
+def batched_phase(D, WL, torch, event_launches=30):
+    """The batched configuration: B independent rooms of K = 16 users and
+    M = 256 antennas at 5.8 GHz, Rician channels (K-factor 6 dB, CN(0,1) NLoS
+    draws from the seed), ZF at 1 W, -90 dBm, per-user SINR_k and R_sum.
+
+    * ``rician``: the 1024 rooms of the configuration through the fused
+      dmimo_beamform_batched (synthesis -> Gram on the matrix cores -> FP64
+      solve -> W, p_m, SINR_k) in FP16x3, BF16x3 and FP32; SINR_k of sampled
+      deployments against the FP64 oracle chain in dB, and against the
+      two-call path (dmimo_channel + dmimo_beamform), which is also timed.
+    * ``sweep``: the fused call for B = 2^10 .. 2^17 (the 1024 rooms tiled),
+      HBM fraction of the algorithmic bytes (batched_bytes).
+    * ``roofline``: B = 2^17 FP16x3 with W written, from HIP events around
+      ``event_launches`` back-to-back launches; traffic from the committed
+      counter summary when it matches the sources.
+    * ``cpu_oracle``: the oracle chain on the sampled deployments, one core."""
     import numpy as np
     from oracle import dmimo_oracle as O
     K, M = 16, 256
@@ -917,55 +942,86 @@ def batched_phase(D, WL, torch):
     ap = torch.from_numpy(w.ap_xyz).cuda()
     users = torch.from_numpy(w.user_xyz).cuda()
     nlos = torch.from_numpy(w.nlos).cuda()
-    pts = D.list_points(users, K)
-    H = D.channel(params, ap, pts, nlos=nlos, prec="f32")
-    ric = {}
     idx = np.arange(0, B, 32)
+    t0 = time.perf_counter()
     Ho = np.stack([O.rician_channel(w.user_xyz[b], w.ap_xyz[b], w.freq_hz, w.kappa_lin,
                                     w.nlos[b].astype(np.complex128)) for b in idx])
     Wo, _ = O.zf_precoder(Ho, None, w.sigma2, w.p_total)
     so = O.user_sinr(Ho, Wo, w.sigma2)
-    for prec in ("f16x3", "f32"):
-        r = D.beamform(H, "zf", None, w.sigma2, w.p_total, prec)
-        ms_bf = timed(lambda: D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=r), 20)
-        ms_ch = timed(lambda: D.channel(params, ap, pts, nlos=nlos, prec="f32", out=H), 20)
-        sg = r.sinr.cpu().numpy()[idx]
-        ric[prec] = {"channel_ms": round(ms_ch, 4), "gram_zf_ms": round(ms_bf, 4),
-                     "ms": round(ms_ch + ms_bf, 4),
-                     "G_h_per_s": round(2 * B * K * M / ((ms_ch + ms_bf) * 1e-3) / 1e9, 2),
+    t_oracle = time.perf_counter() - t0
+    ric = {}
+    for prec in ("f16x3", "bf16x3", "f32"):
+        r = D.beamform_batched(params, ap, users, nlos, "zf", None, w.sigma2, w.p_total, prec)
+        ms = timed(lambda: D.beamform_batched(params, ap, users, nlos, "zf", None, w.sigma2,
+                                              w.p_total, prec, out=r), 20)
+        ric[prec] = {"ms": round(ms, 4),
+                     "deployments_per_s": round(B / (ms * 1e-3), 1),
+                     "G_h_per_s": round(B * K * M / (ms * 1e-3) / 1e9, 2),
+                     "hbm_frac": round(batched_bytes(B, K, M) / (ms * 1e-3) / HBM_PEAK, 4),
                      "failed_deployments": int((r.info != 0).sum().item()),
-                     "err_db_user_sinr": plain_db(sg, so)}
+                     "err_db_user_sinr": plain_db(r.sinr.cpu().numpy()[idx], so)}
+        if prec in ("f16x3", "f32"):
+            # the two-call path: channel to HBM, then Gram + ZF from HBM
+            pts = D.list_points(users, K)
+            H = D.channel(params, ap, pts, nlos=nlos, prec="f32")
+            r2 = D.beamform(H, "zf", None, w.sigma2, w.p_total, prec)
+            ms_ch = timed(lambda: D.channel(params, ap, pts, nlos=nlos, prec="f32", out=H), 20)
+            ms_bf = timed(lambda: D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=r2), 20)
+            ric[prec]["two_call"] = {"channel_ms": round(ms_ch, 4), "gram_zf_ms": round(ms_bf, 4),
+                                     "ms": round(ms_ch + ms_bf, 4)}
+            ric[prec]["err_db_vs_two_call"] = plain_db(r.sinr.cpu().numpy(), r2.sinr.cpu().numpy())
+            del H, r2
+        del r
     ric["workload"] = ("1024 rooms 20x20x4 m, 16x16 jittered ceiling APs, 16 users at 1.2 m, "
                        "5.8 GHz, Rician K-factor 6 dB with CN(0,1) NLoS draws, ZF at 1 W, "
-                       "-90 dBm; dmimo_channel (Rician) then dmimo_beamform")
+                       "-90 dBm; one dmimo_beamform_batched launch")
     ric["compared"] = f"per-user SINR_k of {len(idx)} sampled deployments vs the oracle chain"
-    del H, nlos
     torch.cuda.empty_cache()
 
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(3)
-    bmax = 1 << 17
-    Hs = torch.complex(torch.randn(bmax, K, M, generator=gen, device="cuda"),
-                       torch.randn(bmax, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
     sweep = []
-    for prec in ("f32", "f16x3"):
+    roof = None
+    bmax = 1 << 17
+    f = bmax // B
+    apT = ap.repeat(f, 1, 1).contiguous()
+    usT = users.repeat(f, 1, 1).contiguous()
+    nlT = nlos.repeat(f, 1, 1).contiguous()
+    for prec in ("f16x3", "f32"):
         for e in (10, 12, 14, 16, 17):
             Bs = 1 << e
-            Hb = Hs[:Bs]
-            r = D.beamform(Hb, "zf", None, 1e-12, 1.0, prec)
-            ms = timed(lambda: D.beamform(Hb, "zf", None, 1e-12, 1.0, prec, out=r),
-                       20 if Bs <= 1 << 14 else 5)
+            a_, u_, n_ = apT[:Bs], usT[:Bs], nlT[:Bs]
+            r = D.beamform_batched(params, a_, u_, n_, "zf", None, w.sigma2, w.p_total, prec)
+            ms = timed(lambda: D.beamform_batched(params, a_, u_, n_, "zf", None, w.sigma2,
+                                                  w.p_total, prec, out=r),
+                       20 if Bs <= 1 << 14 else 10)
             sweep.append({"B": Bs, "prec": prec, "ms": round(ms, 4),
                           "deployments_per_s": round(Bs / ms * 1e3, 1),
                           "G_h_per_s": round(Bs * K * M / ms / 1e6, 2),
-                          "hbm_frac_h_read_w_write": round(16 * Bs * K * M / (ms * 1e-3) / HBM_PEAK, 4)})
+                          "hbm_frac": round(batched_bytes(Bs, K, M) / (ms * 1e-3) / HBM_PEAK, 4)})
+            if e == 17 and prec == "f16x3":
+                launch_ms = timed(lambda: D.beamform_batched(params, a_, u_, n_, "zf", None, w.sigma2,
+                                                             w.p_total, prec, out=r), event_launches)
+                byts = batched_bytes(Bs, K, M)
+                khash = _src_hash(BATCHED_SOURCES)
+                roof = {"bound": "hbm",
+                        "kernel": "beamform_batched_kernel<1> (FP16x3), 131072 Rician rooms, W written",
+                        "achieved": round(byts / (launch_ms * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": round(byts / (launch_ms * 1e-3) / HBM_PEAK, 4),
+                        "traffic": load_traffic(khash, BATCHED_TRAFFIC_FILE),
+                        "launch_ms": round(launch_ms, 5), "launches_timed": event_launches,
+                        "algorithmic_bytes_per_launch": byts, "source_hash": khash}
             del r
-    del Hs
+    del apT, usT, nlT
     torch.cuda.empty_cache()
     return {"rician": ric,
-            "sweep_workload": "Gram + ZF alone: B deployments x K=16 users x M=256 antennas, "
-                              "H ~ CN(0,1) (device draws), total power 1 W, noise -90 dBm",
-            "sweep": sweep}
+            "sweep_workload": "fused dmimo_beamform_batched, B rooms (the 1024 tiled) x K=16 x M=256, "
+                              "Rician, ZF at 1 W, W written; hbm_frac of the algorithmic bytes "
+                              "(NLoS + positions read, W + p_m + SINR + R_sum written)",
+            "sweep": sweep,
+            "roofline": roof,
+            "cpu_oracle": {"value": round(len(idx) / t_oracle, 2), "unit": "deployments/s",
+                           "cores": 1, "kind": "oracle",
+                           "sample": f"{len(idx)} deployments: rician_channel + zf_precoder + user_sinr"}}
 
 
 def serving_phase(args, D, WL, torch):

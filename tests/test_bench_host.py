@@ -84,3 +84,12 @@ def test_hall_roofline_fields():
 def test_host_info():
     h = bench.host_info()
     assert h["nproc"] >= 1
+
+
+def test_batched_bytes_per_room():
+    # one room of K = 16 users and M = 256 antennas: NLoS draws and positions
+    # read, W, p_m, SINR_k, R_sum, l21 and info written
+    import bench
+    per = 16 * 256 * 8 + 256 * 24 + 16 * 24 + 16 * 256 * 8 + 256 * 8 + 16 * 8 + 8 + 8 + 4
+    assert bench.batched_bytes(1, 16, 256) == per == 74260
+    assert bench.batched_bytes(1024, 16, 256, want_W=False) == 1024 * (per - 16 * 256 * 8)
