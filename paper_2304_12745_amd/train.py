@@ -124,6 +124,25 @@ def evaluate(H, lambdas, etas, gamma_lin, sigma2=1.0):
     return {"rsum": r.rsum.mean().item(), "pcg": pcg}
 
 
+def convergence(H, lambdas, etas, gamma_lin, sigma2=1.0,
+                long_iters=(20, 50, 100, 200, 500, 1000, 2000, 3500, 5000)):
+    """Mean R_sum and PCG per layer (Sec. VI-C): the trained network cut after
+    layer i, and plain PGD (lambda = 1/15, eta = 1/L~) after i iterations, for
+    i = 1 .. I; plain PGD also at the longer iteration counts.  Every point is
+    one dmimo_pgd launch over all channels H [B][K][M] from W(0) = H^*."""
+    I = len(lambdas)
+    K, M = H.shape[1], H.shape[2]
+    L = (math.sqrt(K) + math.sqrt(M)) ** 2
+    uf = [evaluate(H, lambdas[:i], etas[:i], gamma_lin, sigma2) for i in range(1, I + 1)]
+    pgd = [evaluate(H, [1.0 / 15.0] * i, [1.0 / L] * i, gamma_lin, sigma2) for i in range(1, I + 1)]
+    long = [dict(iterations=n, **evaluate(H, [1.0 / 15.0] * n, [1.0 / L] * n, gamma_lin, sigma2))
+            for n in long_iters]
+    return {"layers": list(range(1, I + 1)),
+            "ufpgd": {"pcg": [x["pcg"] for x in uf], "rsum": [x["rsum"] for x in uf]},
+            "pgd": {"pcg": [x["pcg"] for x in pgd], "rsum": [x["rsum"] for x in pgd]},
+            "pgd_long": long}
+
+
 def main(argv=None):
     p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     p.add_argument("--epochs", type=int, default=200)
@@ -136,6 +155,8 @@ def main(argv=None):
     p.add_argument("--lr", type=float, default=1e-3)
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--out", default=None, help="write the trained schedule and metrics as JSON")
+    p.add_argument("--curve", action="store_true",
+                   help="also evaluate R_sum and PCG per layer / iteration on the test set")
     a = p.parse_args(argv)
 
     import torch
@@ -159,12 +180,23 @@ def main(argv=None):
               patience=a.patience, seed=a.seed, log=lambda s: print(s, flush=True))
     test = evaluate(Hte, res.lambdas, res.etas, g)
     print(f"UfPGD, {a.layers} layers, best epoch {res.best_epoch + 1}: {test}", flush=True)
+    curve = None
+    if a.curve:
+        curve = convergence(Hte, res.lambdas, res.etas, g)
+        for i, n in enumerate(curve["layers"]):
+            print(f"layer {n:2d}: UfPGD PCG {curve['ufpgd']['pcg'][i]:.4f} R_sum "
+                  f"{curve['ufpgd']['rsum'][i]:.3f} | PGD PCG {curve['pgd']['pcg'][i]:.4f} R_sum "
+                  f"{curve['pgd']['rsum'][i]:.3f}", flush=True)
+        for x in curve["pgd_long"]:
+            print(f"PGD {x['iterations']:5d} iterations: PCG {x['pcg']:.4f} R_sum {x['rsum']:.3f}",
+                  flush=True)
     if a.out:
         with open(a.out, "w") as f:
             json.dump({"lambdas": res.lambdas, "etas": res.etas, "best_epoch": res.best_epoch + 1,
                        "epochs_run": res.epochs_run, "steps": res.steps, "seconds": res.seconds,
                        "val_cost": res.val_cost, "train_cost": res.train_cost,
-                       "test": test, "pgd_baseline": base, "args": vars(a)}, f, indent=1)
+                       "test": test, "pgd_baseline": base, "curve": curve, "args": vars(a)},
+                      f, indent=1)
     return 0
 
 
