@@ -1,14 +1,16 @@
 // Users' channels, precoder and epilogues of many small deployments in one
 // launch (K <= 16 users, M <= 256 antennas): the batched workload of
 // independent rooms with LoS or Rician channels.  Persistent 256-thread
-// workgroups (four waves, three per CU) take the deployments in turn, with
-// the next deployment's positions and NLoS draws loaded into registers while
-// the current one runs; everything else is in LDS:
+// workgroups (four waves, three per CU) take the deployments b, b + grid, ...
+// in a two-stage pipeline: while wave 0 inverts the Gram of deployment b,
+// waves 1 - 3 synthesise the channel of b + grid into registers, and the
+// inputs of b + 2 grid are loaded.  Per deployment:
 //
 //  1. H: thread m synthesises antenna m's terms for every user with the
 //     channel kernel's term arithmetic (FP64 distance and phase, the same
 //     bits as dmimo_channel), reading the Rician NLoS draws once, coalesced
-//     along m.  H goes to LDS ([K][M], rows padded) and, if asked, to HBM.
+//     along m, into registers (and, if asked, H to HBM); the column goes to
+//     LDS ([16][257], zero past K and M) once the previous deployment is done.
 //  2. G = H H^H on the matrix cores, wave w over antennas 64 w .. 64 w + 63:
 //     FP32 16x16x4 products (DMIMO_F32), or 16x16x32 FP16 / BF16 products of
 //     hi/lo splits, three per real product (MIX modes; FP16 with a power-of-
@@ -16,15 +18,16 @@
 //     Gi = Hi Hr^T - Hr Hi^T, with one register feeding both MFMA operands.
 //     The four partial sums are added in wave order in FP64, and the upper
 //     triangle is mirrored (G exactly Hermitian).
-//  3. ZF: G^-1 by FP64 Gauss-Jordan without pivoting, one entry per thread;
-//     the pivot test of dmimo_beamform (info = failed step).  MR: none.
-//  4. X = G^-1 H by FP32 16x16x4 products (the FP64 inverse rounded to FP32;
-//     Xr = Ar Hr - Ai Hi, Xi = Ar Hi + Ai Hr), or X = H for MR; then
-//     W = c conj(X) to HBM (optional), p_m = sum_k |w_km|^2 and sum_m sqrt(p_m)
-//     in FP64.
-//  5. The gains A = H W^T.  With W = conj(G^-1 H) D_c and G = H H^H this is
-//     A = G G^-1 D_c for ZF and A = c G for MR (exact identities), formed in
-//     FP64 from the same G; SINR_k and the sum rate follow (Sec. VI-B).
+//  3. ZF: G^-1 by FP64 Gauss-Jordan without pivoting in wave 0's registers;
+//     the pivot test of dmimo_beamform (info = failed step); the scales of
+//     W's rows.  MR: the scales only.
+//  4. Waves 1 - 3: X = G^-1 H (FP32 16x16x4 products of the FP64 inverse
+//     rounded to FP32, or split-FP16 16x16x32 products in the MIX modes), or
+//     X = H for MR; W = c conj(X) to HBM (optional), p_m and sum_m sqrt(p_m).
+//  5. Wave 0: the gains A = H W^T.  With W = conj(G^-1 H) D_c and G = H H^H
+//     this is A = G G^-1 D_c for ZF and A = G D_c for MR (exact identities),
+//     formed in FP64 on the matrix cores from the same G; SINR_k and the sum
+//     rate follow (Sec. VI-B).
 // A deployment reads its NLoS draws (8 B per term) and positions and writes
 // W (8 B per term, optional) and the epilogues: nothing else touches HBM.
 #include <algorithm>
@@ -169,6 +172,65 @@ __device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[
     return 0;
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// 5. (one wave) the gains A = G G^-1 D_c (ZF) or G D_c (MR) in FP64, on the
+// matrix cores for ZF (16x16x4 FP64: lane (k', i) supplies G[i][4t + k'],
+// lane (k', j) G^-1[4t + k'][j]; lane (g, j) receives A[g + 4r][j]), then
+// SINR_k = |A_kk|^2 / (sum_{j != k} |A_kj|^2 + sigma^2) by 16-lane shuffle
+// sums, written for k < K with log2(1 + SINR_k) to LDS for R_sum.
+__device__ __forceinline__ void bb_gains(const BbDev& a, int64_t b, BbShared& S, int K, int lane,
+                                         int fail, bool zf) {
+    const int kq = lane >> 4, x = lane & 15;
+    f64x4 ar = {0.0, 0.0, 0.0, 0.0}, ai = {0.0, 0.0, 0.0, 0.0};
+    if (zf) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double2 g = S.g0[x][4 * t + kq];
+            const double2 v = S.gi[4 * t + kq][x];
+            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.x, ar, 0, 0, 0);
+            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-g.y, v.y, ar, 0, 0, 0);
+            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.y, ai, 0, 0, 0);
+            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(g.y, v.x, ai, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double2 g = S.g0[kq + 4 * r][x];
+            ar[r] = g.x;
+            ai[r] = g.y;
+        }
+    }
+    const double cj = S.c[x];
+    double sig[4], itf[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double pw = (ar[r] * ar[r] + ai[r] * ai[r]) * (cj * cj);
+        const bool diag = x == kq + 4 * r;
+        sig[r] = diag ? pw : 0.0;
+        itf[r] = diag ? 0.0 : pw;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sig[r] += __shfl_xor(sig[r], off, 64);
+            itf[r] += __shfl_xor(itf[r], off, 64);
+        }
+    }
+    if (x == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = kq + 4 * r;
+            if (k < K) {
+                const double sv = fail ? 0.0 : sig[r] / (itf[r] + a.sigma2);
+                if (a.sinr) a.sinr[b * K + k] = sv;
+                S.rate[k] = log2(1.0 + sv);
+            }
+        }
+    }
+}
+
 // The Gram partial of wave `wave` (antennas 64 wave .. 64 wave + 63) into part[wave].
 template <int MODE>   // 0: FP32, 1: FP16 x3, 2: BF16 x3
 __device__ __forceinline__ void bb_gram(BbShared& S, int wave, int lane, int hexp) {
@@ -256,53 +318,59 @@ __device__ __forceinline__ void bb_fetch(const BbDev& a, int64_t b, int tid, BbI
     if (tid < 3 * K) in.u = a.users[b * K * 3 + tid];
 }
 
-// 1. the users' channels of deployment b, from the inputs in registers:
-// rows i < K only (rows K .. 15 of H in LDS stay zero from the start of the
-// kernel); lanes m >= M compute antenna M - 1's terms (clamped inputs) and
-// write them to the pad column, which nothing reads, so H's columns M .. 255
-// stay zero as well.  Returns the lane's largest |Re h|, |Im h| (MIX).
+// 1. The users' channels of deployment b into registers, thread m holding
+// antenna m's column h[0 .. 15]: rows i < K (rows past K stay zero); lanes
+// m >= M compute antenna M - 1's terms from the clamped inputs (written to
+// the pad column of LDS, which nothing reads).  Returns the lane's largest
+// |Re h|, |Im h| (MIX).
 template <int MODE, bool RICIAN, bool WANT_H>
-__device__ __forceinline__ float bb_synth_rows(const BbDev& a, int64_t b, BbShared& S, const BbIn& in,
-                                               int K, int M, int tid) {
+__device__ __forceinline__ float bb_synth_rows(const BbDev& a, int64_t b, const BbShared& S, const BbIn& in,
+                                               int K, int M, int tid, float2 (&h)[kBbK]) {
     const bool live = tid < M;
-    const int col = live ? tid : kBbP - 1;
     float2* const Hb = WANT_H ? a.H + b * K * M + tid : nullptr;
     const float a_los = (float)a.w.a_los, a_nlos = (float)a.w.a_nlos;
     float mx = 0.0f;
 #pragma unroll
     for (int i = 0; i < kBbK; ++i) {
+        h[i] = make_float2(0.0f, 0.0f);
         if (i >= K) continue;   // uniform; the loop stays fully unrolled
         const TermF32 t = wave_term_f32(S.user[i][0] - in.ax, S.user[i][1] - in.ay, S.user[i][2] - in.az,
                                         a.w.inv_lam, (float)a.w.amp_c, (float)a.w.inv_dmin);
-        float2 h;
+        float2 v;
         if constexpr (RICIAN) {
             const float2 g = in.g[i];
-            h.x = t.amp * fmaf(a_los, t.c, a_nlos * g.x);
-            h.y = t.amp * fmaf(-a_los, t.s, a_nlos * g.y);
+            v.x = t.amp * fmaf(a_los, t.c, a_nlos * g.x);
+            v.y = t.amp * fmaf(-a_los, t.s, a_nlos * g.y);
         } else {
-            h.x = t.amp * t.c;
-            h.y = -t.amp * t.s;
+            v.x = t.amp * t.c;
+            v.y = -t.amp * t.s;
         }
         if constexpr (WANT_H) {
-            if (live) Hb[i * M] = h;
+            if (live) Hb[i * M] = v;
         }
-        if constexpr (MODE != 0) mx = fmaxf(mx, fmaxf(fabsf(h.x), fabsf(h.y)));
-        S.h[i][col] = h;
+        if constexpr (MODE != 0) mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        h[i] = v;
     }
     return mx;
 }
 
 template <int MODE>
-__device__ __forceinline__ void bb_deployment(const BbDev& a, int64_t b, BbShared& S, const BbIn& in,
-                                              int K, int M, int tid) {
-    float mx;
-    if (a.nlos) {
-        mx = a.H ? bb_synth_rows<MODE, true, true>(a, b, S, in, K, M, tid)
-                 : bb_synth_rows<MODE, true, false>(a, b, S, in, K, M, tid);
-    } else {
-        mx = a.H ? bb_synth_rows<MODE, false, true>(a, b, S, in, K, M, tid)
-                 : bb_synth_rows<MODE, false, false>(a, b, S, in, K, M, tid);
-    }
+__device__ __forceinline__ float bb_synth(const BbDev& a, int64_t b, const BbShared& S, const BbIn& in,
+                                          int K, int M, int tid, float2 (&h)[kBbK]) {
+    if (a.nlos)
+        return a.H ? bb_synth_rows<MODE, true, true>(a, b, S, in, K, M, tid, h)
+                   : bb_synth_rows<MODE, true, false>(a, b, S, in, K, M, tid, h);
+    return a.H ? bb_synth_rows<MODE, false, true>(a, b, S, in, K, M, tid, h)
+               : bb_synth_rows<MODE, false, false>(a, b, S, in, K, M, tid, h);
+}
+
+// The synthesised column to LDS (H, [K][M] padded to 16 x 256 with zeros) and
+// the wave's largest component to hmax (MIX).
+template <int MODE>
+__device__ __forceinline__ void bb_store_h(BbShared& S, const float2 (&h)[kBbK], float mx, int M, int tid) {
+    const int col = tid < M ? tid : kBbP - 1;
+#pragma unroll
+    for (int i = 0; i < kBbK; ++i) S.h[i][col] = h[i];
     if constexpr (MODE != 0) {
         for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
         if ((tid & 63) == 0) S.hmax[tid >> 6] = mx;
@@ -310,15 +378,27 @@ __device__ __forceinline__ void bb_deployment(const BbDev& a, int64_t b, BbShare
     (void)mx;
 }
 
-// 2 - 5: the Gram, the precoder and the epilogues of deployment b; the next
-// deployment's users (in.u, if `more`) go to LDS before the last barrier
+// One deployment b, with H(b) in LDS: its Gram, precoder and epilogues, while
+// the next deployment's channel (b + gridDim.x, if `more1`) is synthesised
+// into hn and the one after (if `more2`) is loaded into `in`.
+//   A  users of b + grid to LDS; the Gram partials of b
+//   S  wave 0: G, G^-1 and the scales of b;  waves 1 - 3: their columns of
+//      H(b + grid), then the loads of b + 2 grid
+//   X  wave 0: its columns of H(b + grid), its loads, the gains and SINR_k
+//      of b;  waves 1 - 3: X, W and p_m of b
+//   W  H(b + grid) to LDS; the scalar outputs of b
+// Four barriers per deployment.  The FP64 solve of b runs beside the
+// synthesis of b + grid instead of before it.
 template <int MODE>
-__device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, BbIn& in,
-                                        bool more, int K, int M, int tid) {
+__device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, BbIn& in,
+                                        float2 (&hn)[kBbK], bool more1, bool more2, int K, int M,
+                                        int tid) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const bool zf = a.precoder == DMIMO_ZF;
-    __syncthreads();
+    const int64_t bn = b + gridDim.x;
+    // A.  `in` holds the inputs of b + grid (loaded one deployment ago)
+    if (more1 && tid < 3 * K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     // MIX: largest |h| of the deployment scaled into [2^13, 2^14) for the
     // FP16 products (the Gram in FP16 mode, X = G^-1 H in both)
     int xexp = 0;
@@ -340,11 +420,13 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
     }
     __syncthreads();
 
+    // S.
+    float mxn = 0.0f;
     // 3. wave 0: the partials added in wave order in FP64 (upper triangle,
     //    mirrored: G exactly Hermitian), G^-1 (ZF), the scale of every row of W
     if (wave == 0) {
-        // the other waves wait for this one: it issues ahead of the waves of
-        // the other workgroups on its SIMD until the scales are out
+        // the solve is the deployment's longest dependent chain: this wave
+        // issues ahead of the other waves on its SIMD until the scales are out
         __builtin_amdgcn_s_setprio(3);
         const int r = lane >> 2, q = lane & 3;
         double2 v[4];
@@ -411,19 +493,32 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
         }
         __builtin_amdgcn_s_setprio(0);
     }
+    else if (more1) {
+        mxn = bb_synth<MODE>(a, bn, S, in, K, M, tid, hn);
+        if (more2) bb_fetch(a, bn + gridDim.x, tid, in, K, M);
+    }
     __syncthreads();
     const int fail = S.fail;
-    // The next deployment's inputs, loaded since the synthesis, are waited
-    // for here, before this deployment's stores: the loads and the stores
-    // share one counter, and a wait for a load behind pending stores would
-    // be a wait for the stores as well.
-    bb_settle(in);
 
-    // 4. X = G^-1 H (or H), W = c conj(X), p_m (FP32 sum of the 16 |w_km|^2);
-    //    wave w takes antenna tiles 4 w .. 4 w + 3 of 16 antennas.  A failed
-    //    deployment has c = 0, hence W = 0 (X is finite).
+    // X.
+    if (wave == 0) {
+        if (more1) {
+            mxn = bb_synth<MODE>(a, bn, S, in, K, M, tid, hn);
+            if (more2) bb_fetch(a, bn + gridDim.x, tid, in, K, M);
+        }
+        bb_gains(a, b, S, K, lane, fail, zf);
+    } else {
+        // the loads of b + 2 grid, issued during the solve, are waited for
+        // before this wave's stores: the loads and the stores share one
+        // counter, and a later wait for a load behind pending stores would be
+        // a wait for the stores as well
+        bb_settle(in);
+    }
+    // 4. waves 1 - 3: X = G^-1 H (or H), W = c conj(X), p_m (FP32 sum of
+    //    the 16 |w_km|^2); wave w takes the 16-antenna tiles w - 1, w + 2,
+    //    w + 5, ...  A failed deployment has c = 0, hence W = 0 (X is finite).
     double l21_part = 0.0;
-    {
+    if (wave != 0) {
         const int g = lane >> 4, col = lane & 15;    // operand lane (g, i) / output lane (g, c)
         float2* const Wt = a.W ? a.W + (b * K + 4 * g) * M + col : nullptr;
         double* const Pt = a.p_ant ? a.p_ant + b * M + col : nullptr;
@@ -467,9 +562,8 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
             float cs[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) cs[r] = ldexpf((float)S.c[4 * g + r], -xs);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int m0 = 64 * wave + 16 * t;
+            for (int tt = wave - 1; tt < 16; tt += 3) {
+                const int m0 = 16 * tt;
                 if (m0 >= M) break;
                 f32x4 xr = {0.f, 0.f, 0.f, 0.f}, xi = {0.f, 0.f, 0.f, 0.f};
                 if constexpr (!ZF) {
@@ -507,16 +601,16 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
                     xi = mfma16<false>(aih, bl, xi);
                 }
                 // lane (g, c) holds X[4 g + r][m0 + c]
-                const bool in = m0 + col < M;
+                const bool live = m0 + col < M;
                 float pm = 0.0f;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float2 wv = make_float2(cs[r] * xr[r], -cs[r] * xi[r]);
-                    if (Wt && in && 4 * g + r < K) Wt[r * M + m0] = wv;
+                    if (Wt && live && 4 * g + r < K) Wt[r * M + m0] = wv;
                     pm = fmaf(wv.x, wv.x, fmaf(wv.y, wv.y, pm));
                 }
                 pm = sum_rows4(pm);
-                if (g == 0 && in) {
+                if (g == 0 && live) {
                     if (Pt) Pt[m0] = (double)pm;
                     l21_part += (double)__builtin_amdgcn_sqrtf(pm);   // hardware sqrt, within an ulp
                 }
@@ -530,39 +624,9 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
     for (int off = 8; off > 0; off >>= 1) l21_part += __shfl_xor(l21_part, off, 64);
     if (lane == 0) S.red[wave] = l21_part;
 
-    // 5. gains A = G G^-1 D_c (ZF) or G D_c (MR), FP64, thread (k, j) on
-    //    A[k][j]; SINR_k = |A_kk|^2 / (sum_{j != k} |A_kj|^2 + sigma^2)
-    {
-        const int k = tid >> 4, j = tid & 15;
-        double2 acc = make_double2(0.0, 0.0);
-        if (zf) {
-#pragma unroll
-            for (int l = 0; l < kBbK; ++l) {
-                const double2 x = S.g0[k][l], y = S.gi[l][j];
-                acc.x = fma(x.x, y.x, fma(-x.y, y.y, acc.x));
-                acc.y = fma(x.x, y.y, fma(x.y, y.x, acc.y));
-            }
-        } else {
-            acc = S.g0[k][j];
-        }
-        const double cj = S.c[j];
-        acc.x *= cj;
-        acc.y *= cj;
-        const double pw = acc.x * acc.x + acc.y * acc.y;
-        double sig = j == k ? pw : 0.0, itf = j == k ? 0.0 : pw;
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            sig += __shfl_xor(sig, off, 64);
-            itf += __shfl_xor(itf, off, 64);
-        }
-        if (j == 0 && k < K) {
-            const double s = fail ? 0.0 : sig / (itf + a.sigma2);
-            if (a.sinr) a.sinr[b * K + k] = s;
-            S.rate[k] = log2(1.0 + s);
-        }
-    }
-    if (more && tid < 3 * K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     __syncthreads();
+    // W.
+    if (more1) bb_store_h<MODE>(S, hn, mxn, M, tid);
     if (tid == 0) {
         double rs = 0.0;
 #pragma unroll
@@ -571,35 +635,42 @@ __device__ __forceinline__ void bb_rest(const BbDev& a, int64_t b, BbShared& S, 
         if (a.l21) a.l21[b] = fail ? 0.0 : ((S.red[0] + S.red[1]) + S.red[2]) + S.red[3];
         if (a.info) a.info[b] = fail;
     }
+    __syncthreads();
 }
 
-// Persistent: workgroup w takes deployments w, w + gridDim.x, ...; the next
-// deployment's inputs are loaded into registers while the current one runs.
-// Four barriers per deployment: H in LDS, the Gram partials, G^-1 and the
-// scales, the epilogues (which also publish the next deployment's users).
+// Persistent: workgroup w takes deployments w, w + gridDim.x, ...
 template <int MODE>
 __global__ __launch_bounds__(kBbThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void beamform_batched_kernel(BbDev a) {
     __shared__ BbShared S;
     const int tid = threadIdx.x;
     BbIn in;
+    float2 hn[kBbK];
     if (tid < kBbK) S.cpaper[tid] = a.cpaper[tid];
+    // H's columns M .. 255 stay zero for the whole launch (lanes m >= M
+    // write only the pad column)
 #pragma unroll
     for (int i = 0; i < kBbK; ++i) S.h[i][tid] = make_float2(0.0f, 0.0f);
-    bb_fetch(a, blockIdx.x, tid, in, a.K, a.M);   // the grid has at most B workgroups
+    // the first deployment's channel (the grid has at most B workgroups)
+    const int64_t b0 = blockIdx.x;
+    bb_fetch(a, b0, tid, in, a.K, a.M);
     bb_settle(in);
     if (tid < 3 * a.K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     __syncthreads();
-    for (int64_t b = blockIdx.x; b < a.B; b += gridDim.x) {
+    const float mx0 = bb_synth<MODE>(a, b0, S, in, a.K, a.M, tid, hn);
+    if (b0 + gridDim.x < a.B) {
+        bb_fetch(a, b0 + gridDim.x, tid, in, a.K, a.M);
+        bb_settle(in);
+    }
+    bb_store_h<MODE>(S, hn, mx0, a.M, tid);
+    __syncthreads();
+    for (int64_t b = b0; b < a.B; b += gridDim.x) {
         // K, M and the thread index made opaque in every iteration: what is
         // derived from them is formed where it is used instead of held in
         // registers across the loop
         int K = a.K, M = a.M, t = tid;
         asm volatile("" : "+s"(K), "+s"(M), "+v"(t));
-        bb_deployment<MODE>(a, b, S, in, K, M, t);
-        const bool more = b + gridDim.x < a.B;
-        if (more) bb_fetch(a, b + gridDim.x, t, in, K, M);   // in flight meanwhile
-        bb_rest<MODE>(a, b, S, in, more, K, M, t);
+        bb_step<MODE>(a, b, S, in, hn, b + gridDim.x < a.B, b + 2 * (int64_t)gridDim.x < a.B, K, M, t);
     }
 }
 
