@@ -618,14 +618,17 @@ def room_phase(args, D, WL, torch):
     ms_n = run_steps(ra, "f32", w, D, params, ap, ap0, users, gpts, H,
                      nstreams=args.room_streams)[0] if args.room_streams > 1 else ms_one
     ms_mix, launch_mix, maps_mix, _ = run_steps(ra, "f16x3", w, D, params, ap, ap0, users, gpts, H)
-    terms = 3 * K * M + 2 * N * M
+    # distinct channel terms per step: the users' K M and the map's N M; the
+    # map term feeds both precoders' streams in one contraction
+    terms = K * M + N * M
     khash = _src_hash(POWERMAP_SOURCES)
-    slots = alg_slots_per_term(K)
+    slots = alg_slots_per_term(2 * K)
     res = {
         "workload": f"room: M={M} APs jittered 8x8 ceiling grid 20x20x4 m, K={K} users, 3.5 GHz, "
                     f"MR+ZF at 1 W, noise -90 dBm, {w.grid.nx}x{w.grid.ny} power+SINR+best-stream "
-                    "maps at z=1.2 m (both maps in one launch)",
+                    "maps at z=1.2 m (both maps in one launch: one contraction of the 2K streams)",
         "terms_per_step": terms,
+        "terms_counted": "distinct channel terms: K M of the users' channels + N M of the grid",
         "f32": {"ms_per_step_one_stream": round(ms_one, 5),
                 "value_one_stream": round(terms / (ms_one * 1e-3) / 1e9, 3),
                 "streams": args.room_streams, "ms_per_step": round(ms_n, 5),
@@ -634,10 +637,18 @@ def room_phase(args, D, WL, torch):
         "f16x3": {"ms_per_step_one_stream": round(ms_mix, 5),
                   "value_one_stream": round(terms / (ms_mix * 1e-3) / 1e9, 3),
                   "maps_launch_ms": round(launch_mix, 5)},
-        "roofline": {"bound": "alu", "kernel": "powermap_mfma_kernel<1, 4, 8>, grid 512 x 2",
+        "roofline": {"bound": "alu",
+                     "kernel": "powermap_mfma_kernel<2, 2, 8>: MR and ZF, 16 streams, one grid",
                      "alg_slots_per_term": slots,
-                     "frac": round(slots * 2 * N * M / (launch * 1e-3) / VALU_PEAK_SLOTS, 4),
-                     "mfma_f32_frac": round(8 * K * 2 * N * M / (launch * 1e-3) / MFMA_F32_PEAK, 4),
+                     "frac": round(slots * N * M / (launch * 1e-3) / VALU_PEAK_SLOTS, 4),
+                     "mfma_f32_frac": round(8 * 2 * K * N * M / (launch * 1e-3) / MFMA_F32_PEAK, 4),
+                     # FP32 MFMA does not co-issue with the VALU: the floor is
+                     # the synthesis at the slot peak plus the contraction at
+                     # the FP32 matrix-core peak
+                     "floor_ms": round((slots * N * M / VALU_PEAK_SLOTS
+                                        + 8 * 2 * K * N * M / MFMA_F32_PEAK) * 1e3, 5),
+                     "frac_of_floor": round((slots * N * M / VALU_PEAK_SLOTS
+                                             + 8 * 2 * K * N * M / MFMA_F32_PEAK) / (launch * 1e-3), 4),
                      "launch_ms": round(launch, 5),
                      "traffic": load_traffic(khash, ROOM_TRAFFIC_FILE), "source_hash": khash},
     }

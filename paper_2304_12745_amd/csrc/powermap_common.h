@@ -13,7 +13,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 struct PmMapDev {
     PointsDev P;
     int M;
-    int K;
+    int K;               // streams of the contraction
+    int G;               // streams per output map: map g takes streams g G .. g G + G - 1
     double inv_lam;      // 1 / lambda: positions are converted to wavelengths
     float amp_rev;       // 1 / (4 pi): amplitude = amp_rev / d_rev
     float inv_dmin_rev;  // lambda / d_min
@@ -55,6 +56,7 @@ inline PmMapDev make_map_dev(const PowermapArgs& a) {
     d.P = a.P;
     d.M = a.M;
     d.K = a.K;
+    d.G = a.K;
     d.inv_lam = a.w.inv_lam;
     d.amp_rev = (float)(1.0 / (4.0 * kPi));
     d.inv_dmin_rev = (float)(a.w.inv_dmin / a.w.inv_lam);
@@ -259,27 +261,33 @@ __device__ __forceinline__ void map_epilogue(const PmMapDev& a, const f32x4 (&ac
         }
         return;
     }
-    float y = 0.0f, pb = -1.0f;
-    int kb = 0;
-    for (int k = 0; k < K; ++k) {
-        const float p = row[k];
-        y += p;
-        if (p > pb) {
-            pb = p;
-            kb = k;
+    // one output map per group of G streams (G = K: one map)
+    const int G = a.G;
+    const int64_t N = a.P.n;
+    for (int g0 = 0, o = 0; g0 < K; g0 += G, ++o) {
+        const float* rg = row + g0;
+        float y = 0.0f, pb = -1.0f;
+        int kb = 0;
+        for (int k = 0; k < G; ++k) {
+            const float p = rg[k];
+            y += p;
+            if (p > pb) {
+                pb = p;
+                kb = k;
+            }
         }
-    }
-    a.power[n] = y;
-    if (a.sinr) {
-        float intf = 0.0f;
-        for (int k = 0; k < K; ++k)
-            if (k != kb) intf += row[k];
-        a.sinr[n] = pb / (intf + a.sigma2);
-    }
-    if (a.best_k) a.best_k[n] = kb;
-    if (a.per_stream) {
-        float* ps = a.per_stream + n * K;
-        for (int k = 0; k < K; ++k) ps[k] = row[k];
+        a.power[o * N + n] = y;
+        if (a.sinr) {
+            float intf = 0.0f;
+            for (int k = 0; k < G; ++k)
+                if (k != kb) intf += rg[k];
+            a.sinr[o * N + n] = pb / (intf + a.sigma2);
+        }
+        if (a.best_k) a.best_k[o * N + n] = kb;
+        if (a.per_stream) {
+            float* ps = a.per_stream + (o * N + n) * G;
+            for (int k = 0; k < G; ++k) ps[k] = rg[k];
+        }
     }
 }
 

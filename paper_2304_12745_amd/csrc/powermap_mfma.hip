@@ -85,7 +85,23 @@ dmimo_status launch_x3(const PmMapDev& d, int maps, hipStream_t s) {
 
 }  // namespace
 
+// Several maps of K <= 8 streams each (8 < maps K <= 32) run as one contraction
+// of maps K streams (W [maps][K][M] is [maps K][M]), whose epilogue splits the
+// streams into the maps: every channel term is synthesised once for all maps.
+static bool joint_maps(const PowermapArgs& a) { return a.maps > 1 && a.K <= 8 && a.maps * a.K > 8 && a.maps * a.K <= 32; }
+
+static PmMapDev joint_dev(const PowermapArgs& a) {
+    PmMapDev d = make_map_dev(a);
+    d.K = a.maps * a.K;
+    d.G = a.K;
+    return d;
+}
+
 dmimo_status launch_powermap_f32_mfma(const PowermapArgs& a, hipStream_t s) {
+    if (joint_maps(a)) {
+        const PmMapDev d = joint_dev(a);
+        return d.K <= 16 ? launch_f32<2>(d, 1, s) : launch_f32<4>(d, 1, s);
+    }
     const PmMapDev d = make_map_dev(a);
     if (a.K <= 8) return launch_f32<1>(d, a.maps, s);
     if (a.K <= 16) return launch_f32<2>(d, a.maps, s);
@@ -93,6 +109,12 @@ dmimo_status launch_powermap_f32_mfma(const PowermapArgs& a, hipStream_t s) {
 }
 
 dmimo_status launch_powermap_mfma(const PowermapArgs& a, hipStream_t s) {
+    if (joint_maps(a)) {
+        const PmMapDev d = joint_dev(a);
+        if (a.prec == DMIMO_MIX_BF16X3)
+            return d.K <= 16 ? launch_x3w<2, true>(d, 1, s) : launch_x3w<4, true>(d, 1, s);
+        return d.K <= 16 ? launch_x3w<2, false>(d, 1, s) : launch_x3w<4, false>(d, 1, s);
+    }
     const PmMapDev d = make_map_dev(a);
     if (a.prec == DMIMO_MIX_BF16X3) {
         if (a.K <= 8) return launch_x3<1, true>(d, a.maps, s);

@@ -294,6 +294,7 @@ int ServerImpl::admit_one(Query* q) {
     m.P = q->P;
     m.M = d.M;
     m.K = K;
+    m.G = K;
     m.inv_lam = d.w.inv_lam;
     m.amp_rev = (float)(1.0 / (4.0 * kPi));
     m.inv_dmin_rev = (float)(d.w.inv_dmin / d.w.inv_lam);

@@ -840,13 +840,34 @@ def test_powermap_hall_sampled(D, prec):
     check_db(sinr[rows].ravel(), s_ref, MAP_TOL[prec], what="sinr rows")
 
 
+def _same_maps_joint(prec, batch, one):
+    # a joint launch (maps of K <= 8 streams with 8 < maps K <= 32, one
+    # contraction of all their streams) against the single map: per-stream
+    # powers, power and SINR within the precision's rounding, the best stream
+    # equal wherever the two largest streams are not within that rounding
+    import torch
+    rtol = 2e-5 if prec == "f32" else 2e-4
+    ps, po = batch.per_stream.double(), one.per_stream.double()
+    scale = po.amax(dim=-1, keepdim=True)
+    assert torch.all((ps - po).abs() <= rtol * scale)
+    for a, b in ((batch.power, one.power), (batch.sinr, one.sinr)):
+        assert torch.allclose(a.double(), b.double(), rtol=4 * rtol, atol=0.0)
+    top2 = po.topk(2, dim=-1).values
+    clear = (top2[..., 0] - top2[..., 1]) > 4 * rtol * top2[..., 0]
+    assert torch.equal(batch.best_k[clear], one.best_k[clear])
+
+
 # several precoders over the same points in one launch (map p on grid row p of
 # the kernel) equal one call per precoder bit for bit, in every kernel family:
 # FP32 VALU (K <= 2), FP32 MFMA (K <= 8, 16, 32), FP64, FP16x3, BF16x3; a
-# ragged grid (41 x 29) and a ragged antenna chunk (M = 70)
+# ragged grid (41 x 29) and a ragged antenna chunk (M = 70).  Maps of K <= 8
+# streams with 8 < maps K <= 32 in FP32 or the split modes run as one joint
+# contraction of all their streams (each term synthesised once for all maps):
+# there the maps equal the single calls to the rounding of the products
 @pytest.mark.parametrize("prec,K,kind", [("f32", 2, "grid"), ("f32", 8, "grid"), ("f32", 12, "grid"),
                                          ("f32", 32, "grid"), ("f64", 8, "grid"), ("f16x3", 8, "grid"),
-                                         ("bf16x3", 20, "grid"), ("f32", 8, "list"), ("f64", 3, "list")])
+                                         ("bf16x3", 20, "grid"), ("f32", 8, "list"), ("f64", 3, "list"),
+                                         ("bf16x3", 5, "grid"), ("f32", 3, "list")])
 def test_powermap_batch_equals_single_maps(D, prec, K, kind):
     import torch
     say(f"powermap batch of 3 precoders, K={K}, {prec}, {kind} points")
@@ -865,29 +886,49 @@ def test_powermap_batch_equals_single_maps(D, prec, K, kind):
     apd = dev(aps)
     r = D.powermap_batch(params, apd, W, pts, 1e-9, prec, want_per_stream=True)
     assert tuple(r.power.shape) == (P, n)
+    joint = prec != "f64" and K > 2 and K <= 8 and 8 < P * K <= 32
     for p in range(P):
         one = D.powermap(params, apd, W[p].contiguous(), pts, 1e-9, prec, want_per_stream=True)
+        if joint:
+            class Map:
+                pass
+            b = Map()
+            b.power, b.sinr, b.best_k, b.per_stream = r.power[p], r.sinr[p], r.best_k[p], r.per_stream[p]
+            _same_maps_joint(prec, b, one)
+            continue
         for a, b in ((r.power[p], one.power), (r.sinr[p], one.sinr), (r.best_k[p], one.best_k),
                      (r.per_stream[p], one.per_stream)):
             assert torch.equal(a, b), p
 
 
 # the bench step's two maps (MR and ZF of the room's 8 users, 512 x 512 grid)
-# in one launch equal the two single calls bit for bit
-def test_powermap_batch_room_step_maps(D):
-    import torch
-    say("powermap batch: room MR + ZF maps, 512 x 512")
+# in one launch (one joint contraction of the 16 streams) equal the two single
+# calls to the rounding of the products, and the oracle on sampled rows
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_powermap_batch_room_step_maps(D, prec):
+    say(f"powermap batch: room MR + ZF maps, 512 x 512, {prec}")
     w = WL.room_workload()
     aps = w.ap_xyz[0]
     Hu = O.los_channel(w.user_xyz[0], aps, w.freq_hz)
     Wst = np.stack([O.mr_precoder(Hu[None], 1.0)[0], O.zf_precoder(Hu[None], None, w.sigma2, 1.0)[0][0]])
     W = dev(c64(Wst))
     params, apd, pts = D.channel_params(w.freq_hz), dev(aps), D.grid_points(w.grid)
-    r = D.powermap_batch(params, apd, W, pts, w.sigma2, "f32")
+    r = D.powermap_batch(params, apd, W, pts, w.sigma2, prec, want_per_stream=True)
+    rows = [0, 255, 511]
+    Hg = O.los_channel(grid_pts(w.grid).reshape(512, 512, 3)[rows].reshape(-1, 3), aps, w.freq_hz)
     for p in range(2):
-        one = D.powermap(params, apd, W[p].contiguous(), pts, w.sigma2, "f32")
-        assert torch.equal(r.power[p], one.power) and torch.equal(r.sinr[p], one.sinr)
-        assert torch.equal(r.best_k[p], one.best_k)
+        one = D.powermap(params, apd, W[p].contiguous(), pts, w.sigma2, prec, want_per_stream=True)
+
+        class Map:
+            pass
+        b = Map()
+        b.power, b.sinr, b.best_k, b.per_stream = r.power[p], r.sinr[p], r.best_k[p], r.per_stream[p]
+        _same_maps_joint(prec, b, one)
+        Wc = c64(Wst[p]).astype(np.complex128)
+        check_db(host(r.power[p]).reshape(512, 512)[rows].ravel(), O.power_map(Hg, Wc),
+                 MAP_TOL[prec], what=f"power rows, map {p}")
+        check_db(host(r.sinr[p]).reshape(512, 512)[rows].ravel(), O.sinr_map(Hg, Wc, w.sigma2)[0],
+                 MAP_TOL[prec], what=f"sinr rows, map {p}")
 
 
 def test_room_steps_on_two_streams_equal_one_stream(D):
