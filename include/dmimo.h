@@ -285,7 +285,11 @@ dmimo_status dmimo_powermap(const dmimo_channel_params* params, int32_t M,
 /* The maps of `maps` precoders of one deployment over the same points in one
  * launch, as Sec. VI compares the coverage of several precoders (MR, ZF, the
  * PA-aware one) on one room: map p is dmimo_powermap of W[p].  Saves the
- * per-launch ramp and drain of every map after the first.
+ * per-launch ramp and drain of every map after the first.  With K <= 8 and
+ * 8 < maps K <= 32 in DMIMO_F32 or a MIX mode (K >= 3 for DMIMO_F32), the maps
+ * are one contraction of all maps K streams (each channel term synthesised
+ * once), whose results equal the single calls to the rounding of the products
+ * rather than bit for bit; otherwise they are bitwise the single calls.
  *   maps    0 <= maps <= 65535 (0: nothing to do).
  *   W       device [maps][K][M] (complex128 for DMIMO_F64, else complex64).
  *   power, sinr, best_k  device [maps][N]; per_stream [maps][N][K].
