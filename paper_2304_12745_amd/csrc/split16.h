@@ -24,10 +24,12 @@ __device__ __forceinline__ uint32_t pack_hi(float x0, float x1, float& r0, float
         r1 = x1 - __uint_as_float(b1 << 16);
         return b0 | (b1 << 16);
     } else {
-        const auto h = __builtin_amdgcn_cvt_pkrtz(x0, x1);
-        r0 = x0 - (float)h[0];
-        r1 = x1 - (float)h[1];
-        return __builtin_bit_cast(uint32_t, h);
+        const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0, x1));
+        // x - hi, exact, by one mixed-precision FMA each that reads its FP16
+        // half in place (instead of a conversion back to FP32 and a subtraction)
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(h), "v"(x0));
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r1) : "v"(h), "v"(x1));
+        return h;
     }
 }
 
