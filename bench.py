@@ -112,6 +112,7 @@ POWERMAP_SOURCES = ["paper_2304_12745_amd/csrc/powermap.hip",
                     "paper_2304_12745_amd/csrc/dmimo_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_hall_traffic.json")
 ROOM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_traffic.json")
+ROOM_F16_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powermap_room_f16x3_traffic.json")
 
 
 def load_traffic(kernel_hash: str, path: str = None):
@@ -652,6 +653,20 @@ def room_phase(args, D, WL, torch):
                      "launch_ms": round(launch, 5),
                      "traffic": load_traffic(khash, ROOM_TRAFFIC_FILE), "source_hash": khash},
     }
+    # the split FP16 contraction co-issues with the synthesis: its floor is
+    # the larger of the VALU time and the FP16 matrix-core time
+    sl16 = alg_slots_per_term(2 * K, "f16x3")
+    t_v, t_m = sl16 * N * M / VALU_PEAK_SLOTS, mfma_flops_per_term(2 * K, "f16x3") * N * M / MFMA_F16_PEAK
+    res["roofline_f16x3"] = {
+        "bound": "alu",
+        "kernel": "powermap_x3w_kernel<2, 2, false, 8>: MR and ZF, 16 streams, one grid, FP16 hi/lo x3",
+        "alg_slots_per_term": sl16,
+        "frac": round(sl16 * N * M / (launch_mix * 1e-3) / VALU_PEAK_SLOTS, 4),
+        "mfma_f16_frac": round(t_m / (launch_mix * 1e-3), 4),
+        "floor_ms": round(max(t_v, t_m) * 1e3, 5),
+        "frac_of_floor": round(max(t_v, t_m) / (launch_mix * 1e-3), 4),
+        "launch_ms": round(launch_mix, 5),
+        "traffic": load_traffic(khash, ROOM_F16_TRAFFIC_FILE), "source_hash": khash}
     res["err_db"] = room_errors(w, maps, maps_mix)
     return res
 
