@@ -519,8 +519,10 @@ __device__ __forceinline__ void map_x3_wg(const PmMapDev& a, int64_t wg_first, c
 //    feeds PT tiles, and a workgroup stages one table per chunk for
 //    16 PT WAVES points;
 //  * the weights of the next chunk are loaded into registers while the
-//    current chunk runs, and split into the other of two LDS buffers after
-//    it: one barrier per chunk;
+//    current chunk runs, and split into the other of two LDS buffers during
+//    it;
+//  * the two waves of a SIMD run half a step apart, so that the synthesis of
+//    one overlaps the products of the other (four barriers per chunk);
 //  * FP16 weights are scaled per chunk and stream: the eight threads that
 //    stage one stream of a chunk are eight consecutive lanes, which find the
 //    stream's largest magnitude among themselves (no cross-wave step);
@@ -709,104 +711,51 @@ __device__ __forceinline__ void x3w_positions(const X3wBuf<NT>& T, int s, int gr
     }
 }
 
-#ifdef DMIMO_X3W_PIPE
-// One chunk (two steps of 32 antennas; slots past the last antenna carry zero
-// weights) for the PT tiles of a wave.  The (step, tile) blocks run in order;
-// the terms of the next block are synthesised in program order before the
-// products of the current one, so that the VALU work of one overlaps the
-// matrix-core work of the other.  The B operands of a step are loaded once
-// and serve its PT tiles.
-template <int NT, int PT, bool BF16, bool ROW, bool GUARD>
-__device__ __forceinline__ void x3w_chunk(const X3wBuf<NT>& T, int grp, int lane, float amp_s,
-                                          float inv_dmin_rev, const double (&px)[PT],
-                                          const double (&py)[PT], const double (&pz)[PT],
-                                          f32x4 (&acc)[PT][NT]) {
-    double xs[8], ys[8], zs[8];
-    u32x4 Ac[4], An[4];
-    u32x4 B[NT][4];
-    x3w_positions<NT, ROW>(T, 0, grp, xs, ys, zs);
-    x3w_synth<BF16, ROW, GUARD>(px[0], py[0], pz[0], xs, ys, zs, amp_s, inv_dmin_rev, Ac[0], Ac[1],
-                                Ac[2], Ac[3]);
+// The terms of one step (32 antennas, positions xs, ys, zs of this lane's 8)
+// for the PT tiles of a wave, as split A operands.
+template <int PT, bool BF16, bool ROW, bool GUARD>
+__device__ __forceinline__ void x3w_synth_step(const double (&xs)[8], const double (&ys)[8],
+                                               const double (&zs)[8], float amp_s,
+                                               float inv_dmin_rev, const double (&px)[PT],
+                                               const double (&py)[PT], const double (&pz)[PT],
+                                               u32x4 (&A)[PT][4]) {
 #pragma unroll
-    for (int u = 0; u < 2 * PT; ++u) {
-        const int s = u / PT, t = u % PT;
-        if (u + 1 < 2 * PT) {
-            const int s1 = (u + 1) / PT, t1 = (u + 1) % PT;
-            if (s1 != s) x3w_positions<NT, ROW>(T, s1, grp, xs, ys, zs);
-            x3w_synth<BF16, ROW, GUARD>(px[t1], py[t1], pz[t1], xs, ys, zs, amp_s, inv_dmin_rev,
-                                        An[0], An[1], An[2], An[3]);
-        }
-        const int sl = x3w_slot(lane, s);
+    for (int t = 0; t < PT; ++t)
+        x3w_synth<BF16, ROW, GUARD>(px[t], py[t], pz[t], xs, ys, zs, amp_s, inv_dmin_rev, A[t][0],
+                                    A[t][1], A[t][2], A[t][3]);
+}
+
+// The products of step s for the PT tiles of a wave (slots past the last
+// antenna carry zero weights); each B operand is loaded once for the PT tiles.
+template <int NT, int PT, bool BF16>
+__device__ __forceinline__ void x3w_mma_step(const X3wBuf<NT>& T, int s, int lane,
+                                             const u32x4 (&A)[PT][4], f32x4 (&acc)[PT][NT]) {
+    const int sl = x3w_slot(lane, s);
 #pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            if (t == 0) {
+    for (int q = 0; q < NT; ++q) {
+        const u32x4 b1h = T.b[s][q][0][sl], b1l = T.b[s][q][1][sl];
+        const u32x4 b2h = T.b[s][q][2][sl], b2l = T.b[s][q][3][sl];
 #pragma unroll
-                for (int w = 0; w < 4; ++w) B[q][w] = T.b[s][q][w][sl];
-            }
+        for (int t = 0; t < PT; ++t) {
             f32x4 c = acc[t][q];
-            c = mfma16<BF16>(Ac[0], B[q][0], c);
-            c = mfma16<BF16>(Ac[1], B[q][0], c);
-            c = mfma16<BF16>(Ac[0], B[q][1], c);
-            c = mfma16<BF16>(Ac[2], B[q][2], c);
-            c = mfma16<BF16>(Ac[3], B[q][2], c);
-            c = mfma16<BF16>(Ac[2], B[q][3], c);
+            c = mfma16<BF16>(A[t][0], b1h, c);
+            c = mfma16<BF16>(A[t][1], b1h, c);
+            c = mfma16<BF16>(A[t][0], b1l, c);
+            c = mfma16<BF16>(A[t][2], b2h, c);
+            c = mfma16<BF16>(A[t][3], b2h, c);
+            c = mfma16<BF16>(A[t][2], b2l, c);
             acc[t][q] = c;
         }
-#pragma unroll
-        for (int w = 0; w < 4; ++w) Ac[w] = An[w];
-    }
-#ifdef DMIMO_X3W_SCHED
-    // schedule: the first block's synthesis, then each block's products one
-    // at a time between groups of the next block's VALU instructions
-    __builtin_amdgcn_sched_group_barrier(0x002, DMIMO_X3W_SCHED_HEAD, 0);
-#pragma unroll
-    for (int i = 0; i < (2 * PT - 1) * 6 * NT; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, DMIMO_X3W_SCHED, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, 6 * NT, 0);
-#endif
-}
-
-#else
-// One chunk (two steps of 32 antennas; slots past the last antenna carry zero
-// weights) for the PT tiles of a wave: per step, the terms of all PT tiles,
-// then the products, with each B operand loaded once for the PT tiles.
-template <int NT, int PT, bool BF16, bool ROW, bool GUARD>
-__device__ __forceinline__ void x3w_chunk(const X3wBuf<NT>& T, int grp, int lane, float amp_s,
-                                          float inv_dmin_rev, const double (&px)[PT],
-                                          const double (&py)[PT], const double (&pz)[PT],
-                                          f32x4 (&acc)[PT][NT]) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        double xs[8], ys[8], zs[8];
-        x3w_positions<NT, ROW>(T, s, grp, xs, ys, zs);
-        u32x4 A[PT][4];
-#pragma unroll
-        for (int t = 0; t < PT; ++t)
-            x3w_synth<BF16, ROW, GUARD>(px[t], py[t], pz[t], xs, ys, zs, amp_s, inv_dmin_rev,
-                                        A[t][0], A[t][1], A[t][2], A[t][3]);
-        const int sl = x3w_slot(lane, s);
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            const u32x4 b1h = T.b[s][q][0][sl], b1l = T.b[s][q][1][sl];
-            const u32x4 b2h = T.b[s][q][2][sl], b2l = T.b[s][q][3][sl];
-#pragma unroll
-            for (int t = 0; t < PT; ++t) {
-                f32x4 c = acc[t][q];
-                c = mfma16<BF16>(A[t][0], b1h, c);
-                c = mfma16<BF16>(A[t][1], b1h, c);
-                c = mfma16<BF16>(A[t][0], b1l, c);
-                c = mfma16<BF16>(A[t][2], b2h, c);
-                c = mfma16<BF16>(A[t][3], b2h, c);
-                c = mfma16<BF16>(A[t][2], b2l, c);
-                acc[t][q] = c;
-            }
-        }
     }
 }
 
-#endif
+// A workgroup barrier that the compiler schedules nothing across, so that the
+// VALU phase and the matrix-core phase of a wave stay on their sides of it.
+__device__ __forceinline__ void x3w_phase_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 // One workgroup: points wg_first .. wg_first + 16 PT WAVES - 1.  smem: at
 // least x3w_lds_bytes<NT, PT, WAVES>() bytes, 16-byte aligned.
@@ -860,6 +809,19 @@ __device__ __forceinline__ void map_x3w_wg(const PmMapDev& a, int64_t wg_first, 
     st.wexp = 0;
     st.set = false;
     const int nch = (M + kChunk - 1) / kChunk;
+    // Waves w and w + 4 share a SIMD.  The second half of the workgroup runs
+    // every step one phase behind the first: while one wave synthesises the
+    // terms of a step on the VALU, the other runs the products of its last
+    // step on the matrix cores, and a barrier ends each phase.  A products
+    // phase also reads the antenna positions of the wave's next step, so that
+    // its synthesis phase starts without waiting for LDS.  The weights of chunk
+    // c + 1 are staged in the products phase of chunk c's first step: after the
+    // last read of their buffer (chunk c - 1, ended by the barrier that opens
+    // that phase for either half) and at least one barrier before the first
+    // read of chunk c + 1 (the positions, in the products phase of chunk c's
+    // second step).
+    static_assert(WAVES == 8, "map_x3w_wg: two waves per SIMD");
+    const bool late = wave >= 4;
     // the chunk loop, compiled once for grid-row workgroups and once for the
     // others (one copy of the accumulators per loop)
     auto run = [&](auto row_tag) {
@@ -868,52 +830,66 @@ __device__ __forceinline__ void map_x3w_wg(const PmMapDev& a, int64_t wg_first, 
         x3w_write<NT, BF16>(a, buf[0], 0, tid, st, ROW, ry, rz, far_c);
         if (nch > 1) x3w_load<NT>(a, kChunk, tid, st);
         __syncthreads();
+        double xs[8], ys[8], zs[8];
+        x3w_positions<NT, ROW>(buf[0], 0, grp, xs, ys, zs);
+        bool guard = !ROW || !buf[0].far;
+        if (late) x3w_phase_barrier();
         for (int c = 0; c < nch; ++c) {
             const X3wBuf<NT>& T = buf[c & 1];
-            if constexpr (!BF16) {
-                // the column's stream changed its scale: rescale its sums exactly
-                int ne[NT / 2];
-                bool moved = false;
 #pragma unroll
-                for (int b = 0; b < NT / 2; ++b) {
-                    ne[b] = T.wexp[16 * b + (lane & 15)];
-                    moved = moved || (c > 0 && ne[b] != cur[b]);
-                }
-                if (__builtin_expect(__any(moved), 0)) {
+            for (int s = 0; s < 2; ++s) {
+                u32x4 A[PT][4];
+                if (guard)
+                    x3w_synth_step<PT, BF16, ROW, true>(xs, ys, zs, amp_s, a.inv_dmin_rev, px, py,
+                                                        pz, A);
+                else
+                    x3w_synth_step<PT, BF16, ROW, false>(xs, ys, zs, amp_s, a.inv_dmin_rev, px, py,
+                                                         pz, A);
+                x3w_phase_barrier();
+                if (!BF16 && s == 0) {
+                    // the column's stream changed its scale: rescale its sums exactly
+                    int ne[NT / 2];
+                    bool moved = false;
 #pragma unroll
                     for (int b = 0; b < NT / 2; ++b) {
-                        const int d = c > 0 ? ne[b] - cur[b] : 0;
-#pragma unroll
-                        for (int t = 0; t < PT; ++t)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                acc[t][2 * b][r] = ldexpf(acc[t][2 * b][r], d);
-                                acc[t][2 * b + 1][r] = ldexpf(acc[t][2 * b + 1][r], d);
-                            }
+                        ne[b] = T.wexp[16 * b + (lane & 15)];
+                        moved = moved || (c > 0 && ne[b] != cur[b]);
                     }
-                }
+                    if (__builtin_expect(__any(moved), 0)) {
 #pragma unroll
-                for (int b = 0; b < NT / 2; ++b) cur[b] = ne[b];
+                        for (int b = 0; b < NT / 2; ++b) {
+                            const int d = c > 0 ? ne[b] - cur[b] : 0;
+#pragma unroll
+                            for (int t = 0; t < PT; ++t)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    acc[t][2 * b][r] = ldexpf(acc[t][2 * b][r], d);
+                                    acc[t][2 * b + 1][r] = ldexpf(acc[t][2 * b + 1][r], d);
+                                }
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < NT / 2; ++b) cur[b] = ne[b];
+                }
+                // the positions of the next step
+                if (s == 0) {
+                    x3w_positions<NT, ROW>(T, 1, grp, xs, ys, zs);
+                } else if (c + 1 < nch) {
+                    const X3wBuf<NT>& Tn = buf[(c + 1) & 1];
+                    x3w_positions<NT, ROW>(Tn, 0, grp, xs, ys, zs);
+                    guard = !ROW || !Tn.far;
+                }
+                x3w_mma_step<NT, PT, BF16>(T, s, lane, A, acc);
+                if (s == 0 && c + 1 < nch) {
+                    // buffer (c + 1) & 1 was last read in chunk c - 1
+                    x3w_write<NT, BF16>(a, buf[(c + 1) & 1], (c + 1) * kChunk, tid, st, ROW, ry, rz,
+                                        far_c);
+                    if (c + 2 < nch) x3w_load<NT>(a, (c + 2) * kChunk, tid, st);
+                }
+                x3w_phase_barrier();
             }
-            if constexpr (ROW) {
-                if (T.far)
-                    x3w_chunk<NT, PT, BF16, true, false>(T, grp, lane, amp_s, a.inv_dmin_rev, px, py,
-                                                         pz, acc);
-                else
-                    x3w_chunk<NT, PT, BF16, true, true>(T, grp, lane, amp_s, a.inv_dmin_rev, px, py,
-                                                        pz, acc);
-            } else {
-                x3w_chunk<NT, PT, BF16, false, true>(T, grp, lane, amp_s, a.inv_dmin_rev, px, py, pz,
-                                                     acc);
-            }
-            if (c + 1 < nch) {
-                // buffer (c + 1) & 1 was last read in chunk c - 1, before the barrier
-                x3w_write<NT, BF16>(a, buf[(c + 1) & 1], (c + 1) * kChunk, tid, st, ROW, ry, rz,
-                                    far_c);
-                if (c + 2 < nch) x3w_load<NT>(a, (c + 2) * kChunk, tid, st);
-            }
-            __syncthreads();
         }
+        if (!late) x3w_phase_barrier();
     };
     if (row)
         run(std::true_type{});
