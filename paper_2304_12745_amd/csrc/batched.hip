@@ -120,10 +120,63 @@ __device__ __forceinline__ double quad_bcast(double x, int q) {
     }
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+// Cross-lane reductions without LDS: DPP moves within each 16-lane row
+// (quad_perm [1,0,3,2] and [2,3,0,1], then row_ror:4 and row_ror:8), then the
+// row swaps of v_permlane16_swap / v_permlane32_swap across the four rows.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    return __hiloint2double(dpp_i<CTRL>(__double2hiint(x)), dpp_i<CTRL>(__double2loint(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+
+// x summed over the 16 lanes of its row (in every lane of the row)
+__device__ __forceinline__ double row_sum16(double x) {
+    x += dpp_d<0xB1>(x);
+    x += dpp_d<0x4E>(x);
+    x += dpp_d<0x124>(x);
+    x += dpp_d<0x128>(x);
     return x;
+}
+
+// x summed over the lanes l, l ^ 16, l ^ 32, l ^ 48
+__device__ __forceinline__ double sum_rows4_d(double x) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
+    x = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+    const auto lo2 = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi2 = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+    return __hiloint2double(hi2[0], lo2[0]) + __hiloint2double(hi2[1], lo2[1]);
+}
+
+__device__ __forceinline__ double wave_sum(double x) { return sum_rows4_d(row_sum16(x)); }
+
+__device__ __forceinline__ int wave_max_i(int x) {
+    x = max(x, dpp_i<0xB1>(x));
+    x = max(x, dpp_i<0x4E>(x));
+    x = max(x, dpp_i<0x124>(x));
+    x = max(x, dpp_i<0x128>(x));
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    x = max((int)s[0], (int)s[1]);
+    const auto t = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return max((int)t[0], (int)t[1]);
+}
+
+__device__ __forceinline__ float wave_max_f(float x) {
+    x = fmaxf(x, dpp_f<0xB1>(x));
+    x = fmaxf(x, dpp_f<0x4E>(x));
+    x = fmaxf(x, dpp_f<0x124>(x));
+    x = fmaxf(x, dpp_f<0x128>(x));
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = fmaxf(__uint_as_float(s[0]), __uint_as_float(s[1]));
+    const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return fmaxf(__uint_as_float(t[0]), __uint_as_float(t[1]));
 }
 
 // Gauss-Jordan elimination without pivoting of a 16 x 16 Hermitian positive
@@ -207,26 +260,22 @@ __device__ __forceinline__ void bb_gains(const BbDev& a, int64_t b, BbShared& S,
     for (int r = 0; r < 4; ++r) {
         const double pw = (ar[r] * ar[r] + ai[r] * ai[r]) * (cj * cj);
         const bool diag = x == kq + 4 * r;
-        sig[r] = diag ? pw : 0.0;
-        itf[r] = diag ? 0.0 : pw;
+        sig[r] = row_sum16(diag ? pw : 0.0);
+        itf[r] = row_sum16(diag ? 0.0 : pw);
     }
+    // lane (kq, x < 4) finishes row k = kq + 4 x
+    if (x < 4) {
+        const int k = kq + 4 * x;
+        double sg = sig[0], it = itf[0];
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            sig[r] += __shfl_xor(sig[r], off, 64);
-            itf[r] += __shfl_xor(itf[r], off, 64);
+        for (int r = 1; r < 4; ++r) {
+            sg = x == r ? sig[r] : sg;
+            it = x == r ? itf[r] : it;
         }
-    }
-    if (x == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k = kq + 4 * r;
-            if (k < K) {
-                const double sv = fail ? 0.0 : sig[r] / (itf[r] + a.sigma2);
-                if (a.sinr) a.sinr[b * K + k] = sv;
-                S.rate[k] = log2(1.0 + sv);
-            }
+        if (k < K) {
+            const double sv = fail ? 0.0 : sg / (it + a.sigma2);
+            if (a.sinr) a.sinr[b * K + k] = sv;
+            S.rate[k] = log2(1.0 + sv);
         }
     }
 }
@@ -372,7 +421,7 @@ __device__ __forceinline__ void bb_store_h(BbShared& S, const float2 (&h)[kBbK],
 #pragma unroll
     for (int i = 0; i < kBbK; ++i) S.h[i][col] = h[i];
     if constexpr (MODE != 0) {
-        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        mx = wave_max_f(mx);
         if ((tid & 63) == 0) S.hmax[tid >> 6] = mx;
     }
     (void)mx;
@@ -469,9 +518,9 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
                 mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
             }
             if (MODE != 0) {
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-                aexp = mx > 0.0 ? 14 - (ilogb(mx) + 1) : 0;
+                // the exponent of the largest entry: the largest exponent
+                const int e = wave_max_i(mx > 0.0 ? ilogb(mx) : -(1 << 20));
+                aexp = e > -(1 << 20) ? 14 - (e + 1) : 0;
             }
         } else {
 #pragma unroll
@@ -621,7 +670,7 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
         else
             tiles(std::false_type{});
     }
-    for (int off = 8; off > 0; off >>= 1) l21_part += __shfl_xor(l21_part, off, 64);
+    l21_part = row_sum16(l21_part);   // lanes 16 .. 63 hold zero
     if (lane == 0) S.red[wave] = l21_part;
 
     __syncthreads();
