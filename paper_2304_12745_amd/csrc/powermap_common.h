@@ -264,6 +264,37 @@ __device__ __forceinline__ void map_epilogue(const PmMapDev& a, const f32x4 (&ac
     // one output map per group of G streams (G = K: one map)
     const int G = a.G;
     const int64_t N = a.P.n;
+    if (G == K) {
+        // one map: the row's 8 NT columns loaded at once (columns past K hold
+        // zero powers, which change no sum, maximum or index below)
+        constexpr int S = 8 * NT;
+        float p[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) p[k] = row[k];
+        float y = 0.0f, pb = -1.0f;
+        int kb = 0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            y += p[k];
+            if (p[k] > pb) {
+                pb = p[k];
+                kb = k;
+            }
+        }
+        a.power[n] = y;
+        if (a.sinr) {
+            float intf = 0.0f;
+#pragma unroll
+            for (int k = 0; k < S; ++k) intf += k != kb ? p[k] : 0.0f;
+            a.sinr[n] = pb / (intf + a.sigma2);
+        }
+        if (a.best_k) a.best_k[n] = kb;
+        if (a.per_stream) {
+            float* ps = a.per_stream + n * K;
+            for (int k = 0; k < K; ++k) ps[k] = row[k];
+        }
+        return;
+    }
     for (int g0 = 0, o = 0; g0 < K; g0 += G, ++o) {
         const float* rg = row + g0;
         float y = 0.0f, pb = -1.0f;
