@@ -184,6 +184,39 @@ constexpr int ep_bytes() {
     return WAVES * 16 * PT * ep_stride<NT>() * 4;
 }
 
+// The outputs of one map at output index idx from the powers p[0 .. GS - 1]
+// of its streams (GS unrolled; zero powers past the map's G streams change
+// nothing): power, SINR of the strongest stream, its index, and the G
+// per-stream powers at idx G.
+template <int GS>
+__device__ __forceinline__ void ep_group(const PmMapDev& a, const float* p, int64_t idx,
+                                         int64_t ps_idx, int G) {
+    float y = 0.0f, pb = -1.0f;
+    int kb = 0;
+#pragma unroll
+    for (int k = 0; k < GS; ++k) {
+        y += p[k];
+        if (p[k] > pb) {
+            pb = p[k];
+            kb = k;
+        }
+    }
+    a.power[idx] = y;
+    if (a.sinr) {
+        float intf = 0.0f;
+#pragma unroll
+        for (int k = 0; k < GS; ++k) intf += k != kb ? p[k] : 0.0f;
+        a.sinr[idx] = pb / (intf + a.sigma2);
+    }
+    if (a.best_k) a.best_k[idx] = kb;
+    if (a.per_stream) {
+        float* ps = a.per_stream + ps_idx * G;
+#pragma unroll
+        for (int k = 0; k < GS; ++k)
+            if (k < G) ps[k] = p[k];
+    }
+}
+
 // Epilogue of all PT x NT accumulator tiles of a wave.
 //
 // The per-stream powers go through LDS.  Lane (grp, col) holds D[4 grp + r][col]
@@ -264,34 +297,20 @@ __device__ __forceinline__ void map_epilogue(const PmMapDev& a, const f32x4 (&ac
     // one output map per group of G streams (G = K: one map)
     const int G = a.G;
     const int64_t N = a.P.n;
-    if (G == K) {
-        // one map: the row's 8 NT columns loaded at once (columns past K hold
-        // zero powers, which change no sum, maximum or index below)
+    if (G == K || G == 8) {
+        // one map, or maps of 8 streams: the row's 8 NT columns loaded at once
+        // (columns past K hold zero powers, which change no sum, maximum or
+        // index below)
         constexpr int S = 8 * NT;
         float p[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) p[k] = row[k];
-        float y = 0.0f, pb = -1.0f;
-        int kb = 0;
+        if (G == K) {
+            ep_group<S>(a, p, n, n, K);
+        } else {
 #pragma unroll
-        for (int k = 0; k < S; ++k) {
-            y += p[k];
-            if (p[k] > pb) {
-                pb = p[k];
-                kb = k;
-            }
-        }
-        a.power[n] = y;
-        if (a.sinr) {
-            float intf = 0.0f;
-#pragma unroll
-            for (int k = 0; k < S; ++k) intf += k != kb ? p[k] : 0.0f;
-            a.sinr[n] = pb / (intf + a.sigma2);
-        }
-        if (a.best_k) a.best_k[n] = kb;
-        if (a.per_stream) {
-            float* ps = a.per_stream + n * K;
-            for (int k = 0; k < K; ++k) ps[k] = row[k];
+            for (int o = 0; o < S / 8; ++o)
+                if (8 * o < K) ep_group<8>(a, p + 8 * o, o * N + n, o * N + n, 8);
         }
         return;
     }
