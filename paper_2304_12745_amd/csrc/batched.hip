@@ -180,26 +180,45 @@ __device__ __forceinline__ float wave_max_f(float x) {
 }
 
 // Gauss-Jordan elimination without pivoting of a 16 x 16 Hermitian positive
-// definite matrix held by one wave in registers: lane l holds row l / 4,
-// columns 4 (l % 4) .. + 3 in v.  Step p reads the pivot from its lane
-// (readlane), gives every lane the pivot-column entry of its row by a
+// definite matrix G held by one wave in registers: lane l holds row l / 4,
+// columns 4 (l % 4) .. + 3 in v.  The elimination runs on the Jacobi-scaled
+// matrix G' = S G S, S = diag(G)^-1/2 (unit diagonal, every pivot at most 1),
+// and G^-1 = S G'^-1 S at the end.  Step p reads the pivot from its lane
+// (readlane), gives every lane the pivot-column entry g of its row by a
 // broadcast within the quad that holds the row (DPP), and the pivot row's
 // entries of its columns through LDS (prow), where the lanes of row p + 1
-// leave that row after step p.  The pivot of step p is the diagonal entry of
-// the Schur complement (L_pp^2 of the Cholesky factor); one not above th[p]
-// (held by lane p) stops the elimination.  Returns 0 or the failed step
-// p + 1, the same in every lane (v is then not used).
-__device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[kBbK], double th,
+// leave that row after step p with 1 in place of its pivot.  Every row then
+// takes the same update x - (g / piv) pr: the pivot row with g - 1 (which
+// gives pr / piv up to piv 2^-53 relative, piv <= 1), the pivot column with
+// x = 0 (1 in the pivot row), so no row needs a case of its own.  The pivot
+// of step p is the Schur complement's diagonal entry of G' (L_pp^2 / G_pp of
+// the Cholesky factor L of G); one not above tol stops the elimination.
+// Returns 0 or the failed step p + 1, the same in every lane (v is then not
+// used).
+__device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[kBbK], double tol,
                                                int lane) {
     const int r = lane >> 2, q = lane & 3;
+    // 1 / sqrt(G_rr), held by the lane that holds the diagonal entry of row r
+    double dg = 1.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dg = 4 * q + e == r ? v[e].x : dg;
+    const double sd = 1.0 / sqrt(dg);
+    const double sr = __shfl(sd, 4 * r + (r >> 2), 64);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double sc = __shfl(sd, 4 * (4 * q + e) + q, 64);
+        const bool dia = 4 * q + e == r;
+        v[e].x = dia ? 1.0 : v[e].x * sr * sc;
+        v[e].y = dia ? 0.0 : v[e].y * sr * sc;
+    }
     if (r == 0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) prow[0][4 * q + e] = v[e];
+        for (int e = 0; e < 4; ++e) prow[0][4 * q + e] = 4 * q + e == 0 ? make_double2(1.0, 0.0) : v[e];
     }
 #pragma unroll
     for (int p = 0; p < kBbK; ++p) {
         const double piv = readlane_d(v[p & 3].x, 4 * p + (p >> 2));
-        if (!(piv > readlane_d(th, p))) return p + 1;
+        if (!(piv > tol)) return p + 1;
         // 1 / piv: hardware reciprocal and two Newton steps (within an ulp)
         double inv = __builtin_amdgcn_rcp(piv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
@@ -207,20 +226,31 @@ __device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[
         double2 pr[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) pr[e] = prow[p][4 * q + e];
-        const double2 gip = make_double2(quad_bcast(v[p & 3].x, p >> 2), quad_bcast(v[p & 3].y, p >> 2));
+        const double gx = quad_bcast(v[p & 3].x, p >> 2) - (r == p ? 1.0 : 0.0);
+        const double gy = quad_bcast(v[p & 3].y, p >> 2);
+        const double gix = gx * inv, giy = gy * inv;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const bool jp = 4 * q + e == p;
-            const double2 rv = jp ? make_double2(inv, 0.0) : make_double2(pr[e].x * inv, pr[e].y * inv);
-            const double2 x = jp ? make_double2(0.0, 0.0) : v[e];
-            const double2 nv = make_double2(fma(-gip.x, rv.x, fma(gip.y, rv.y, x.x)),
-                                            fma(-gip.x, rv.y, fma(-gip.y, rv.x, x.y)));
-            v[e] = r == p ? rv : nv;
+            double xx = v[e].x, xy = v[e].y;
+            if (e == (p & 3)) {
+                const bool jp = q == (p >> 2);
+                xx = jp ? (r == p ? 1.0 : 0.0) : xx;
+                xy = jp ? 0.0 : xy;
+            }
+            v[e].x = fma(-gix, pr[e].x, fma(giy, pr[e].y, xx));
+            v[e].y = fma(-gix, pr[e].y, fma(-giy, pr[e].x, xy));
         }
         if (p + 1 < kBbK && r == p + 1) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) prow[p + 1][4 * q + e] = v[e];
+            for (int e = 0; e < 4; ++e)
+                prow[p + 1][4 * q + e] = 4 * q + e == p + 1 ? make_double2(1.0, 0.0) : v[e];
         }
+    }
+    // G^-1 = S G'^-1 S
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double sc = __shfl(sd, 4 * (4 * q + e) + q, 64);
+        v[e] = make_double2(v[e].x * sr * sc, v[e].y * sr * sc);
     }
     return 0;
 }
@@ -501,13 +531,12 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
         double t = 0.0;
         if (zf) {
             // padded to 16 x 16 with the identity outside K x K
-            const double th = (lane & 15) < K ? a.pivot_tol * S.g0[lane & 15][lane & 15].x : 0.5;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = 4 * q + e;
                 if (r >= K || j >= K) v[e] = make_double2(r == j ? 1.0 : 0.0, 0.0);
             }
-            fail = bb_gauss_jordan(v, S.u.prow, th, lane);
+            fail = bb_gauss_jordan(v, S.u.prow, a.pivot_tol, lane);
             double mx = 0.0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
