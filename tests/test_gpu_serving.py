@@ -276,22 +276,31 @@ def test_zf_query_with_duplicate_users_fails(D):
 
 
 def test_full_pending_queue_is_busy(D):
-    # one admitted query at a time and a pending queue of 64: a burst of large
-    # queries gets DMIMO_E_BUSY once 64 wait; every accepted query completes
+    # one admitted query at a time and a pending queue of 64: a burst of 100
+    # large queries (2048 x 2048 points, 512 APs, K = 16: milliseconds each),
+    # with every input prepared before the burst so that the submissions take
+    # microseconds, gets DMIMO_E_BUSY once 64 wait; every accepted query
+    # completes
     say("serving: pending queue full -> DMIMO_E_BUSY")
     rng = np.random.default_rng(22)
+    side, n = 2048, 100
+    g = WL.Grid(0.0, 0.0, 20.0 / side, 20.0 / side, 1.2, side, side)
+    pts = D.grid_points(g)
+    users = [WL.uniform_positions(rng, 16, 20.0, 20.0, 1.2) for _ in range(n)]
+    outs = [torch.full((g.n,), -1.0, device="cuda") for _ in range(n)]
+    torch.cuda.synchronize()
     with D.Server(1 << 30, 1) as srv:
         dep = srv.add_deployment(D.channel_params(5.8e9), _room(rng, 512, 5.8e9))
         tickets, busy = [], 0
-        for _ in range(80):
+        for i in range(n):
             try:
-                tickets.append(_big_query(D, srv, dep, rng)[0])
+                tickets.append(srv.submit(dep, users[i], "zf", pts, 1e-12, 1.0, "f32", outs[i]))
             except D.DmimoError as e:
                 assert e.status == 7
                 busy += 1
         say(f"    accepted {len(tickets)}, busy {busy}")
-        assert busy > 0
-        assert all(s == D.Q_DONE for s in _drain(srv, tickets, 120.0))
+        assert busy > 0 and len(tickets) >= 64
+        assert all(s == D.Q_DONE for s in _drain(srv, tickets, 300.0))
 
 
 def test_cancel_a_queued_query(D):
