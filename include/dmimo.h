@@ -176,8 +176,9 @@ dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
  * FP32 products; MIX modes: FP16 / BF16 hi/lo split products, FP32
  * accumulation), inverse in FP64 (Gauss-Jordan, the pivot test of
  * dmimo_beamform), G^-1 H by FP32 matrix-core products.  SINR_k uses the gains
- * A = H W^T, which for ZF equal G G^-1 D_c and for MR c G (Sec. II-A; exact
- * identities of W = conj(G^-1 H) D_c and G = H H^H), formed in FP64.
+ * A = H W^T, which for ZF equal D_c (no interference: SINR_k = c_k^2 / sigma2)
+ * and for MR c G (Sec. II-A; exact identities of W = conj(G^-1 H) D_c and
+ * G = H H^H), the latter formed in FP64.
  *   precoder   DMIMO_MR or DMIMO_ZF.
  *   params     LoS or Rician; nlos: device complex64 [B][K][M] for Rician,
  *              NULL for LoS.

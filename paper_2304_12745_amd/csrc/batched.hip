@@ -25,9 +25,9 @@
 //     rounded to FP32, or split-FP16 16x16x32 products in the MIX modes), or
 //     X = H for MR; W = c conj(X) to HBM (optional), p_m and sum_m sqrt(p_m).
 //  5. Wave 0: the gains A = H W^T.  With W = conj(G^-1 H) D_c and G = H H^H
-//     this is A = G G^-1 D_c for ZF and A = G D_c for MR (exact identities),
-//     formed in FP64 on the matrix cores from the same G; SINR_k and the sum
-//     rate follow (Sec. VI-B).
+//     this is A = D_c for ZF and A = G D_c for MR (exact identities), so ZF
+//     has SINR_k = c_k^2 / sigma^2 and MR sums its interference from G;
+//     SINR_k and the sum rate follow (Sec. VI-B).
 // A deployment reads its NLoS draws (8 B per term) and positions and writes
 // W (8 B per term, optional) and the epilogues: nothing else touches HBM.
 #include <algorithm>
@@ -255,34 +255,31 @@ __device__ __forceinline__ int bb_gauss_jordan(double2 (&v)[4], double2 (*prow)[
     return 0;
 }
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// 5. (one wave) the gains A = G G^-1 D_c (ZF) or G D_c (MR) in FP64, on the
-// matrix cores for ZF (16x16x4 FP64: lane (k', i) supplies G[i][4t + k'],
-// lane (k', j) G^-1[4t + k'][j]; lane (g, j) receives A[g + 4r][j]), then
-// SINR_k = |A_kk|^2 / (sum_{j != k} |A_kj|^2 + sigma^2) by 16-lane shuffle
-// sums, written for k < K with log2(1 + SINR_k) to LDS for R_sum.
+// 5. (one wave) the gains A = H W^T and SINR_k = |A_kk|^2 / (sum_{j != k}
+// |A_kj|^2 + sigma^2), written for k < K with log2(1 + SINR_k) to LDS for
+// R_sum.  ZF: A = G G^-1 D_c = D_c, no interference, SINR_k = c_k^2 / sigma^2
+// (the product G G^-1 formed in FP64 differs from I only by the inverse's
+// rounding, which changes no digit of SINR_k).  MR: A = G D_c, the
+// interference summed over the 16 lanes of a row group (lane (g, j) holds
+// A[g + 4r][j]) and SINR_k formed by lane (g, x < 4) for row g + 4x.
 __device__ __forceinline__ void bb_gains(const BbDev& a, int64_t b, BbShared& S, int K, int lane,
                                          int fail, bool zf) {
-    const int kq = lane >> 4, x = lane & 15;
-    f64x4 ar = {0.0, 0.0, 0.0, 0.0}, ai = {0.0, 0.0, 0.0, 0.0};
     if (zf) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const double2 g = S.g0[x][4 * t + kq];
-            const double2 v = S.gi[4 * t + kq][x];
-            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.x, ar, 0, 0, 0);
-            ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-g.y, v.y, ar, 0, 0, 0);
-            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.y, ai, 0, 0, 0);
-            ai = __builtin_amdgcn_mfma_f64_16x16x4f64(g.y, v.x, ai, 0, 0, 0);
+        if (lane < K) {
+            const double ck = S.c[lane];
+            const double sv = fail ? 0.0 : (ck * ck) / a.sigma2;
+            if (a.sinr) a.sinr[b * K + lane] = sv;
+            S.rate[lane] = log2(1.0 + sv);
         }
-    } else {
+        return;
+    }
+    const int kq = lane >> 4, x = lane & 15;
+    double ar[4], ai[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double2 g = S.g0[kq + 4 * r][x];
-            ar[r] = g.x;
-            ai[r] = g.y;
-        }
+    for (int r = 0; r < 4; ++r) {
+        const double2 g = S.g0[kq + 4 * r][x];
+        ar[r] = g.x;
+        ai[r] = g.y;
     }
     const double cj = S.c[x];
     double sig[4], itf[4];
