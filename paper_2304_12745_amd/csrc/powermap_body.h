@@ -773,6 +773,12 @@ __device__ __forceinline__ void map_x3w_wg(const PmMapDev& a, int64_t wg_first, 
     const int64_t base = wg_first + (int64_t)wave * (16 * PT);
     const int hexp = BF16 ? 0 : a.hexp;
     const float amp_s = ldexpf(a.amp_rev, hexp);
+    // the first chunk's weights and antenna positions, loaded before the
+    // points are located so that their latency overlaps that arithmetic
+    X3wStage st;
+    st.wexp = 0;
+    st.set = false;
+    x3w_load<NT>(a, 0, tid, st);
 
     const bool grid = a.P.kind == DMIMO_PTS_GRID;
     const WgGrid wg = grid ? wg_grid(a, wg_first, 16 * PT * WAVES) : WgGrid{};
@@ -805,9 +811,6 @@ __device__ __forceinline__ void map_x3w_wg(const PmMapDev& a, int64_t wg_first, 
 #pragma unroll
     for (int b = 0; b < NT / 2; ++b) cur[b] = 0;
 
-    X3wStage st;
-    st.wexp = 0;
-    st.set = false;
     const int nch = (M + kChunk - 1) / kChunk;
     // Waves w and w + 4 share a SIMD.  The second half of the workgroup runs
     // every step one phase behind the first: while one wave synthesises the
@@ -826,7 +829,6 @@ __device__ __forceinline__ void map_x3w_wg(const PmMapDev& a, int64_t wg_first, 
     // others (one copy of the accumulators per loop)
     auto run = [&](auto row_tag) {
         constexpr bool ROW = decltype(row_tag)::value;
-        x3w_load<NT>(a, 0, tid, st);
         x3w_write<NT, BF16>(a, buf[0], 0, tid, st, ROW, ry, rz, far_c);
         if (nch > 1) x3w_load<NT>(a, kChunk, tid, st);
         __syncthreads();
