@@ -38,7 +38,8 @@ The JSON line also carries:
 * Secondary configurations: ``room`` (the 512x512 MR + ZF room step),
   ``focus`` (the FP64 MR focusing map), ``batched`` (Rician Gram + ZF over
   many deployments), ``paper`` (the paper's ZF sum rate), ``serving``
-  (Poisson queries, p50/p99), ``pgd`` and ``pa`` (the paper's solver), and
+  (Poisson queries, p50/p99, FP16x3 maps with the same stream in FP32 beside
+  them), ``pgd`` and ``pa`` (the paper's solver), and
   ``channel`` (the channel materialised in HBM), each with its dB errors.
 
 Only the CPU-baseline and error legs import the oracle; they run before the
@@ -168,7 +169,10 @@ def parse_args():
                    help="measured window of the serving phase (0 disables it)")
     p.add_argument("--serve-warmup", type=float, default=5.0)
     p.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (1/s)")
-    p.add_argument("--serve-prec", default="f32", choices=["f32", "f16x3", "bf16x3"])
+    p.add_argument("--serve-prec", default="f16x3", choices=["f32", "f16x3", "bf16x3"],
+                   help="precision of the served maps (the FP32 stream is also run, shorter, "
+                        "as the comparison; --serve-compare-seconds 0 skips it)")
+    p.add_argument("--serve-compare-seconds", type=float, default=10.0)
     p.add_argument("--serve-sweep", action="store_true",
                    help="also serve at 500, 1000, 2000 and 4000 queries/s (3 s each)")
     p.add_argument("--room-steps", type=int, default=500)
@@ -577,6 +581,13 @@ def main():
         if args.serve_seconds > 0:
             out["serving"] = serving_phase(args, D, WL, torch)
             out["p99_query_ms"] = out["serving"]["p99_ms"]
+            if args.serve_prec != "f32" and args.serve_compare_seconds > 0:
+                # the same Poisson stream served in FP32 (shorter window)
+                a2 = argparse.Namespace(**vars(args))
+                a2.serve_prec, a2.serve_seconds, a2.serve_warmup = "f32", args.serve_compare_seconds, 2.0
+                r = serving_phase(a2, D, WL, torch)
+                out["serving"]["f32"] = {k: r[k] for k in ("measured_s", "queries", "failed", "p50_ms",
+                                                           "p99_ms", "max_ms", "sustained_Gh_per_s")}
         if args.serve_sweep:
             sweep = []
             for rate in (500.0, 1000.0, 2000.0, 4000.0):
