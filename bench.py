@@ -950,9 +950,13 @@ def batched_phase(D, WL, torch, event_launches=30):
       dmimo_beamform_batched (synthesis -> Gram on the matrix cores -> FP64
       solve -> W, p_m, SINR_k) in FP16x3, BF16x3 and FP32; SINR_k of sampled
       deployments against the FP64 oracle chain in dB, and against the
-      two-call path (dmimo_channel + dmimo_beamform), which is also timed.
+      two-call path (dmimo_channel + dmimo_beamform), which is also timed
+      (dmimo_beamform runs the same kernel on the written H: equal bits).
     * ``sweep``: the fused call for B = 2^10 .. 2^17 (the 1024 rooms tiled),
       HBM fraction of the algorithmic bytes (batched_bytes).
+    * ``from_h``: dmimo_beamform (ZF at 1 W) of B = 2^17 CN(0,1) channels
+      drawn on the device, FP32 and FP16x3, HBM fraction of H read + W and
+      the epilogues written.
     * ``roofline``: B = 2^17 FP16x3 with W written, from HIP events around
       ``event_launches`` back-to-back launches; traffic from the committed
       counter summary when it matches the sources.
@@ -998,14 +1002,17 @@ def batched_phase(D, WL, torch, event_launches=30):
                      "failed_deployments": int((r.info != 0).sum().item()),
                      "err_db_user_sinr": plain_db(r.sinr.cpu().numpy()[idx], so)}
         if prec in ("f16x3", "f32"):
-            # the two-call path: channel to HBM, then Gram + ZF from HBM
+            # the two-call path: channel to HBM, then ZF from HBM
             pts = D.list_points(users, K)
             H = D.channel(params, ap, pts, nlos=nlos, prec="f32")
             r2 = D.beamform(H, "zf", None, w.sigma2, w.p_total, prec)
             ms_ch = timed(lambda: D.channel(params, ap, pts, nlos=nlos, prec="f32", out=H), 20)
             ms_bf = timed(lambda: D.beamform(H, "zf", None, w.sigma2, w.p_total, prec, out=r2), 20)
-            ric[prec]["two_call"] = {"channel_ms": round(ms_ch, 4), "gram_zf_ms": round(ms_bf, 4),
-                                     "ms": round(ms_ch + ms_bf, 4)}
+            ric[prec]["two_call"] = {"channel_ms": round(ms_ch, 4), "beamform_ms": round(ms_bf, 4),
+                                     "ms": round(ms_ch + ms_bf, 4),
+                                     "equal_bits": all(torch.equal(getattr(r, n), getattr(r2, n))
+                                                       for n in ("W", "p_ant", "l21", "sinr",
+                                                                 "rsum", "info"))}
             ric[prec]["err_db_vs_two_call"] = plain_db(r.sinr.cpu().numpy(), r2.sinr.cpu().numpy())
             del H, r2
         del r
@@ -1050,7 +1057,25 @@ def batched_phase(D, WL, torch, event_launches=30):
             del r
     del apT, usT, nlT
     torch.cuda.empty_cache()
+    # dmimo_beamform from H (8 < K <= 16, M <= 256: the same kernel, channel loaded)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    Hr = torch.complex(torch.randn(bmax, K, M, generator=gen, device="cuda"),
+                       torch.randn(bmax, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
+    from_h = {"workload": f"dmimo_beamform ZF at 1 W of {bmax} CN(0,1) channels K={K} M={M}, "
+                          "sigma2 = 1, H resident; hbm_frac of H read + W, p_m, SINR_k and "
+                          "the scalars written"}
+    hbytes = bmax * (K * M * 16 + M * 8 + K * 8 + 20)
+    for prec in ("f32", "f16x3"):
+        r = D.beamform(Hr, "zf", None, 1.0, 1.0, prec)
+        ms = timed(lambda: D.beamform(Hr, "zf", None, 1.0, 1.0, prec, out=r), 10)
+        from_h[prec] = {"ms": round(ms, 4), "hbm_frac": round(hbytes / (ms * 1e-3) / HBM_PEAK, 4),
+                        "failed_deployments": int((r.info != 0).sum().item())}
+        del r
+    del Hr
+    torch.cuda.empty_cache()
     return {"rician": ric,
+            "from_h": from_h,
             "sweep_workload": "fused dmimo_beamform_batched, B rooms (the 1024 tiled) x K=16 x M=256, "
                               "Rician, ZF at 1 W, W written; hbm_frac of the algorithmic bytes "
                               "(NLoS + positions read, W + p_m + SINR + R_sum written)",

@@ -141,6 +141,13 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *             antennas (M > 448) also form G in FP64, from per-tile sums
  *             computed in parallel workgroups and added in tile order (MR
  *             calls of that shape sum ||H||_F^2 the same way).
+ *             MR and ZF with 8 < K <= 16, M <= 256 in DMIMO_F32 or a MIX mode
+ *             run on the kernel of dmimo_beamform_batched with H given (the
+ *             same bits as that call on the H it writes): the Gram on the
+ *             matrix cores in the precision asked for, G^-1 in FP64, G^-1 H by
+ *             FP32 (DMIMO_F32) or split-FP16 (MIX) matrix-core products, and
+ *             SINR_k from the gains' identities (ZF: c_k^2 / sigma2; MR: from
+ *             G in FP64).
  * Outputs (device; any may be NULL except W):
  *   W      [B][K][M] precoder, same complex type as H.
  *   p_ant  FP64 [B][M]  per-antenna power p_m = sum_k |w_km|^2.
@@ -159,7 +166,8 @@ dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t 
  *                 for MR and equal-gain MR.  The MR size is 0 (NULL accepted)
  *                 except for calls of at most 64 deployments with M > 448, which
  *                 spread each deployment over parallel workgroups of 64 antennas
- *                 and keep per-tile shares there.  A smaller workspace returns
+ *                 and keep per-tile shares there; the ZF size is 0 on the
+ *                 batched kernel's shapes above.  A smaller workspace returns
  *                 DMIMO_E_WORKSPACE. */
 dmimo_status dmimo_beamform(int32_t precoder, int32_t B, int32_t K, int32_t M,
                             const void* H, const double* gamma_lin, double sigma2,
@@ -205,7 +213,8 @@ dmimo_status dmimo_beamform_batched(int32_t precoder, const dmimo_channel_params
  *   Every argument and output as for dmimo_beamform.
  *   A call whose workspace (dmimo_workspace_size of dmimo_beamform) exceeds
  *   DMIMO_NOALLOC_SCRATCH_BYTES returns DMIMO_E_WORKSPACE before any launch
- *   (e.g. FP32 ZF with K = 16, M = 256 fits up to B = 4096).
+ *   (e.g. FP32 ZF with K = 16, M = 300 fits up to B = 4096; K = 16, M <= 256
+ *   needs none).
  *   All calls on one device share the array: calls that overlap on one device
  *   (on different streams or host threads) race and must be serialised by the
  *   caller.  No call depends on what an earlier call left in the array. */

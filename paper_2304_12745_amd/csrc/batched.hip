@@ -30,6 +30,10 @@
 //     SINR_k and the sum rate follow (Sec. VI-B).
 // A deployment reads its NLoS draws (8 B per term) and positions and writes
 // W (8 B per term, optional) and the epilogues: nothing else touches HBM.
+// The same kernel with H given (HIN: dmimo_beamform's ZF and MR at these
+// shapes) loads thread m's column of H in step 1 instead of synthesising it
+// and runs steps 2 - 5 unchanged: the same bits as the fused call on the H
+// that call writes.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -56,6 +60,7 @@ struct BbDev {
     const double* ap;      // [B][M][3]
     const double* users;   // [B][K][3]
     const float2* nlos;    // [B][K][M] CN(0,1) draws, or null (LoS)
+    const float2* Hin;     // [B][K][M]: the channel given (the HIN kernel)
     double cpaper[kBbK];   // ZF at p_total <= 0: the row scales sigma sqrt(gamma_k)
     double sigma2, p_total, pivot_tol;
     float2* H;             // [B][K][M] or null
@@ -365,7 +370,8 @@ __device__ __forceinline__ void bb_gram(BbShared& S, int wave, int lane, int hex
 }
 
 // Inputs of one deployment held in registers: thread m's antenna position
-// and NLoS draws (16 users), and one coordinate of the users.
+// and NLoS draws (16 users), and one coordinate of the users; with H given,
+// thread m's column of H in g.
 struct BbIn {
     double ax, ay, az, u;
     float2 g[kBbK];
@@ -379,9 +385,17 @@ __device__ __forceinline__ void bb_settle(BbIn& in) {
     for (int i = 0; i < kBbK; ++i) asm volatile("" : "+v"(in.g[i].x), "+v"(in.g[i].y));
 }
 
+template <bool HIN>
 __device__ __forceinline__ void bb_fetch(const BbDev& a, int64_t b, int tid, BbIn& in, int K, int M) {
     // clamped indices: every lane loads a valid address, unused values are never read
     const int m = tid < M ? tid : M - 1;
+    if constexpr (HIN) {
+        const float2* hb = a.Hin + b * K * M + m;
+#pragma unroll
+        for (int i = 0; i < kBbK; ++i) in.g[i] = hb[(i < K ? i : K - 1) * M];
+        in.ax = in.ay = in.az = in.u = 0.0;
+        return;
+    }
     const double* q = a.ap + (b * M + m) * 3;
     in.ax = q[0];
     in.ay = q[1];
@@ -430,9 +444,19 @@ __device__ __forceinline__ float bb_synth_rows(const BbDev& a, int64_t b, const 
     return mx;
 }
 
-template <int MODE>
+template <int MODE, bool HIN>
 __device__ __forceinline__ float bb_synth(const BbDev& a, int64_t b, const BbShared& S, const BbIn& in,
                                           int K, int M, int tid, float2 (&h)[kBbK]) {
+    if constexpr (HIN) {
+        // the loaded column: rows past K zero, lanes m >= M hold antenna M - 1's
+        float mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kBbK; ++i) {
+            h[i] = i < K ? in.g[i] : make_float2(0.0f, 0.0f);
+            if constexpr (MODE != 0) mx = fmaxf(mx, fmaxf(fabsf(h[i].x), fabsf(h[i].y)));
+        }
+        return mx;
+    }
     if (a.nlos)
         return a.H ? bb_synth_rows<MODE, true, true>(a, b, S, in, K, M, tid, h)
                    : bb_synth_rows<MODE, true, false>(a, b, S, in, K, M, tid, h);
@@ -465,7 +489,7 @@ __device__ __forceinline__ void bb_store_h(BbShared& S, const float2 (&h)[kBbK],
 //   W  H(b + grid) to LDS; the scalar outputs of b
 // Four barriers per deployment.  The FP64 solve of b runs beside the
 // synthesis of b + grid instead of before it.
-template <int MODE>
+template <int MODE, bool HIN>
 __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, BbIn& in,
                                         float2 (&hn)[kBbK], bool more1, bool more2, int K, int M,
                                         int tid) {
@@ -474,7 +498,7 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
     const bool zf = a.precoder == DMIMO_ZF;
     const int64_t bn = b + gridDim.x;
     // A.  `in` holds the inputs of b + grid (loaded one deployment ago)
-    if (more1 && tid < 3 * K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
+    if (!HIN && more1 && tid < 3 * K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     // MIX: largest |h| of the deployment scaled into [2^13, 2^14) for the
     // FP16 products (the Gram in FP16 mode, X = G^-1 H in both)
     int xexp = 0;
@@ -569,8 +593,8 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
         __builtin_amdgcn_s_setprio(0);
     }
     else if (more1) {
-        mxn = bb_synth<MODE>(a, bn, S, in, K, M, tid, hn);
-        if (more2) bb_fetch(a, bn + gridDim.x, tid, in, K, M);
+        mxn = bb_synth<MODE, HIN>(a, bn, S, in, K, M, tid, hn);
+        if (more2) bb_fetch<HIN>(a, bn + gridDim.x, tid, in, K, M);
     }
     __syncthreads();
     const int fail = S.fail;
@@ -578,8 +602,8 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
     // X.
     if (wave == 0) {
         if (more1) {
-            mxn = bb_synth<MODE>(a, bn, S, in, K, M, tid, hn);
-            if (more2) bb_fetch(a, bn + gridDim.x, tid, in, K, M);
+            mxn = bb_synth<MODE, HIN>(a, bn, S, in, K, M, tid, hn);
+            if (more2) bb_fetch<HIN>(a, bn + gridDim.x, tid, in, K, M);
         }
         bb_gains(a, b, S, K, lane, fail, zf);
     } else {
@@ -714,7 +738,7 @@ __device__ __forceinline__ void bb_step(const BbDev& a, int64_t b, BbShared& S, 
 }
 
 // Persistent: workgroup w takes deployments w, w + gridDim.x, ...
-template <int MODE>
+template <int MODE, bool HIN>
 __global__ __launch_bounds__(kBbThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void beamform_batched_kernel(BbDev a) {
     __shared__ BbShared S;
@@ -728,13 +752,13 @@ void beamform_batched_kernel(BbDev a) {
     for (int i = 0; i < kBbK; ++i) S.h[i][tid] = make_float2(0.0f, 0.0f);
     // the first deployment's channel (the grid has at most B workgroups)
     const int64_t b0 = blockIdx.x;
-    bb_fetch(a, b0, tid, in, a.K, a.M);
+    bb_fetch<HIN>(a, b0, tid, in, a.K, a.M);
     bb_settle(in);
-    if (tid < 3 * a.K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
+    if (!HIN && tid < 3 * a.K) S.user[tid / 3][tid - 3 * (tid / 3)] = in.u;
     __syncthreads();
-    const float mx0 = bb_synth<MODE>(a, b0, S, in, a.K, a.M, tid, hn);
+    const float mx0 = bb_synth<MODE, HIN>(a, b0, S, in, a.K, a.M, tid, hn);
     if (b0 + gridDim.x < a.B) {
-        bb_fetch(a, b0 + gridDim.x, tid, in, a.K, a.M);
+        bb_fetch<HIN>(a, b0 + gridDim.x, tid, in, a.K, a.M);
         bb_settle(in);
     }
     bb_store_h<MODE>(S, hn, mx0, a.M, tid);
@@ -745,7 +769,7 @@ void beamform_batched_kernel(BbDev a) {
         // registers across the loop
         int K = a.K, M = a.M, t = tid;
         asm volatile("" : "+s"(K), "+s"(M), "+v"(t));
-        bb_step<MODE>(a, b, S, in, hn, b + gridDim.x < a.B, b + 2 * (int64_t)gridDim.x < a.B, K, M, t);
+        bb_step<MODE, HIN>(a, b, S, in, hn, b + gridDim.x < a.B, b + 2 * (int64_t)gridDim.x < a.B, K, M, t);
     }
 }
 
@@ -765,44 +789,79 @@ int device_cus() {
 
 }  // namespace
 
-dmimo_status launch_beamform_batched(const BeamformArgs& ba, const WaveConst& w,
-                                     const double* ap_xyz, const double* user_xyz,
-                                     const void* nlos, void* H, hipStream_t s) {
-    if (ba.K < 1 || ba.K > kBbK || ba.M < 1 || ba.M > kBbM)
-        return fail(DMIMO_E_SHAPE, "beamform_batched: K <= 16 and M <= 256");
-    if (ba.B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "beamform_batched: B too large");
-    if (ba.B == 0) return DMIMO_OK;
+namespace {
+
+BbDev bb_dev(const BeamformArgs& ba) {
     BbDev d;
-    d.w = w;
+    d.w = WaveConst{};
     d.B = ba.B;
     d.K = ba.K;
     d.M = (int)ba.M;
     d.precoder = ba.precoder;
     d.prec = ba.prec;
-    d.ap = ap_xyz;
-    d.users = user_xyz;
-    d.nlos = reinterpret_cast<const float2*>(nlos);
+    d.ap = nullptr;
+    d.users = nullptr;
+    d.nlos = nullptr;
+    d.Hin = nullptr;
     for (int k = 0; k < kBbK; ++k) d.cpaper[k] = std::sqrt(ba.sigma2) * std::sqrt(ba.gamma[k]);
     d.sigma2 = ba.sigma2;
     d.p_total = ba.p_total;
     d.pivot_tol = ba.prec == DMIMO_MIX_BF16X3 ? 1e-4 : 1e-6;
-    d.H = reinterpret_cast<float2*>(H);
+    d.H = nullptr;
     d.W = reinterpret_cast<float2*>(ba.W);
     d.p_ant = ba.p_ant;
     d.l21 = ba.l21;
     d.sinr = ba.sinr;
     d.rsum = ba.rsum;
     d.info = ba.info;
+    return d;
+}
+
+template <bool HIN>
+dmimo_status bb_launch(const BbDev& d, int prec, hipStream_t s) {
     // persistent workgroups: three per CU fit the 51 KB of LDS
     const int64_t wgs = 3 * (int64_t)device_cus();
-    const dim3 grid((unsigned)std::min<int64_t>(ba.B, wgs)), block(kBbThreads);
-    if (ba.prec == DMIMO_MIX_F16X3)
-        beamform_batched_kernel<1><<<grid, block, 0, s>>>(d);
-    else if (ba.prec == DMIMO_MIX_BF16X3)
-        beamform_batched_kernel<2><<<grid, block, 0, s>>>(d);
+    const dim3 grid((unsigned)std::min<int64_t>(d.B, wgs)), block(kBbThreads);
+    if (prec == DMIMO_MIX_F16X3)
+        beamform_batched_kernel<1, HIN><<<grid, block, 0, s>>>(d);
+    else if (prec == DMIMO_MIX_BF16X3)
+        beamform_batched_kernel<2, HIN><<<grid, block, 0, s>>>(d);
     else
-        beamform_batched_kernel<0><<<grid, block, 0, s>>>(d);
+        beamform_batched_kernel<0, HIN><<<grid, block, 0, s>>>(d);
     return check_launch("beamform_batched_kernel");
+}
+
+dmimo_status bb_check(const BeamformArgs& ba) {
+    if (ba.K < 1 || ba.K > kBbK || ba.M < 1 || ba.M > kBbM)
+        return fail(DMIMO_E_SHAPE, "beamform_batched: K <= 16 and M <= 256");
+    if (ba.B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "beamform_batched: B too large");
+    return DMIMO_OK;
+}
+
+}  // namespace
+
+dmimo_status launch_beamform_batched(const BeamformArgs& ba, const WaveConst& w,
+                                     const double* ap_xyz, const double* user_xyz,
+                                     const void* nlos, void* H, hipStream_t s) {
+    if (const dmimo_status st = bb_check(ba)) return st;
+    if (ba.B == 0) return DMIMO_OK;
+    BbDev d = bb_dev(ba);
+    d.w = w;
+    d.ap = ap_xyz;
+    d.users = user_xyz;
+    d.nlos = reinterpret_cast<const float2*>(nlos);
+    d.H = reinterpret_cast<float2*>(H);
+    return bb_launch<false>(d, ba.prec, s);
+}
+
+// The kernel with the channel given (ba.H, [B][K][M] complex64): the MR and
+// ZF calls of dmimo_beamform at 8 < K <= 16, M <= 256 in FP32 or MIX.
+dmimo_status launch_beamform_batched_h(const BeamformArgs& ba, hipStream_t s) {
+    if (const dmimo_status st = bb_check(ba)) return st;
+    if (ba.B == 0) return DMIMO_OK;
+    BbDev d = bb_dev(ba);
+    d.Hin = reinterpret_cast<const float2*>(ba.H);
+    return bb_launch<true>(d, ba.prec, s);
 }
 
 }  // namespace dmimo

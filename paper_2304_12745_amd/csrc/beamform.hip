@@ -1015,6 +1015,15 @@ dmimo_status launch_wide(const BfDev& d, int64_t B, int prec, hipStream_t s) {
 // The one-pass kernel's antenna limit: LDS holds H and W, 8 x (MT + 1) each.
 int64_t small_max_m(int prec) { return prec == DMIMO_F64 ? kSmallMaxM / 2 : kSmallMaxM; }
 
+// Shapes past the one-pass kernel that the batched kernel takes from H (MR or
+// ZF, 8 < K <= 16, M <= 256, FP32 or MIX): one persistent launch, the Gram on
+// the matrix cores and G^-1 in FP64, no workspace (launch_beamform_batched_h,
+// batched.hip).
+bool batched_h_shape(int precoder, int K, int64_t M, int prec) {
+    return (precoder == DMIMO_ZF || precoder == DMIMO_MR) && prec != DMIMO_F64 && K > kSmallK &&
+           K <= 16 && M <= 256;
+}
+
 template <typename T2, int MT_WIDE>
 dmimo_status launch_small(const BfDev& d, int64_t B, int P, hipStream_t s) {
     dim3 grid((unsigned)B, (unsigned)P), block(kThreads);
@@ -1025,8 +1034,13 @@ dmimo_status launch_small(const BfDev& d, int64_t B, int P, hipStream_t s) {
 
 }  // namespace
 
+// batched.hip: dmimo_beamform_batched's kernel with the channel given (a.H,
+// [B][K][M] complex64), K <= 16, M <= 256, FP32 or MIX; no workspace.
+dmimo_status launch_beamform_batched_h(const BeamformArgs& a, hipStream_t s);
+
 size_t beamform_workspace_bytes(int precoder, int64_t B, int K, int64_t M, int prec) {
     const int layout = precoder == DMIMO_ZF ? DMIMO_ZF : DMIMO_MR;
+    if (batched_h_shape(precoder, K, M, prec)) return 0;
     if (!wide_shape(B, M) || (K <= kSmallK && M <= small_max_m(prec)))
         return layout == DMIMO_ZF ? ws_align((size_t)B * K * K * (prec == DMIMO_F64 ? 16 : 8)) : 0;
     return wide_layout(layout, B, K, M, prec).total;
@@ -1064,6 +1078,7 @@ dmimo_status launch_beamform(const BeamformArgs& a, hipStream_t s) {
         if (a.prec == DMIMO_F64) return launch_small<double2, kSmallMaxM / 2>(d, a.B, 1, s);
         return launch_small<float2, kSmallMaxM>(d, a.B, 1, s);
     }
+    if (batched_h_shape(a.precoder, a.K, a.M, a.prec)) return launch_beamform_batched_h(a, s);
     if (wide_shape(a.B, a.M)) {
         // ZF: G from FP64 tile sums, so the FP64 Gram's tolerance for FP64
         // input and the FP32 one otherwise

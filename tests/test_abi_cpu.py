@@ -42,7 +42,13 @@ def test_status_strings(lib):
 
 
 def test_workspace_size(lib):
-    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 16, 256, 0, D.F32) == 1024 * 16 * 16 * 8
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 16, 300, 0, D.F32) == 1024 * 16 * 16 * 8
+    # 8 < K <= 16, M <= 256 in FP32 / MIX: the persistent batched kernel, no
+    # workspace; FP64 keeps the Gram in the workspace
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 16, 256, 0, D.F32) == 0
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 9, 1, 0, D.MIX_F16X3) == 0
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 16, 256, 0, D.F64) == 1024 * 16 * 16 * 16
+    assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 1024, 17, 256, 0, D.F32) == 1024 * 17 * 17 * 8
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_ZF, 3, 5, 9, 0, D.F64) == 1280  # 3*25*16 = 1200 -> 256-aligned
     assert lib.dmimo_workspace_size(D.CALL_BEAMFORM_MR, 1024, 16, 256, 0, D.F32) == 0
     # few deployments with at least 8 tiles of 64 antennas: the Gram, G^-1,

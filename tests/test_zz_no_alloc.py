@@ -5,9 +5,11 @@ Its outputs must equal dmimo_beamform's (with a caller workspace) bit for bit:
 both run the same kernels on the same inputs.  Two calls in a row, the second
 with a smaller input, so that the second call runs over what the first left
 in the shared array.  Shapes: the batched one-pass kernel (K <= 8), the
-general kernel with its Gram in the array (K = 16), and the wide path of one
-large deployment (K = 32, M = 1024), whose per-tile shares live in the array.
-A call whose scratch would exceed the array is refused before any launch.
+general kernel with its Gram in the array (K = 16, M = 300), the persistent
+kernel of dmimo_beamform_batched (K = 16, M <= 256, no scratch), and the
+wide path of one large deployment (K = 32, M = 1024), whose per-tile shares
+live in the array.  A call whose scratch would exceed the array is refused
+before any launch.
 """
 import numpy as np
 import pytest
@@ -42,9 +44,10 @@ def _same(a, b):
 
 # (first call, second smaller call): precoder, precision, B, K, M
 CASES = [
-    (("zf", "f32", 1024, 16, 256), ("zf", "f32", 100, 12, 200)),
+    (("zf", "f32", 1024, 16, 300), ("zf", "f32", 100, 12, 280)),
     (("zf", "f64", 64, 8, 64), ("zf", "f64", 7, 5, 37)),
     (("zf", "f16x3", 512, 16, 256), ("zf", "f16x3", 3, 9, 130)),
+    (("zf", "f16x3", 256, 16, 300), ("zf", "f16x3", 5, 16, 257)),
     (("zf", "f32", 1, 32, 1024), ("zf", "f32", 1, 20, 700)),
     (("mr", "f32", 2, 32, 1024), ("mr", "f32", 1, 16, 513)),
 ]
@@ -64,7 +67,7 @@ def test_noalloc_equals_workspace_call(D, first, second):
 
 
 def test_noalloc_refuses_scratch_beyond_the_array(D):
-    B, K, M = 8192, 16, 256                        # FP32 ZF: 16 MiB of Gram > 8 MiB
+    B, K, M = 8192, 16, 300                        # FP32 ZF: 16 MiB of Gram > 8 MiB
     need = D.workspace_size(D.CALL_BEAMFORM_ZF, B, K, M, 0, "f32")
     assert need > D.NOALLOC_SCRATCH_BYTES
     H = torch.zeros((B, K, M), dtype=torch.complex64, device="cuda")
@@ -76,3 +79,5 @@ def test_noalloc_refuses_scratch_beyond_the_array(D):
     H = _H(B, K, M, 5)
     _same(D.beamform_noalloc(H, "zf", None, 1e-12, 1.0, "f32"),
           D.beamform(H, "zf", None, 1e-12, 1.0, "f32"))
+    # K = 16, M = 256 runs on the persistent batched kernel: no scratch at any B
+    assert D.workspace_size(D.CALL_BEAMFORM_ZF, 8192, K, 256, 0, "f32") == 0
