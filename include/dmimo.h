@@ -115,8 +115,11 @@ dmimo_status dmimo_channel(const dmimo_channel_params* params, int32_t B, int32_
 /* K x K Gram G[b] = H[b] H[b]^H (the K x K form of the paper's H^T H^*,
  * Sec. IV).
  *   H    device [B][K][M], complex128 for DMIMO_F64, else complex64.
- *   prec DMIMO_F64: FP64 FMA.  DMIMO_F32: FP32 FMA.  MIX modes: hi/lo split
- *        FP16 or BF16 MFMA products with FP32 accumulation.
+ *   prec DMIMO_F64: FP64 FMA.  DMIMO_F32: FP32 FMA (FP32 matrix-core products
+ *        at 12 < K <= 16, 128 < M <= 256).  MIX modes: hi/lo split FP16 or
+ *        BF16 MFMA products with FP32 accumulation.  At K <= 16, M <= 256
+ *        (FP32 as above; MIX when K M > 512) the deployment's four 64-antenna
+ *        partial sums are added in FP64 and rounded once.
  *   G    device [B][K][K], complex128 for DMIMO_F64, else complex64; full
  *        Hermitian matrix written. */
 dmimo_status dmimo_gram(int32_t B, int32_t K, int32_t M, const void* H, int32_t prec,

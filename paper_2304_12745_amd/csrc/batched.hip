@@ -312,16 +312,21 @@ __device__ __forceinline__ void bb_gains(const BbDev& a, int64_t b, BbShared& S,
     }
 }
 
-// The Gram partial of wave `wave` (antennas 64 wave .. 64 wave + 63) into part[wave].
+// The Gram partial of wave `wave` over antennas 64 wave .. 64 wave + 63 of
+// h (LDS, [16][kBbP], zero past K and M): lane (g, j) gets Re and Im of
+// entry (4 g + r, j) in gr[r], gim[r].  MIX: h scaled by 2^hexp before the
+// split (FP16), so the partial is 2^(2 hexp) times the Gram's.
 template <int MODE>   // 0: FP32, 1: FP16 x3, 2: BF16 x3
-__device__ __forceinline__ void bb_gram(BbShared& S, int wave, int lane, int hexp) {
-    f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gim = {0.f, 0.f, 0.f, 0.f};
+__device__ __forceinline__ void gram_partial(const float2 (*h)[kBbP], int wave, int lane, int hexp,
+                                             f32x4& gr, f32x4& gim) {
+    gr = f32x4{0.f, 0.f, 0.f, 0.f};
+    gim = f32x4{0.f, 0.f, 0.f, 0.f};
     if constexpr (MODE == 0) {
         // lane (k, i): H[i][64 wave + 4 s + k]; the same value is A[i][k] and B[k][i]
         const int k = lane >> 4, i = lane & 15;
 #pragma unroll 4
         for (int s = 0; s < 16; ++s) {
-            const float2 v = S.h[i][64 * wave + 4 * s + k];
+            const float2 v = h[i][64 * wave + 4 * s + k];
             gr = mfma4(v.x, v.x, gr);
             gr = mfma4(v.y, v.y, gr);
             gim = mfma4(v.y, v.x, gim);
@@ -334,7 +339,7 @@ __device__ __forceinline__ void bb_gram(BbShared& S, int wave, int lane, int hex
         const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const float2* row = &S.h[i][64 * wave + 32 * s + 8 * g];
+            const float2* row = &h[i][64 * wave + 32 * s + 8 * g];
             u32x4 rh, rl, ih, il;
 #pragma unroll
             for (int e = 0; e < 8; e += 2) {
@@ -360,6 +365,13 @@ __device__ __forceinline__ void bb_gram(BbShared& S, int wave, int lane, int hex
             gim = mfma16<BF16>(nrh, il, gim);
         }
     }
+}
+
+// The Gram partial of wave `wave` into part[wave].
+template <int MODE>
+__device__ __forceinline__ void bb_gram(BbShared& S, int wave, int lane, int hexp) {
+    f32x4 gr, gim;
+    gram_partial<MODE>(S.h, wave, lane, hexp, gr, gim);
     // lane (g, j) holds D[4 g + r][j]
     const int g = lane >> 4, j = lane & 15;
 #pragma unroll
@@ -773,6 +785,92 @@ void beamform_batched_kernel(BbDev a) {
     }
 }
 
+// dmimo_gram at K <= 16, M <= 256 in FP32 or MIX: G = H H^H of many
+// deployments with the products of the fused kernel's step 2.  Persistent
+// 256-thread workgroups, four per CU, take deployments blockIdx.x,
+// blockIdx.x + grid, ...: thread m holds antenna m's column of the next
+// deployment in registers (16 coalesced loads, issued while the current one
+// is reduced), puts it in LDS, and every wave forms the partial of its 64
+// antennas on the matrix cores; the four partials are added in wave order in
+// FP64 and rounded once, the upper triangle mirrored (G exactly Hermitian).
+// H is read once, G written once: 8 K M + 8 K^2 bytes per deployment.
+struct GmShared {
+    union {
+        float2 h[kBbK][kBbP];                    // the channel, zero past K and M
+        float part[4][2][kBbK][kBbK + 1];        // the waves' partials (over h)
+    } u;
+    float hmax[4];
+};
+
+__device__ __forceinline__ void gm_load(const float2* H, int64_t b, int K, int M, int tid,
+                                        float2 (&h)[kBbK]) {
+    // clamped indices: every lane loads a valid address, unused values are never read
+    const float2* hb = H + b * K * M + (tid < M ? tid : M - 1);
+#pragma unroll
+    for (int i = 0; i < kBbK; ++i) h[i] = hb[(i < K ? i : K - 1) * M];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBbThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void gram_batched_kernel(const float2* __restrict__ H, float2* __restrict__ G, int64_t B, int K,
+                         int M) {
+    __shared__ GmShared S;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float2 h[kBbK];
+    gm_load(H, blockIdx.x, K, M, tid, h);
+    for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+        // the column to LDS (zero past K and M) and the wave's largest component
+        const bool live = tid < M;
+        float mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kBbK; ++i) {
+            const float2 v = live && i < K ? h[i] : make_float2(0.0f, 0.0f);
+            S.u.h[i][tid] = v;
+            if constexpr (MODE == 1) mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+        if constexpr (MODE == 1) {
+            mx = wave_max_f(mx);
+            if (lane == 0) S.hmax[wave] = mx;
+        }
+        __syncthreads();
+        if (b + gridDim.x < B) gm_load(H, b + gridDim.x, K, M, tid, h);
+        // FP16: the largest |h| of the deployment scaled into [2^13, 2^14)
+        int hexp = 0;
+        if constexpr (MODE == 1) {
+            const float m4 = fmaxf(fmaxf(S.hmax[0], S.hmax[1]), fmaxf(S.hmax[2], S.hmax[3]));
+            hexp = m4 > 0.0f ? 14 - (ilogbf(m4) + 1) : 0;
+        }
+        f32x4 gr = {0.f, 0.f, 0.f, 0.f}, gim = {0.f, 0.f, 0.f, 0.f};
+        if (64 * wave < M) gram_partial<MODE>(S.u.h, wave, lane, hexp, gr, gim);
+        __syncthreads();
+        {
+            const int g = lane >> 4, j = lane & 15;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                S.u.part[wave][0][4 * g + r][j] = gr[r];
+                S.u.part[wave][1][4 * g + r][j] = gim[r];
+            }
+        }
+        __syncthreads();
+        // thread (r, c), r <= c < K: entry (r, c) and its mirror
+        const int r = tid >> 4, c = tid & 15;
+        if (r <= c && c < K) {
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                re += (double)S.u.part[w][0][r][c];
+                im += (double)S.u.part[w][1][r][c];
+            }
+            const float fr = (float)ldexp(re, -2 * hexp);
+            const float fi = r == c ? 0.0f : (float)ldexp(im, -2 * hexp);
+            float2* Gb = G + b * K * K;
+            Gb[r * K + c] = make_float2(fr, fi);
+            if (r != c) Gb[c * K + r] = make_float2(fr, -fi);
+        }
+        __syncthreads();
+    }
+}
+
 // Compute units of the current device (cached per device).
 int device_cus() {
     static std::atomic<int> cache[64];
@@ -852,6 +950,27 @@ dmimo_status launch_beamform_batched(const BeamformArgs& ba, const WaveConst& w,
     d.nlos = reinterpret_cast<const float2*>(nlos);
     d.H = reinterpret_cast<float2*>(H);
     return bb_launch<false>(d, ba.prec, s);
+}
+
+// dmimo_gram's FP32 and MIX Gram at K <= 16, M <= 256 (G: [B][K][K] complex64).
+dmimo_status launch_gram_batched(int64_t B, int K, int64_t M, const void* H, int prec, void* G,
+                                 hipStream_t s) {
+    if (K < 1 || K > kBbK || M < 1 || M > kBbM)
+        return fail(DMIMO_E_SHAPE, "gram_batched: K <= 16 and M <= 256");
+    if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "gram_batched: B too large");
+    if (B == 0) return DMIMO_OK;
+    // persistent workgroups: four per CU fit the 33 KB of LDS
+    const int64_t wgs = 4 * (int64_t)device_cus();
+    const dim3 grid((unsigned)std::min<int64_t>(B, wgs)), block(kBbThreads);
+    const float2* h = static_cast<const float2*>(H);
+    float2* g = static_cast<float2*>(G);
+    if (prec == DMIMO_MIX_F16X3)
+        gram_batched_kernel<1><<<grid, block, 0, s>>>(h, g, B, K, (int)M);
+    else if (prec == DMIMO_MIX_BF16X3)
+        gram_batched_kernel<2><<<grid, block, 0, s>>>(h, g, B, K, (int)M);
+    else
+        gram_batched_kernel<0><<<grid, block, 0, s>>>(h, g, B, K, (int)M);
+    return check_launch("gram_batched_kernel");
 }
 
 // The kernel with the channel given (ba.H, [B][K][M] complex64): the MR and

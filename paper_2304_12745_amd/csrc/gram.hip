@@ -117,10 +117,26 @@ void launch_valu(dim3 grid, dim3 block, const T2* H, T2* G, int K, int64_t M, hi
 
 }  // namespace
 
+// batched.hip: FP32 and MIX at K <= 16, M <= 256 on the matrix cores,
+// persistent workgroups (G complex64).
+dmimo_status launch_gram_batched(int64_t B, int K, int64_t M, const void* H, int prec, void* G,
+                                 hipStream_t s);
+
+// Where that kernel measured faster than the one-wave MIX kernel and the VALU
+// FP32 kernel (16 384 deployments): MIX with K M > 512 (K = 16, M = 256:
+// 0.113 against 0.326 ms FP16x3), FP32 with K > 12 and M > 128 (K = 16,
+// M = 256: 0.119 against 0.184 ms; at K <= 8 the VALU kernel's K^2 work is
+// the smaller, and at M <= 64 one wave of four has antennas).
+bool gram_batched_shape(int K, int64_t M, int prec) {
+    if (prec == DMIMO_F64 || K > 16 || M > 256) return false;
+    return prec == DMIMO_F32 ? K > 12 && M > 128 : (int64_t)K * M > 512;
+}
+
 dmimo_status launch_gram(int64_t B, int K, int64_t M, const void* H, int prec, void* G,
                          hipStream_t s) {
     dim3 grid((unsigned)B), block(256);
     if (B > 0x7fffffff) return fail(DMIMO_E_SHAPE, "gram: B too large");
+    if (gram_batched_shape(K, M, prec)) return launch_gram_batched(B, K, M, H, prec, G, s);
     switch (prec) {
         case DMIMO_F64:
             launch_valu<double2, double>(grid, block, reinterpret_cast<const double2*>(H),

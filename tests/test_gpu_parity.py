@@ -292,6 +292,31 @@ def test_gram(D, prec, K, M):
     np.testing.assert_array_equal(G, np.conj(np.swapaxes(G, 1, 2)))
 
 
+# The persistent Gram kernel (four workgroups per CU) takes MIX at K M > 512
+# and FP32 at 12 < K <= 16, 128 < M <= 256 (the last two shapes stay on the
+# VALU kernel in FP32): more deployments than workgroups, antenna counts on
+# and past the boundaries of the waves' 64-antenna shares, deployments whose
+# scales differ by 10^5 (the FP16 scale is per deployment) and an all-zero one
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
+@pytest.mark.parametrize("B,K,M", [(1500, 16, 256), (1100, 13, 129), (3, 16, 192), (5, 14, 200),
+                                   (4, 4, 256), (3, 9, 65)])
+def test_gram_batched_kernel(D, prec, B, K, M):
+    say(f"gram (persistent kernel) prec={prec} B={B} K={K} M={M}")
+    rng = np.random.default_rng(B + 10 * K + 100 * M)
+    H = WL.complex_normal(rng, (B, K, M)) * 10.0 ** rng.uniform(-4, 1, (B, 1, 1))
+    H[1] = 0.0
+    H = c64(H)
+    G = host(D.gram(dev(H), prec=prec))
+    assert not np.any(G[1])
+    ok = np.arange(B) != 1
+    ref = O.gram(H[ok].astype(np.complex128))
+    d = np.sqrt(np.abs(np.einsum("bkk->bk", ref)))
+    e = np.max(np.abs(G[ok] - ref) / (d[:, :, None] * d[:, None, :]))
+    say(f"    max |dG|/sqrt(GkkGjj) = {e:.3e}")
+    assert e <= GRAM_TOL[prec]
+    np.testing.assert_array_equal(G, np.conj(np.swapaxes(G, 1, 2)))
+
+
 # ---------------------------------------------------------------------------
 # dmimo_beamform
 # ---------------------------------------------------------------------------
