@@ -956,7 +956,8 @@ def batched_phase(D, WL, torch, event_launches=30):
       HBM fraction of the algorithmic bytes (batched_bytes).
     * ``from_h``: dmimo_beamform (ZF at 1 W) of B = 2^17 CN(0,1) channels
       drawn on the device, FP32 and FP16x3, HBM fraction of H read + W and
-      the epilogues written.
+      the epilogues written; ``gram``: dmimo_gram of the same channels in
+      FP32, FP16x3 and BF16x3.
     * ``roofline``: B = 2^17 FP16x3 with W written, from HIP events around
       ``event_launches`` back-to-back launches; traffic from the committed
       counter summary when it matches the sources.
@@ -1047,7 +1048,7 @@ def batched_phase(D, WL, torch, event_launches=30):
                 byts = batched_bytes(Bs, K, M)
                 khash = _src_hash(BATCHED_SOURCES)
                 roof = {"bound": "hbm",
-                        "kernel": "beamform_batched_kernel<1> (FP16x3), 131072 Rician rooms, W written",
+                        "kernel": "beamform_batched_kernel<1, false> (FP16x3), 131072 Rician rooms, W written",
                         "achieved": round(byts / (launch_ms * 1e-3) / 1e9, 1),
                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                         "frac": round(byts / (launch_ms * 1e-3) / HBM_PEAK, 4),
@@ -1072,10 +1073,19 @@ def batched_phase(D, WL, torch, event_launches=30):
         from_h[prec] = {"ms": round(ms, 4), "hbm_frac": round(hbytes / (ms * 1e-3) / HBM_PEAK, 4),
                         "failed_deployments": int((r.info != 0).sum().item())}
         del r
+    # dmimo_gram of the same channels (H read, G written)
+    gram = {"workload": f"dmimo_gram of the same {bmax} channels; hbm_frac of H read + G written"}
+    gbytes = bmax * (K * M * 8 + K * K * 8)
+    for prec in ("f32", "f16x3", "bf16x3"):
+        G = D.gram(Hr, prec)
+        ms = timed(lambda: D.gram(Hr, prec, out=G), 10)
+        gram[prec] = {"ms": round(ms, 4), "hbm_frac": round(gbytes / (ms * 1e-3) / HBM_PEAK, 4)}
+        del G
     del Hr
     torch.cuda.empty_cache()
     return {"rician": ric,
             "from_h": from_h,
+            "gram": gram,
             "sweep_workload": "fused dmimo_beamform_batched, B rooms (the 1024 tiled) x K=16 x M=256, "
                               "Rician, ZF at 1 W, W written; hbm_frac of the algorithmic bytes "
                               "(NLoS + positions read, W + p_m + SINR + R_sum written)",
