@@ -233,3 +233,26 @@ def test_beamform_from_h_against_oracle(D, B, K, M, precoder, prec, p_total):
     else:
         W_or = O.mr_precoder(Hc, p_total)
     _check(D, prec, r, Hc, W_or, sigma2, np.ones(B, bool))
+
+
+def test_beamform_from_h_singular_deployment_is_isolated(D):
+    # two identical user rows in deployment 2 (K = 12, on this kernel): its
+    # Gram is singular, the pivot of step 8 (user 7 after user 3) fails in
+    # every precision, its outputs are zero and the other deployments match
+    # the oracle
+    say("beamform from H: duplicated user row in deployment 2 -> pivot 8, zeros")
+    rng = np.random.default_rng(91)
+    B, K, M = 5, 12, 100
+    H = WL.complex_normal(rng, (B, K, M), np.complex64)
+    H[2, 7] = H[2, 3]
+    Hc = H.astype(np.complex128)
+    W_or, sing = O.zf_precoder(Hc, None, 0.5, 1.0)
+    assert sing[2] and not sing[[0, 1, 3, 4]].any()
+    ok = ~sing
+    for prec in ("f32", "f16x3", "bf16x3"):
+        r = D.beamform(torch.from_numpy(H).cuda(), "zf", None, 0.5, 1.0, prec)
+        torch.cuda.synchronize()
+        assert r.info.cpu().numpy().tolist() == [0, 0, 8, 0, 0]
+        assert not torch.any(r.W[2]) and not torch.any(r.p_ant[2]) and not torch.any(r.sinr[2])
+        assert float(r.rsum[2]) == 0.0 and float(r.l21[2]) == 0.0
+        _check(D, prec, r, Hc, W_or, 0.5, ok)
