@@ -388,7 +388,9 @@ def test_beamform_room_zf_total_power(D):
 
 @pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 def test_beamform_batched_rician_zf(D, prec):
-    # ZF via the mixed Gram: SINR within 0.01 dB (FP32) / 0.1 dB (mixed), FP64 inverse
+    # K = 16, M = 256: dmimo_beamform runs the persistent batched kernel with H
+    # given (Gram on the matrix cores in the precision asked for, FP64
+    # inverse); SINR within 0.01 dB (FP32) / 0.1 dB (mixed)
     say(f"beamform ZF batched Rician (K=16, M=256), Gram {prec}")
     w = WL.batched_workload(B=16)
     Hc = np.stack([O.rician_channel(w.user_xyz[b], w.ap_xyz[b], w.freq_hz, w.kappa_lin,
@@ -397,9 +399,10 @@ def test_beamform_batched_rician_zf(D, prec):
                     1e-4 if prec != "bf16x3" else 1e-2)
 
 
-# the batched sweep of bench.py: B deployments of K = 16, M = 256 with H drawn
-# on the device (the same seeded draw), ZF at 1 W; sampled deployments against
-# the oracle.  The noise is sigma2 = 1 here (the launch is the same): at the
+# dmimo_beamform at the batched sweep's shape: B deployments of K = 16,
+# M = 256 with H drawn on the device (the seeded draw of the bench's from-H
+# leg), ZF at 1 W, on the persistent batched kernel; sampled deployments
+# against the oracle.  The noise is sigma2 = 1 here (the launch is the same): at the
 # sweep's -90 dBm with unit channels the SINR would measure the FP32 rounding
 # interference of W, not the precoder.
 @pytest.mark.parametrize("B,prec", [(1024, "f32"), (131072, "f32"), (131072, "f16x3")])
