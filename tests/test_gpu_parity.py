@@ -293,13 +293,14 @@ def test_gram(D, prec, K, M):
 
 
 # The persistent Gram kernel (four workgroups per CU) takes MIX at K M > 512
-# and FP32 at 12 < K <= 16, 128 < M <= 256 (the last two shapes stay on the
-# VALU kernel in FP32): more deployments than workgroups, antenna counts on
+# and FP32 at 12 < K <= 16, 128 < M <= 256 (the last four shapes stay on the
+# VALU kernel in FP32, two of them just past its boundary): more deployments
+# than workgroups, antenna counts on
 # and past the boundaries of the waves' 64-antenna shares, deployments whose
 # scales differ by 10^5 (the FP16 scale is per deployment) and an all-zero one
 @pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 @pytest.mark.parametrize("B,K,M", [(1500, 16, 256), (1100, 13, 129), (3, 16, 192), (5, 14, 200),
-                                   (4, 4, 256), (3, 9, 65)])
+                                   (4, 4, 256), (3, 9, 65), (6, 12, 200), (6, 16, 128)])
 def test_gram_batched_kernel(D, prec, B, K, M):
     say(f"gram (persistent kernel) prec={prec} B={B} K={K} M={M}")
     rng = np.random.default_rng(B + 10 * K + 100 * M)
