@@ -435,6 +435,34 @@ def test_beamform_batched_sweep_configuration_sampled(D, B, prec):
     assert ew <= 1e-4 and es <= MAP_TOL[prec]
 
 
+# dmimo_gram at the bench's full size: the B = 2^17 CN(0,1) channels of its
+# from-H leg (K = 16, M = 256, the same seeded device draw), each precision on
+# the persistent Gram kernel; sampled deployments against the oracle
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
+def test_gram_bench_configuration_sampled(D, prec):
+    import torch
+    say(f"gram, B = 131072 CN(0,1) channels K=16 M=256, prec={prec}")
+    K, M, B = 16, 256, 1 << 17
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    H = torch.complex(torch.randn(B, K, M, generator=gen, device="cuda"),
+                      torch.randn(B, K, M, generator=gen, device="cuda")) * (0.5 ** 0.5)
+    G = D.gram(H, prec)
+    rng = np.random.default_rng(17)
+    pick = np.concatenate([[0, B - 1], rng.choice(B, 14, replace=False)])
+    idx = torch.from_numpy(pick).to(H.device)
+    Hs = H[idx].cpu().numpy().astype(np.complex128)
+    Gs = G[idx].cpu().numpy()
+    del H, G
+    torch.cuda.empty_cache()
+    ref = O.gram(Hs)
+    d = np.sqrt(np.abs(np.einsum("bkk->bk", ref)))
+    e = np.max(np.abs(Gs - ref) / (d[:, :, None] * d[:, None, :]))
+    say(f"    max |dG|/sqrt(GkkGjj) = {e:.3e}")
+    assert e <= GRAM_TOL[prec]
+    np.testing.assert_array_equal(Gs, np.conj(np.swapaxes(Gs, 1, 2)))
+
+
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 def test_beamform_paper_zf_mixed(D, prec):
     # K <= 8 and M <= 256: G is formed in FP64 inside the one-pass kernel in
