@@ -39,7 +39,8 @@ The JSON line also carries:
   ``focus`` (the FP64 MR focusing map), ``batched`` (Rician Gram + ZF over
   many deployments), ``paper`` (the paper's ZF sum rate), ``serving``
   (Poisson queries, p50/p99, FP16x3 maps with the same stream in FP32 beside
-  them), ``pgd`` and ``pa`` (the paper's solver), and
+  them; ``serving_sweep``: p50/p99 at 500 to 4000 queries/s), ``pgd`` and
+  ``pa`` (the paper's solver), and
   ``channel`` (the channel materialised in HBM), each with its dB errors.
 
 Only the CPU-baseline and error legs import the oracle; they run before the
@@ -173,8 +174,9 @@ def parse_args():
                    help="precision of the served maps (the FP32 stream is also run, shorter, "
                         "as the comparison; --serve-compare-seconds 0 skips it)")
     p.add_argument("--serve-compare-seconds", type=float, default=10.0)
-    p.add_argument("--serve-sweep", action="store_true",
-                   help="also serve at 500, 1000, 2000 and 4000 queries/s (3 s each)")
+    p.add_argument("--no-serve-sweep", dest="serve_sweep", action="store_false",
+                   help="skip the load sweep (by default, when the stream is served, it is "
+                        "also served at 500, 1000, 2000 and 4000 queries/s, 3 s each after 1 s)")
     p.add_argument("--room-steps", type=int, default=500)
     p.add_argument("--room-warmup", type=int, default=2000)
     p.add_argument("--room-streams", type=int, default=2)
@@ -588,7 +590,7 @@ def main():
                 r = serving_phase(a2, D, WL, torch)
                 out["serving"]["f32"] = {k: r[k] for k in ("measured_s", "queries", "failed", "p50_ms",
                                                            "p99_ms", "max_ms", "sustained_Gh_per_s")}
-        if args.serve_sweep:
+        if args.serve_seconds > 0 and args.serve_sweep:
             sweep = []
             for rate in (500.0, 1000.0, 2000.0, 4000.0):
                 a2 = argparse.Namespace(**vars(args))
