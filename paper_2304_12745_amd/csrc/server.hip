@@ -195,7 +195,8 @@ struct ServerImpl {
     // the serving mix with two workgroups per CU, 6e7 gave p50 / p99 0.17 /
     // 1.68 ms, 3e7 0.15 / 2.09, 1.2e8 0.16 / 1.53, 2.4e8 0.15 / 1.33, 4.8e8
     // 0.15 / 1.40, 1e9 0.14 / 1.48; with three (grid below), 1.6e8 0.16 /
-    // 1.36, 2.4e8 0.15 / 1.35, 3.2e8 0.14 / 1.29
+    // 1.36, 2.4e8 0.15 / 1.35, 3.2e8 0.14 / 1.29, 4.8e8 0.14 / 1.38, 6.4e8
+    // 0.14 / 1.44
     double tick_terms = 3.2e8;
     int grid = 512;
     // schedule of DMIMO_PA queries (device FP64 [2][layers] in the arena)
